@@ -1,0 +1,255 @@
+/*
+ * bp.h -- C ABI of libbp, the MI355X (gfx950) feasibility check of the
+ * bin_packing constraint by lower bounds.
+ *
+ * Method: Tardivo, Michel, Pontelli, "Constraint Propagation on GPU: A Case
+ * Study for the Bin Packing Constraint" (arXiv 2402.14821).
+ *   - the constraint bin_packing(X, W, L) with k bins of capacity c: Sec. 3;
+ *   - the feasibility check "fail when a lower bound exceeds k": Alg. 1;
+ *   - the reduction of a partial packing to a plain instance with one virtual
+ *     item per loaded bin: Sec. 3 ("Feasibility check") and Fig. 3;
+ *   - the bounds L1, L2 and the dual feasible functions MT, RAD2, FS1, CCM1,
+ *     VB2, BJ1 with their parameter ranges: Sec. 3.1;
+ *   - the bound of a function: max over its parameters of
+ *     ceil(sum f(w) / f(c)), and the early return once lb > k: Alg. 2.
+ *
+ * Conventions shared by every entry point:
+ *   - Sizes and capacities are int32: 1 <= C <= 2^31 - 1, 0 <= w <= C,
+ *     0 <= residual <= C.  Reduced instances hold at most BP_MAX_ITEMS items.
+ *   - All arithmetic is exact integer arithmetic; results are deterministic.
+ *   - The caller owns every buffer it passes.  Synchronous calls do not keep
+ *     pointers after they return.  *_dev calls take device pointers and a
+ *     hipStream_t passed as void* (NULL is HIP's null stream); their inputs
+ *     must stay alive and unchanged until the work queued on that stream has
+ *     completed.
+ *   - The library owns contexts, queues and their device workspaces and frees
+ *     them on destroy.  No exception crosses this interface.
+ *   - A context may be used by one host thread at a time.
+ *   - On error a negative bp_status is returned and bp_last_error() gives a
+ *     message for the calling thread.  Output buffers are then unspecified.
+ */
+#ifndef BP_H_
+#define BP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bp_status;
+#define BP_OK 0
+#define BP_ERR_ARG (-1)    /* NULL pointer, negative count, C < 1, bad flags */
+#define BP_ERR_RANGE (-2)  /* size or residual outside [0, C], bin index out of range, bin overfull, sweep outside the paper's range */
+#define BP_ERR_NOMEM (-3)  /* host or device allocation failed */
+#define BP_ERR_DEVICE (-4) /* a HIP call failed */
+#define BP_ERR_AGAIN (-5)  /* queue full or HBM budget exhausted (non-blocking submit) */
+#define BP_ERR_STATE (-6)  /* destroyed handle, unknown ticket, queue shut down */
+#define BP_ERR_LIMIT (-7)  /* input larger than the library's limits */
+
+#define BP_MAX_ITEMS (1 << 22) /* largest reduced instance (items, virtual items included) */
+#define BP_MAX_BATCH (1 << 20) /* most instances in one batched call */
+
+/* The bound collection, in the order used for results and tie-breaks: L1 and
+ * L2 (Sec. 3.1), then the six functions in the order Alg. 2 visits them. */
+enum { BP_L1 = 0, BP_L2, BP_MT, BP_RAD2, BP_FS1, BP_CCM1, BP_VB2, BP_BJ1, BP_NB };
+
+/* Parameter ranges of the bounds.  lo[b] > hi[b] is an empty range (bound 0).
+ * lo/hi of BP_L1 are ignored.  A caller-given range must lie inside the
+ * paper's range of that bound (Sec. 3.1), else BP_ERR_RANGE:
+ *   L2, MT [0, C/2]; RAD2 [C/4 + 1, C/3]; FS1 [1, 100]; CCM1 [1, C/2];
+ *   VB2 [2, C]; BJ1 [1, C]   (all divisions floor). */
+typedef struct bp_sweep {
+  int64_t lo[BP_NB];
+  int64_t hi[BP_NB];
+  uint32_t flags;
+  uint32_t reserved;
+} bp_sweep;
+
+/* flags of bp_sweep: cut the top of the VB2 range to
+ * floor((2^32 - 1) / (r * max w)) as the paper does to stay inside 32-bit
+ * sums (Sec. 4, "Implementation details").  Off by default: the library
+ * accumulates in 64 bits and needs no cut. */
+#define BP_SWEEP_PAPER_VB2_CLAMP 1u
+
+/* Result of one check.  value[b] is the bound, argmax_lambda[b] the smallest
+ * parameter attaining it (-1 for L1 and for an empty range).  lb is the
+ * maximum over the collection, lb_arg the first bound attaining it, verdict
+ * 1 = PASS (lb <= k, not refuted) and 0 = FAIL (lb > k, Alg. 1).  A PASS does
+ * not prove that a packing exists.  r is the reduced item count, evals the
+ * number of (item, parameter) evaluations of the six functions,
+ * r * sum of range sizes.  status is BP_OK or the error found on the device
+ * for this instance (device-side inputs are validated there). */
+typedef struct bp_bounds {
+  int64_t value[BP_NB];
+  int64_t argmax_lambda[BP_NB];
+  int64_t lb;
+  int32_t lb_arg;
+  int32_t verdict;
+  int64_t k;
+  int64_t r;
+  int64_t evals;
+  int32_t status;
+  int32_t early_exit; /* 1 when an early-exit call stopped once lb > k (values then partial) */
+} bp_bounds;
+
+/* Library version string (static storage). */
+const char *bp_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *bp_last_error(void);
+
+/* Fill *out with the paper's parameter ranges for capacity C (Sec. 3.1).
+ * r and max_w are only read with BP_SWEEP_PAPER_VB2_CLAMP.  Host only. */
+bp_status bp_default_sweep(int32_t C, int64_t r, int32_t max_w, uint32_t flags, bp_sweep *out);
+
+/* A context binds one GPU, one HIP stream of default priority, device
+ * workspaces that grow on demand, pinned staging buffers and the captured
+ * HIP graphs of the pipeline.  device is a HIP ordinal. */
+typedef struct bp_ctx bp_ctx;
+bp_status bp_ctx_create(int device, bp_ctx **out);
+bp_status bp_ctx_destroy(bp_ctx *ctx);
+
+/* Stage timing for diagnostics.  With enable = 1 the context launches the
+ * pipeline kernels one by one instead of replaying its graph and records HIP
+ * events around each on the call's stream; bp_ctx_stage_times waits for the
+ * last call and returns its durations in milliseconds:
+ * ms[0] reduction + sort + prefix (prep), ms[1] sweeps, ms[2] finalize. */
+bp_status bp_ctx_set_timing(bp_ctx *ctx, int32_t enable);
+bp_status bp_ctx_stage_times(bp_ctx *ctx, double ms[3]);
+
+/* Reduction of a partial packing (Sec. 3, Fig. 3), run on the device.
+ * residual[m] are the remaining capacities of the k = m bins, unpacked[n] the
+ * sizes of the items not yet packed.  out_items (capacity n + m) receives the
+ * unpacked sizes in order, then the load C - residual[j] of every bin with
+ * residual[j] < C in bin order; *out_r their count.  Host pointers. */
+bp_status bp_residual_reduce(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual,
+                             const int32_t *unpacked, int64_t n, int32_t *out_items, int64_t *out_r);
+
+/* The same reduction from the constraint's variables: size[n] and bin_of[n]
+ * (bin index in [0, m), or -1 for an unpacked item).  out_residual[m]
+ * (optional) receives C minus each bin's load.  Loads above C: BP_ERR_RANGE. */
+bp_status bp_assignment_reduce(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *size,
+                               const int32_t *bin_of, int64_t n, int32_t *out_items, int64_t *out_r,
+                               int32_t *out_residual);
+
+/* All bounds of one reduced instance items[r] (host pointer) with k bins.
+ * sweep = NULL uses the paper's ranges.  Never exits early. */
+bp_status bp_lower_bounds(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *items, int64_t r,
+                          const bp_sweep *sweep, bp_bounds *out);
+
+/* As bp_lower_bounds with device pointers: d_items[r] on the device, the
+ * result written to d_out (device) in stream order.  Validation of the sizes
+ * happens on the device and is reported in d_out->status. */
+bp_status bp_lower_bounds_dev(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *d_items, int64_t r,
+                              const bp_sweep *sweep, bp_bounds *d_out, void *stream);
+
+/* The feasibility check of Alg. 1 on a partial packing: reduce (residual[m],
+ * unpacked[n]) on the device, compute the bounds and FAIL iff lb > m.
+ * flags: BP_NO_EARLY_EXIT evaluates every bound; without it the device stops
+ * scheduling work once lb > m is known (the verdict is the same; lb is then
+ * some value > m).  verdict and lb may be NULL; bounds (optional) receives
+ * the full record. */
+#define BP_NO_EARLY_EXIT 1u
+bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *unpacked,
+                      int64_t n, uint32_t flags, int32_t *verdict, int64_t *lb, bp_bounds *bounds);
+
+/* As bp_feasible with device pointers d_residual[m] and d_unpacked[n]; the
+ * full record goes to d_out (device) in stream order.  Sizes are validated
+ * on the device (d_out->status). */
+bp_status bp_feasible_dev(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *d_residual, const int32_t *d_unpacked,
+                          int64_t n, uint32_t flags, bp_bounds *d_out, void *stream);
+
+/* Batches in CSR form: instance i has items[off[i] .. off[i+1]), capacity
+ * C[i] and k[i] bins.  off has count + 1 entries, off[0] = 0. */
+typedef struct bp_batch {
+  int32_t count;
+  int32_t reserved;
+  const int64_t *off;
+  const int32_t *items;
+  const int32_t *C;
+  const int32_t *k;
+} bp_batch;
+
+/* All instances of a batch in one persistent launch; host pointers.
+ * per_inst (optional) gives one bp_sweep per instance.  out[count]. */
+bp_status bp_lower_bounds_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, bp_bounds *out);
+
+/* Batched with the items on the device: batch->off, C, k are host arrays
+ * (they size the launch), d_items the device item array, d_out[count] a
+ * device array.  Queued on stream; nothing is copied back. */
+bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const int32_t *d_items,
+                                    const bp_sweep *per_inst, bp_bounds *d_out, void *stream);
+
+/* Batched feasibility check of reduced instances with k[i] bins each;
+ * flags as in bp_feasible.  verdict[count], lb[count]. */
+bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb);
+
+/* ---- served checks (continuous batching) -------------------------------- */
+
+/* One request: a partial packing in residual form, as bp_feasible takes it. */
+typedef struct bp_request {
+  int32_t C;
+  int32_t m;
+  int64_t n;
+  const int32_t *residual; /* m entries */
+  const int32_t *unpacked; /* n entries */
+  uint64_t tag;            /* caller's value, returned in the result */
+  uint32_t flags;          /* BP_NO_EARLY_EXIT */
+  uint32_t reserved;
+} bp_request;
+
+typedef struct bp_result {
+  uint64_t ticket;
+  uint64_t tag;
+  bp_status status;
+  int32_t verdict;
+  int64_t lb;
+  double submit_us; /* host clock at submit, microseconds */
+  double start_us;  /* host clock when the request's batch was launched */
+  double done_us;   /* host clock when the result became visible */
+  bp_bounds bounds;
+} bp_result;
+
+typedef struct bp_queue_stats {
+  uint64_t submitted, completed, rejected, batches, in_flight;
+  uint64_t bytes_in_use, bytes_peak, budget;
+  double busy_us;
+} bp_queue_stats;
+
+/* A queue owns a serving thread that admits requests into free slots while
+ * earlier batches run, launches them as batches on its own streams and
+ * publishes results.  hbm_budget_bytes bounds the device memory held by
+ * admitted requests; max_slots bounds the requests admitted at once. */
+typedef struct bp_queue bp_queue;
+bp_status bp_queue_create(bp_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots, bp_queue **out);
+
+/* Copy the request (the caller may free its arrays on return) and return a
+ * ticket.  blocking = 0: BP_ERR_AGAIN when no slot or budget is free;
+ * blocking = 1: wait for one.  A request larger than the whole budget is
+ * BP_ERR_LIMIT. */
+bp_status bp_queue_submit(bp_queue *q, const bp_request *req, int32_t blocking, uint64_t *ticket);
+
+/* Up to max finished results; waits up to timeout_us (0 = do not wait) for
+ * the first one.  *got receives the count. */
+bp_status bp_queue_poll(bp_queue *q, bp_result *out, int32_t max, int32_t *got, int32_t timeout_us);
+
+bp_status bp_queue_stats_get(bp_queue *q, bp_queue_stats *out);
+
+/* Stop admitting, finish the batches on the device, complete still-queued
+ * requests with BP_ERR_STATE, join the thread and free everything. */
+bp_status bp_queue_destroy(bp_queue *q);
+
+/* ---- self test of the host-side division constants ----------------------- */
+
+/* Checks, on the host, the multiply-shift constants the kernels use against
+ * plain integer division: every divisor d in [d_lo, d_hi] with numerators
+ * n in [0, n_hi] (and the extreme numerators).  Returns the number of
+ * mismatches found (0 = all exact) or a negative status. */
+int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32_t mode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BP_H_ */

@@ -1,0 +1,819 @@
+// bp_api.cpp -- host side of libbp: validation, planning, workspaces, the
+// captured pipeline graph and the C ABI declared in include/bp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bp_ctx.h"
+#include "bp_divide.h"
+#include "bp_internal.h"
+
+using namespace bpi;
+
+namespace bpi {
+
+static thread_local std::string g_err;
+
+bp_status fail(bp_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+bp_status hip_fail(hipError_t e, const char *what) {
+  return fail(BP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                     \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+  } while (0)
+
+// Paper's parameter ranges (Sec. 3.1) for integer parameters.
+void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]) {
+  const int64_t c = C;
+  lo[kL1] = 0; hi[kL1] = -1;
+  lo[kL2] = 0; hi[kL2] = c / 2;
+  lo[kMT] = 0; hi[kMT] = c / 2;
+  lo[kRAD2] = c / 4 + 1; hi[kRAD2] = c / 3;
+  lo[kFS1] = 1; hi[kFS1] = 100;
+  lo[kCCM1] = 1; hi[kCCM1] = c / 2;
+  lo[kVB2] = 2; hi[kVB2] = c;
+  lo[kBJ1] = 1; hi[kBJ1] = c;
+}
+
+bp_status DevBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return BP_OK;
+  size_t want = std::max(bytes, cap + cap / 2);
+  want = (want + 4095) & ~size_t(4095);
+  if (p) {
+    hipError_t e = hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+  }
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return fail(BP_ERR_NOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+  }
+  cap = want;
+  return BP_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+bp_status HostBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return BP_OK;
+  size_t want = std::max(bytes, cap + cap / 2);
+  want = (want + 4095) & ~size_t(4095);
+  if (p) {
+    (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return fail(BP_ERR_NOMEM, "hipHostMalloc(%zu): %s", want, hipGetErrorString(e));
+  }
+  cap = want;
+  return BP_OK;
+}
+
+void HostBuf::release() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+// Relative cost of one (item, parameter) evaluation per bound, in issue
+// slots of a full-rate VALU instruction (measured rates on gfx950: 32-bit
+// add/sub/logic/shift-right issue at twice the rate of multiplies, compares,
+// selects and fp64 operations).
+static double unit_cost(int b) {
+  switch (b) {
+    case kMT: return 2.5;
+    case kRAD2: return 3.0;
+    case kFS1: return 9.0;
+    case kCCM1: return 2.0;
+    case kVB2: return 2.5;
+    case kBJ1: return 4.0;
+    default: return 1.0;
+  }
+}
+
+static int ilog2ceil(int64_t x) {
+  int l = 0;
+  while ((1ll << l) < x) ++l;
+  return l;
+}
+
+// Checks a caller range against the paper's range of that bound.
+static bp_status check_sweep(int32_t C, const bp_sweep *sw, int64_t lo[kNB], int64_t hi[kNB]) {
+  int64_t dlo[kNB], dhi[kNB];
+  default_ranges(C, dlo, dhi);
+  for (int b = 0; b < kNB; ++b) {
+    if (!sw) {
+      lo[b] = dlo[b];
+      hi[b] = dhi[b];
+      continue;
+    }
+    lo[b] = sw->lo[b];
+    hi[b] = sw->hi[b];
+    if (b == kL1) continue;
+    if (lo[b] > hi[b]) continue;  // empty by request
+    if (lo[b] < dlo[b] || hi[b] > dhi[b])
+      return fail(BP_ERR_RANGE, "sweep range of bound %d [%lld, %lld] outside [%lld, %lld] for C=%d", b,
+                  (long long)lo[b], (long long)hi[b], (long long)dlo[b], (long long)dhi[b], C);
+  }
+  if (sw && (sw->flags & ~BP_SWEEP_PAPER_VB2_CLAMP)) return fail(BP_ERR_ARG, "unknown bp_sweep flags 0x%x", sw->flags);
+  return BP_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+bp_status Ctx::init(int dev) {
+  device = dev;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (dev < 0 || dev >= ndev) return fail(BP_ERR_ARG, "device %d not in [0, %d)", dev, ndev);
+  HIP_TRY(hipSetDevice(dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  num_cu = prop.multiProcessorCount;
+  HIP_TRY(set_kernel_attrs());
+  HIP_TRY(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+  for (hipEvent_t &e : tev) HIP_TRY(hipEventCreate(&e));
+  bp_status st = desc_buf.reserve(sizeof(LaunchDesc));
+  if (st) return st;
+  st = counter_buf.reserve(256);
+  if (st) return st;
+  st = desc_host.reserve(sizeof(LaunchDesc));
+  if (st) return st;
+  grid_sweep = num_cu * sweep_waves_per_cu;
+  grid_prep_small = num_cu * 2;
+  grid_prep_large = std::max(1, num_cu / 4);
+  grid_fin = 64;
+  const char *ng = getenv("BP_NO_GRAPH");
+  use_graph = !(ng && ng[0] == '1');
+  return BP_OK;
+}
+
+void Ctx::destroy() {
+  if (device >= 0) (void)hipSetDevice(device);
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  graph_exec = nullptr;
+  graph = nullptr;
+  for (DevBuf *b : {&desc_buf, &counter_buf, &in_buf, &plan_buf, &entry_buf, &state_buf, &sorted_buf, &pre_buf,
+                    &rec_buf, &keys_buf, &ref_buf, &out_buf, &red_buf})
+    b->release();
+  for (HostBuf *b : {&desc_host, &in_host, &plan_host, &entry_host, &out_host, &red_host}) b->release();
+  if (staged) (void)hipEventDestroy(staged);
+  if (done) (void)hipEventDestroy(done);
+  for (hipEvent_t &e : tev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  if (stream) (void)hipStreamDestroy(stream);
+  staged = done = nullptr;
+  stream = nullptr;
+}
+
+// Captures the four-kernel pipeline once; every call replays it.
+bp_status Ctx::ensure_graph() {
+  if (!use_graph || graph_exec) return BP_OK;
+  HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = launch_pipeline((const LaunchDesc *)desc_buf.p, grid_prep_small, grid_prep_large, grid_sweep,
+                                  grid_fin, stream);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(stream, &g);
+  if (le != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(le, "capture launch_pipeline");
+  }
+  if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(ie, "hipGraphInstantiate");
+  }
+  graph = g;
+  graph_exec = ex;
+  return BP_OK;
+}
+
+// Build InstPlan + Entry tables into the pinned staging buffers.
+bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
+  const int64_t count = (int64_t)pin.size();
+  bp_status st = plan_host.reserve(sizeof(InstPlan) * std::max<int64_t>(count, 1));
+  if (st) return st;
+  InstPlan *pl = (InstPlan *)plan_host.p;
+  int64_t ws = 0, pre = 0;
+  std::vector<Entry> ent;
+  std::vector<double> tile_cost_v;
+  ent.reserve((size_t)count * 7);
+  double total = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const PlanIn &q = pin[i];
+    InstPlan &p = pl[i];
+    memset(&p, 0, sizeof p);
+    p.in_off = q.in_off;
+    p.res_off = q.res_off;
+    p.n_in = q.n_in;
+    p.k = q.k;
+    p.m_res = q.m_res;
+    p.C = q.C;
+    p.form = q.form;
+    const int64_t rcap = q.n_in + q.m_res;
+    if (rcap > kLargeCap)
+      return fail(BP_ERR_LIMIT, "instance %lld: %lld reduced items exceed the %d-item limit of this build",
+                  (long long)i, (long long)rcap, kLargeCap);
+    p.r_cap = (int32_t)rcap;
+    p.large = rcap > kSmallCap ? 1 : 0;
+    p.flags = (q.clamp ? kPlanClampVB2 : 0u) | (q.early_exit ? kPlanEarlyExit : 0u);
+    p.ws_off = ws;
+    p.pre_off = pre;
+    ws += std::max<int64_t>(rcap, 1);
+    pre += rcap + 1;
+    for (int b = 0; b < kNB; ++b) {
+      p.lo[b] = q.lo[b];
+      p.hi[b] = q.hi[b];
+    }
+    for (int b = kL2; b < kNB; ++b) {
+      if (q.lo[b] > q.hi[b]) continue;
+      Entry e;
+      memset(&e, 0, sizeof e);
+      e.inst = (int32_t)i;
+      e.bound = b;
+      double tc;
+      if (b == kL2) {
+        const int64_t cand = 2 * rcap + 1;
+        e.lam0 = 0;
+        e.ntiles = (cand + kTile - 1) / kTile;
+        tc = (double)kTile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0);
+      } else {
+        const int64_t nl = q.hi[b] - q.lo[b] + 1;
+        e.lam0 = q.lo[b];
+        e.ntiles = (nl + kTile - 1) / kTile;
+        tc = (double)kTile * ((double)rcap * unit_cost(b) + 60.0);
+      }
+      total += tc * (double)e.ntiles;
+      ent.push_back(e);
+      tile_cost_v.push_back(tc);
+    }
+  }
+  ws_items = ws;
+  pre_items = pre;
+  // Task size: at least one tile; about 8 tasks per resident wave overall.
+  const double target = total / (8.0 * (double)grid_sweep);
+  std::vector<double> task_cost(ent.size());
+  for (size_t j = 0; j < ent.size(); ++j) {
+    double tpt = std::floor(target / tile_cost_v[j]);
+    if (tpt < 1) tpt = 1;
+    if (tpt > (double)ent[j].ntiles) tpt = (double)ent[j].ntiles;
+    if (tpt > 1e9) tpt = 1e9;
+    ent[j].tpt = (int32_t)tpt;
+    task_cost[j] = tile_cost_v[j] * tpt;
+  }
+  std::vector<size_t> order(ent.size());
+  for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_cost[a] > task_cost[b]; });
+  st = entry_host.reserve(sizeof(Entry) * std::max<size_t>(ent.size(), 1));
+  if (st) return st;
+  Entry *eo = (Entry *)entry_host.p;
+  int64_t tb = 0;
+  for (size_t j = 0; j < order.size(); ++j) {
+    Entry e = ent[order[j]];
+    e.task_begin = tb;
+    tb += (e.ntiles + e.tpt - 1) / e.tpt;
+    eo[j] = e;
+  }
+  nentries = (int64_t)ent.size();
+  if (nentries == 0) {
+    memset(eo, 0, sizeof(Entry));
+  }
+  *ntasks_out = tb;
+  return BP_OK;
+}
+
+// Runs one planned launch.  in_dev: device input arena (already filled);
+// out_dev: device result array; s: stream to queue on.
+bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *in_dev, bp_bounds *out_dev, hipStream_t s) {
+  bp_status st;
+  const size_t nplan = sizeof(InstPlan) * (size_t)count;
+  const size_t nent = sizeof(Entry) * (size_t)std::max<int64_t>(nentries, 1);
+  if ((st = plan_buf.reserve(nplan))) return st;
+  if ((st = entry_buf.reserve(nent))) return st;
+  if ((st = state_buf.reserve(sizeof(InstState) * count))) return st;
+  if ((st = sorted_buf.reserve(sizeof(int32_t) * ws_items))) return st;
+  if ((st = rec_buf.reserve(sizeof(ItemRec) * ws_items))) return st;
+  if ((st = pre_buf.reserve(sizeof(int64_t) * pre_items))) return st;
+  if ((st = keys_buf.reserve(sizeof(unsigned long long) * kNB * count))) return st;
+  if ((st = ref_buf.reserve(sizeof(int32_t) * count))) return st;
+  LaunchDesc *d = (LaunchDesc *)desc_host.p;
+  d->in = in_dev;
+  d->plan = (const InstPlan *)plan_buf.p;
+  d->entries = (const Entry *)entry_buf.p;
+  d->state = (InstState *)state_buf.p;
+  d->sorted = (int32_t *)sorted_buf.p;
+  d->pre = (int64_t *)pre_buf.p;
+  d->rec = (ItemRec *)rec_buf.p;
+  d->keys = (unsigned long long *)keys_buf.p;
+  d->refuted = (int32_t *)ref_buf.p;
+  d->counter = (unsigned long long *)counter_buf.p;
+  d->out = out_dev;
+  d->count = count;
+  d->nentries = nentries;
+  d->ntasks = ntasks;
+  HIP_TRY(hipMemcpyAsync(plan_buf.p, plan_host.p, nplan, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(entry_buf.p, entry_host.p, nent, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(desc_buf.p, desc_host.p, sizeof(LaunchDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(staged, s));
+  if (timing) {
+    HIP_TRY(launch_pipeline_timed((const LaunchDesc *)desc_buf.p, grid_prep_small, grid_prep_large, grid_sweep,
+                                  grid_fin, s, tev));
+  } else if (use_graph) {
+    if ((st = ensure_graph())) return st;
+    HIP_TRY(hipGraphLaunch(graph_exec, s));
+  } else {
+    HIP_TRY(launch_pipeline((const LaunchDesc *)desc_buf.p, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
+                            s));
+  }
+  return BP_OK;
+}
+
+// The pinned staging buffers may still feed copies of the previous call.
+bp_status Ctx::wait_staging() {
+  HIP_TRY(hipEventSynchronize(staged));
+  return BP_OK;
+}
+
+}  // namespace bpi
+
+// ===========================================================================
+// C ABI
+
+const char *bp_version(void) { return "libbp 0.1 (gfx950)"; }
+
+const char *bp_last_error(void) { return bpi::g_err.c_str(); }
+
+bp_status bp_default_sweep(int32_t C, int64_t r, int32_t max_w, uint32_t flags, bp_sweep *out) {
+  if (!out) return fail(BP_ERR_ARG, "out is NULL");
+  if (C < 1) return fail(BP_ERR_ARG, "C = %d < 1", C);
+  if (flags & ~BP_SWEEP_PAPER_VB2_CLAMP) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  if (r < 0 || max_w < 0) return fail(BP_ERR_ARG, "negative r or max_w");
+  memset(out, 0, sizeof *out);
+  default_ranges(C, out->lo, out->hi);
+  out->flags = flags;
+  if (flags & BP_SWEEP_PAPER_VB2_CLAMP) {
+    const int64_t denom = r * (int64_t)max_w;
+    const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)C;
+    if (cap < out->hi[kVB2]) out->hi[kVB2] = cap;
+  }
+  return BP_OK;
+}
+
+bp_status bp_ctx_create(int device, bp_ctx **out) {
+  if (!out) return fail(BP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  Ctx *c = new (std::nothrow) Ctx();
+  if (!c) return fail(BP_ERR_NOMEM, "context allocation");
+  bp_status st = c->init(device);
+  if (st) {
+    c->destroy();
+    delete c;
+    return st;
+  }
+  c->magic = kCtxMagic;
+  *out = (bp_ctx *)c;
+  return BP_OK;
+}
+
+bp_status bp_ctx_destroy(bp_ctx *ctx) {
+  Ctx *c = (Ctx *)ctx;
+  if (!c || c->magic != kCtxMagic) return fail(BP_ERR_STATE, "bad context");
+  c->magic = 0;
+  c->destroy();
+  delete c;
+  return BP_OK;
+}
+
+static bp_status get_ctx(bp_ctx *ctx, Ctx **c) {
+  Ctx *x = (Ctx *)ctx;
+  if (!x || x->magic != kCtxMagic) return fail(BP_ERR_STATE, "bad context");
+  hipError_t e = hipSetDevice(x->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  *c = x;
+  return BP_OK;
+}
+
+bp_status bp_ctx_set_timing(bp_ctx *ctx, int32_t enable) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  c->timing = enable != 0;
+  return BP_OK;
+}
+
+bp_status bp_ctx_stage_times(bp_ctx *ctx, double ms[3]) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if (!ms) return fail(BP_ERR_ARG, "ms is NULL");
+  if (!c->timing) return fail(BP_ERR_STATE, "timing is off");
+  HIP_TRY(hipEventSynchronize(c->tev[3]));
+  for (int i = 0; i < 3; ++i) {
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, c->tev[i], c->tev[i + 1]));
+    ms[i] = t;
+  }
+  return BP_OK;
+}
+
+// ---- reduction ----------------------------------------------------------
+
+static bp_status reduce_common(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *size,
+                               const int32_t *bin_of, int64_t n, int32_t *out_items, int64_t *out_r,
+                               int32_t *out_residual) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if (C < 1 || m < 0 || n < 0 || !out_items || !out_r) return fail(BP_ERR_ARG, "bad reduction arguments");
+  if ((n > 0 && !size) || (m > 0 && !bin_of && !residual) || (bin_of && n > 0 && !bin_of))
+    return fail(BP_ERR_ARG, "NULL input array");
+  if (n + (int64_t)m > BP_MAX_ITEMS) return fail(BP_ERR_LIMIT, "n + m = %lld > %d", (long long)(n + m), BP_MAX_ITEMS);
+  // host staging: [size n][bin_of n][residual m]
+  const size_t in_bytes = sizeof(int32_t) * (size_t)(2 * n + m) + 64;
+  if ((st = c->wait_staging())) return st;
+  if ((st = c->red_host.reserve(in_bytes + sizeof(int32_t) * (size_t)(n + 2 * (int64_t)m) + 64))) return st;
+  int32_t *h = (int32_t *)c->red_host.p;
+  if (n) memcpy(h, size, sizeof(int32_t) * n);
+  if (bin_of && n) memcpy(h + n, bin_of, sizeof(int32_t) * n);
+  if (!bin_of && m) memcpy(h + 2 * n, residual, sizeof(int32_t) * m);
+  // device: inputs, loads (u64 m), out (n + m), out_residual (m), out_r, bad
+  const size_t dev_bytes = in_bytes + sizeof(uint64_t) * (size_t)(m + 1) + sizeof(int32_t) * (size_t)(n + 2 * (int64_t)m) + 256;
+  if ((st = c->red_buf.reserve(dev_bytes))) return st;
+  char *base = (char *)c->red_buf.p;
+  int32_t *d_size = (int32_t *)base;
+  int32_t *d_bin = d_size + n;
+  int32_t *d_res = d_size + 2 * n;
+  size_t off = (sizeof(int32_t) * (size_t)(2 * n + m) + 63) & ~size_t(63);
+  unsigned long long *d_loads = (unsigned long long *)(base + off);
+  off += (sizeof(uint64_t) * (size_t)(m + 1) + 63) & ~size_t(63);
+  int64_t *d_r = (int64_t *)(base + off);
+  int32_t *d_bad = (int32_t *)(base + off + 8);
+  off += 64;
+  int32_t *d_out = (int32_t *)(base + off);
+  int32_t *d_outres = d_out + n + m;
+  hipStream_t s = c->stream;
+  HIP_TRY(hipMemcpyAsync(d_size, h, sizeof(int32_t) * (size_t)(2 * n + m), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(d_loads, 0, sizeof(uint64_t) * (size_t)(m + 1), s));
+  HIP_TRY(hipMemsetAsync(d_r, 0, 64, s));
+  HIP_TRY(launch_reduce(C, m, bin_of ? nullptr : d_res, d_size, bin_of ? d_bin : nullptr, n, d_loads, d_out, d_r,
+                        d_outres, d_bad, s));
+  int32_t *ho = h + 2 * n + m;
+  HIP_TRY(hipMemcpyAsync(ho, d_out, sizeof(int32_t) * (size_t)(n + 2 * (int64_t)m), hipMemcpyDeviceToHost, s));
+  int64_t *hr = (int64_t *)(((uintptr_t)(ho + n + 2 * (int64_t)m) + 15) & ~uintptr_t(15));
+  HIP_TRY(hipMemcpyAsync(hr, d_r, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int32_t bad = ((int32_t *)hr)[2];
+  if (bad) return fail(BP_ERR_RANGE, "size, bin index or residual out of range, or a bin over capacity");
+  const int64_t r = hr[0];
+  memcpy(out_items, ho, sizeof(int32_t) * (size_t)r);
+  *out_r = r;
+  if (out_residual && m) memcpy(out_residual, ho + n + m, sizeof(int32_t) * (size_t)m);
+  return BP_OK;
+}
+
+bp_status bp_residual_reduce(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *unpacked,
+                             int64_t n, int32_t *out_items, int64_t *out_r) {
+  if (m > 0 && !residual) return fail(BP_ERR_ARG, "residual is NULL");
+  return reduce_common(ctx, C, m, residual, unpacked, nullptr, n, out_items, out_r, nullptr);
+}
+
+bp_status bp_assignment_reduce(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *size, const int32_t *bin_of,
+                               int64_t n, int32_t *out_items, int64_t *out_r, int32_t *out_residual) {
+  if (n > 0 && !bin_of) return fail(BP_ERR_ARG, "bin_of is NULL");
+  static const int32_t dummy = 0;
+  return reduce_common(ctx, C, m, nullptr, size, bin_of ? bin_of : &dummy, n, out_items, out_r, out_residual);
+}
+
+// ---- checks --------------------------------------------------------------
+
+namespace bpi {
+
+// Host-input batch in either form: stage into pinned memory, plan, launch and
+// queue the copy of the results back into c->out_host; c->done marks the end.
+bp_status launch_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<const int32_t *> &src_a,
+                            const std::vector<const int32_t *> &src_b) {
+  bp_status st;
+  const int64_t count = (int64_t)pin.size();
+  // input arena layout: per instance [a: n_in][b: m_res]
+  int64_t tot = 0;
+  for (auto &q : pin) {
+    q.in_off = tot;
+    tot += q.n_in;
+    q.res_off = tot;
+    tot += q.m_res;
+  }
+  if ((st = c->wait_staging())) return st;
+  int64_t ntasks = 0;
+  if ((st = c->plan(pin, &ntasks))) return st;
+  if ((st = c->in_host.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return st;
+  if ((st = c->in_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return st;
+  if ((st = c->out_host.reserve(sizeof(bp_bounds) * count))) return st;
+  if ((st = c->out_buf.reserve(sizeof(bp_bounds) * count))) return st;
+  int32_t *h = (int32_t *)c->in_host.p;
+  for (int64_t i = 0; i < count; ++i) {
+    if (pin[i].n_in) memcpy(h + pin[i].in_off, src_a[i], sizeof(int32_t) * (size_t)pin[i].n_in);
+    if (pin[i].m_res) memcpy(h + pin[i].res_off, src_b[i], sizeof(int32_t) * (size_t)pin[i].m_res);
+  }
+  HIP_TRY(hipMemcpyAsync(c->in_buf.p, h, sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1), hipMemcpyHostToDevice,
+                         c->stream));
+  if ((st = c->run(count, ntasks, (const int32_t *)c->in_buf.p, (bp_bounds *)c->out_buf.p, c->stream))) return st;
+  HIP_TRY(hipMemcpyAsync(c->out_host.p, c->out_buf.p, sizeof(bp_bounds) * count, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipEventRecord(c->done, c->stream));
+  return BP_OK;
+}
+
+// Wait for the batch launched by launch_host_batch and copy its results.
+bp_status collect_host_batch(Ctx *c, int64_t count, bp_bounds *out, bool check_status) {
+  HIP_TRY(hipEventSynchronize(c->done));
+  memcpy(out, c->out_host.p, sizeof(bp_bounds) * count);
+  if (!check_status) return BP_OK;
+  for (int64_t i = 0; i < count; ++i) {
+    if (out[i].status == BP_ERR_RANGE) return fail(BP_ERR_RANGE, "instance %lld: size or residual outside [0, C]", (long long)i);
+    if (out[i].status) return fail(out[i].status, "instance %lld: device status %d", (long long)i, out[i].status);
+  }
+  return BP_OK;
+}
+
+bp_status run_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<const int32_t *> &src_a,
+                                const std::vector<const int32_t *> &src_b, bp_bounds *out) {
+  bp_status st = launch_host_batch(c, pin, src_a, src_b);
+  if (st) return st;
+  return collect_host_batch(c, (int64_t)pin.size(), out, true);
+}
+
+bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,
+                       bool early, PlanIn *q) {
+  if (C < 1) return fail(BP_ERR_ARG, "C = %d < 1", C);
+  if (k < 0) return fail(BP_ERR_ARG, "k = %lld < 0", (long long)k);
+  if (n_in < 0 || m_res < 0) return fail(BP_ERR_ARG, "negative count");
+  if (n_in + m_res > BP_MAX_ITEMS) return fail(BP_ERR_LIMIT, "%lld items > %d", (long long)(n_in + m_res), BP_MAX_ITEMS);
+  memset(q, 0, sizeof *q);
+  q->C = C;
+  q->k = k;
+  q->n_in = n_in;
+  q->m_res = m_res;
+  q->form = form;
+  q->early_exit = early;
+  q->clamp = sw && (sw->flags & BP_SWEEP_PAPER_VB2_CLAMP);
+  return check_sweep(C, sw, q->lo, q->hi);
+}
+
+bp_status host_validate_items(int32_t C, const int32_t *items, int64_t r) {
+  for (int64_t i = 0; i < r; ++i)
+    if (items[i] < 0 || items[i] > C)
+      return fail(BP_ERR_RANGE, "item %lld has size %d outside [0, %d]", (long long)i, items[i], C);
+  return BP_OK;
+}
+
+}  // namespace bpi
+
+bp_status bp_lower_bounds(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *items, int64_t r, const bp_sweep *sweep,
+                          bp_bounds *out) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if (!out || (r > 0 && !items)) return fail(BP_ERR_ARG, "NULL argument");
+  std::vector<PlanIn> pin(1);
+  if ((st = make_plan_in(C, k, r, 0, kFormItems, sweep, false, &pin[0]))) return st;
+  if ((st = host_validate_items(C, items, r))) return st;
+  return run_host_batch(c, pin, {items}, {nullptr}, out);
+}
+
+bp_status bp_lower_bounds_dev(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *d_items, int64_t r,
+                              const bp_sweep *sweep, bp_bounds *d_out, void *stream) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if (!d_out || (r > 0 && !d_items)) return fail(BP_ERR_ARG, "NULL argument");
+  std::vector<PlanIn> pin(1);
+  if ((st = make_plan_in(C, k, r, 0, kFormItems, sweep, false, &pin[0]))) return st;
+  pin[0].in_off = 0;
+  if ((st = c->wait_staging())) return st;
+  int64_t ntasks = 0;
+  if ((st = c->plan(pin, &ntasks))) return st;
+  static const int32_t *dummy = nullptr;
+  (void)dummy;
+  return c->run(1, ntasks, d_items, d_out, (hipStream_t)stream);
+}
+
+bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *unpacked, int64_t n,
+                      uint32_t flags, int32_t *verdict, int64_t *lb, bp_bounds *bounds) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((m > 0 && !residual) || (n > 0 && !unpacked)) return fail(BP_ERR_ARG, "NULL input array");
+  if (flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  std::vector<PlanIn> pin(1);
+  if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0]))) return st;
+  if ((st = host_validate_items(C, unpacked, n))) return st;
+  if ((st = host_validate_items(C, residual, m))) return st;
+  bp_bounds o;
+  if ((st = run_host_batch(c, pin, {unpacked}, {residual}, &o))) return st;
+  if (verdict) *verdict = o.verdict;
+  if (lb) *lb = o.lb;
+  if (bounds) *bounds = o;
+  return BP_OK;
+}
+
+bp_status bp_feasible_dev(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *d_residual, const int32_t *d_unpacked,
+                          int64_t n, uint32_t flags, bp_bounds *d_out, void *stream) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if (!d_out || (m > 0 && !d_residual) || (n > 0 && !d_unpacked)) return fail(BP_ERR_ARG, "NULL argument");
+  if (flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  std::vector<PlanIn> pin(1);
+  if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0]))) return st;
+  // both arrays are addressed from the unpacked base: residual offset in elements
+  const ptrdiff_t diff = (m > 0 && n > 0) ? (d_residual - d_unpacked) : 0;
+  const int32_t *base = n > 0 ? d_unpacked : d_residual;
+  pin[0].in_off = 0;
+  pin[0].res_off = n > 0 ? diff : 0;
+  if ((st = c->wait_staging())) return st;
+  int64_t ntasks = 0;
+  if ((st = c->plan(pin, &ntasks))) return st;
+  return c->run(1, ntasks, base, d_out, (hipStream_t)stream);
+}
+
+static bp_status check_batch(const bp_batch *b) {
+  if (!b || b->count < 0 || (b->count > 0 && (!b->off || !b->C || !b->k)))
+    return fail(BP_ERR_ARG, "bad batch descriptor");
+  if (b->count > BP_MAX_BATCH) return fail(BP_ERR_LIMIT, "batch of %d > %d", b->count, BP_MAX_BATCH);
+  if (b->count > 0 && b->off[0] != 0) return fail(BP_ERR_ARG, "off[0] != 0");
+  for (int32_t i = 0; i < b->count; ++i)
+    if (b->off[i + 1] < b->off[i]) return fail(BP_ERR_ARG, "off not non-decreasing at %d", i);
+  return BP_OK;
+}
+
+static bp_status batch_plan_in(const bp_batch *b, const bp_sweep *per, bool early, std::vector<PlanIn> &pin) {
+  pin.resize(b->count);
+  for (int32_t i = 0; i < b->count; ++i) {
+    bp_status st = make_plan_in(b->C[i], b->k[i], b->off[i + 1] - b->off[i], 0, kFormItems, per ? &per[i] : nullptr,
+                                early, &pin[i]);
+    if (st) return st;
+  }
+  return BP_OK;
+}
+
+bp_status bp_lower_bounds_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, bp_bounds *out) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((st = check_batch(batch))) return st;
+  if (batch->count == 0) return BP_OK;
+  if (!out || !batch->items) return fail(BP_ERR_ARG, "NULL argument");
+  std::vector<PlanIn> pin;
+  if ((st = batch_plan_in(batch, per_inst, false, pin))) return st;
+  std::vector<const int32_t *> a(batch->count), b(batch->count, nullptr);
+  for (int32_t i = 0; i < batch->count; ++i) {
+    a[i] = batch->items + batch->off[i];
+    if ((st = host_validate_items(batch->C[i], a[i], pin[i].n_in))) return st;
+  }
+  return run_host_batch(c, pin, a, b, out);
+}
+
+bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const int32_t *d_items,
+                                    const bp_sweep *per_inst, bp_bounds *d_out, void *stream) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((st = check_batch(batch))) return st;
+  if (batch->count == 0) return BP_OK;
+  if (!d_out || !d_items) return fail(BP_ERR_ARG, "NULL argument");
+  std::vector<PlanIn> pin;
+  if ((st = batch_plan_in(batch, per_inst, false, pin))) return st;
+  for (int32_t i = 0; i < batch->count; ++i) {
+    pin[i].in_off = batch->off[i];
+    pin[i].res_off = batch->off[i];
+  }
+  if ((st = c->wait_staging())) return st;
+  int64_t ntasks = 0;
+  if ((st = c->plan(pin, &ntasks))) return st;
+  return c->run(batch->count, ntasks, d_items, d_out, (hipStream_t)stream);
+}
+
+bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((st = check_batch(batch))) return st;
+  if (flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  if (batch->count == 0) return BP_OK;
+  if (!batch->items) return fail(BP_ERR_ARG, "NULL items");
+  std::vector<PlanIn> pin;
+  if ((st = batch_plan_in(batch, nullptr, !(flags & BP_NO_EARLY_EXIT), pin))) return st;
+  std::vector<const int32_t *> a(batch->count), b(batch->count, nullptr);
+  for (int32_t i = 0; i < batch->count; ++i) {
+    a[i] = batch->items + batch->off[i];
+    if ((st = host_validate_items(batch->C[i], a[i], pin[i].n_in))) return st;
+  }
+  std::vector<bp_bounds> o(batch->count);
+  if ((st = run_host_batch(c, pin, a, b, o.data()))) return st;
+  for (int32_t i = 0; i < batch->count; ++i) {
+    if (verdict) verdict[i] = o[i].verdict;
+    if (lb) lb[i] = o[i].lb;
+  }
+  return BP_OK;
+}
+
+// ---- self test --------------------------------------------------------------
+
+int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32_t mode) {
+  if (d_lo < 1 || d_hi < d_lo || d_hi >= 0x80000000u || n_hi >= 0x80000000u) return BP_ERR_ARG;
+  int64_t bad = 0;
+  if (mode == 0) {
+    // floor(n / d) for n < 2^31 by family (1)
+    for (uint64_t d = d_lo; d <= d_hi; ++d) {
+      const MagicU31 g = magic_u31((uint32_t)d);
+      auto one = [&](uint64_t n) {
+        if (n >= 0x80000000ull) return;
+        if (div_u31((uint32_t)(2 * n), g.m, g.s) != (uint32_t)(n / d)) ++bad;
+      };
+      for (uint64_t n = 0; n <= n_hi; ++n) one(n);
+      for (uint64_t k = 1; k <= 64; ++k) {
+        const uint64_t mult = d * k;
+        one(mult - 1);
+        one(mult);
+        one(mult + 1);
+      }
+      const uint64_t q = 0x7fffffffull / d;
+      for (int64_t t = -2; t <= 2; ++t) {
+        one(q * d + t);
+        one(0x7fffffffull - (uint64_t)(t + 2));
+      }
+    }
+  } else if (mode == 1) {
+    // ceil(a lam / c) - 1 by family (2): c in [d_lo, d_hi], lam in [1, c], a in [1, c] (a capped at n_hi + edges)
+    for (uint64_t c = d_lo; c <= d_hi; ++c) {
+      const uint64_t lam_step = c > 4096 ? c / 4096 : 1;
+      for (uint64_t lam = 1; lam <= c; lam += (lam < 64 || c - lam < 64) ? 1 : lam_step) {
+        const uint64_t R = vb2_recip((uint32_t)lam, (uint32_t)c);
+        auto one = [&](uint64_t a) {
+          if (a < 1 || a > c) return;
+          const unsigned __int128 p = (unsigned __int128)a * lam;
+          const uint64_t want = (uint64_t)((p + c - 1) / c) - 1;
+          if (vb2_part((uint32_t)a, (uint32_t)R, (uint32_t)(R >> 32)) != want) ++bad;
+        };
+        for (uint64_t a = 1; a <= std::min<uint64_t>(c, n_hi); ++a) one(a);
+        for (uint64_t a = c > 64 ? c - 64 : 1; a <= c; ++a) one(a);
+        // a where a lam / c is an integer or just past one
+        for (uint64_t k = 1; k <= 32; ++k) {
+          const unsigned __int128 t = (unsigned __int128)k * c;
+          if (t % lam == 0) {
+            const uint64_t a = (uint64_t)(t / lam);
+            one(a - 1);
+            one(a);
+            one(a + 1);
+          } else {
+            const uint64_t a = (uint64_t)(t / lam);
+            one(a);
+            one(a + 1);
+          }
+        }
+      }
+    }
+  } else {
+    return BP_ERR_ARG;
+  }
+  return bad;
+}
+

@@ -1,0 +1,87 @@
+// bp_ctx.h -- host-side context of libbp (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "bp_internal.h"
+
+namespace bpi {
+
+constexpr uint64_t kCtxMagic = 0x6270637478303031ull;
+
+bp_status fail(bp_status st, const char *fmt, ...);
+bp_status hip_fail(hipError_t e, const char *what);
+void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]);
+
+// kernels (bp_kernels.hip)
+hipError_t set_kernel_attrs();
+hipError_t launch_pipeline(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
+                           int grid_fin, hipStream_t s);
+hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
+                                 int grid_fin, hipStream_t s, hipEvent_t ev[4]);
+hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
+                         int64_t n, unsigned long long *loads, int32_t *out, int64_t *out_r, int32_t *out_residual,
+                         int32_t *bad, hipStream_t s);
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  bp_status reserve(size_t bytes);
+  void release();
+};
+
+struct HostBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  bp_status reserve(size_t bytes);
+  void release();
+};
+
+// One instance as the planner sees it.
+struct PlanIn {
+  int64_t in_off, res_off, n_in, k;
+  int64_t lo[kNB], hi[kNB];
+  int32_t m_res, C, form;
+  bool early_exit, clamp;
+};
+
+struct Ctx {
+  uint64_t magic = 0;
+  int device = -1;
+  int num_cu = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t staged = nullptr;  // staging buffers consumed by the device
+  hipEvent_t done = nullptr;
+  bool use_graph = true;
+  bool timing = false;
+  hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int sweep_waves_per_cu = 24;
+  int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_fin = 0;
+  int64_t ws_items = 0, pre_items = 0, nentries = 0;
+
+  DevBuf desc_buf, counter_buf, in_buf, plan_buf, entry_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf,
+      ref_buf, out_buf, red_buf;
+  HostBuf desc_host, in_host, plan_host, entry_host, out_host, red_host;
+
+  bp_status init(int dev);
+  void destroy();
+  bp_status ensure_graph();
+  bp_status plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out);
+  bp_status run(int64_t count, int64_t ntasks, const int32_t *in_dev, bp_bounds *out_dev, hipStream_t s);
+  bp_status wait_staging();
+};
+
+bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,
+                       bool early, PlanIn *q);
+bp_status host_validate_items(int32_t C, const int32_t *items, int64_t r);
+bp_status launch_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<const int32_t *> &src_a,
+                            const std::vector<const int32_t *> &src_b);
+bp_status collect_host_batch(Ctx *c, int64_t count, bp_bounds *out, bool check_status);
+bp_status run_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<const int32_t *> &src_a,
+                         const std::vector<const int32_t *> &src_b, bp_bounds *out);
+
+}  // namespace bpi

@@ -1,0 +1,85 @@
+// bp_divide.h -- exact integer division by multiplication, for the sweep kernels.
+//
+// Two families, both exact for every input the kernels feed them (proofs
+// inline; the host self-test bp_selftest_division checks them against '/').
+//
+// (1) Division by a per-lane parameter d (1 <= d < 2^31) of a numerator
+//     n < 2^31.  Granlund & Montgomery, "Division by invariant integers using
+//     multiplication" (PLDI 1994), Theorem 4.2 with N = 31: with
+//     s = ceil(log2 d) and m = ceil(2^(31+s) / d), the product satisfies
+//     2^(31+s) <= m d < 2^(31+s) + d <= 2^(31+s) + 2^s, hence
+//     floor(n / d) = floor(m n / 2^(31+s)) for 0 <= n < 2^31.  Feeding 2n
+//     (< 2^32) to a 32x32 high multiply gives floor(m 2n / 2^32) >> s =
+//     floor(m n / 2^(31+s)).  m < 2^32 for every d < 2^31 (m = 2^31 when d is a
+//     power of two).  Cost: one v_mul_hi_u32 and one shift.
+//
+// (2) ceil(a * lam / c) - 1 for 1 <= a < 2^31, 1 <= lam <= c < 2^31 (the
+//     building block of f_VB2).  With the 64-bit per-lane constant
+//     R = ceil(lam 2^64 / c) - 1 we have lam 2^64 / c - 1 <= R < lam 2^64 / c,
+//     so v = a R / 2^64 lies in [a lam / c - 2^-33, a lam / c).  If a lam / c
+//     is an integer q, floor(v) = q - 1; otherwise its fraction is at least
+//     1/c > 2^-31 > 2^-33 and floor(v) = floor(a lam / c).  Both equal
+//     ceil(a lam / c) - 1.  floor(a R / 2^64) is the high word of
+//     a * R_hi + mulhi(a, R_lo) (no overflow: < 2^63 + 2^32).  Cost: one
+//     v_mul_hi_u32 and one v_mad_u64_u32.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace bpi {
+
+struct MagicU31 {
+  uint32_t m;
+  uint32_t s;
+};
+
+__host__ __device__ inline uint32_t ceil_log2_u32(uint32_t d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return d <= 1 ? 0u : 32u - (uint32_t)__clz((int)(d - 1));
+#else
+  return d <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(d - 1);
+#endif
+}
+
+// Constants of family (1) for divisor d in [1, 2^31).
+__host__ __device__ inline MagicU31 magic_u31(uint32_t d) {
+  uint32_t s = ceil_log2_u32(d);
+  uint64_t num = 1ull << (31 + s);
+  uint64_t m = (num + d - 1) / d;
+  return {(uint32_t)m, s};
+}
+
+// floor(n / d) given n2 = 2n (n < 2^31).
+__host__ __device__ inline uint32_t div_u31(uint32_t n2, uint32_t m, uint32_t s) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umulhi(n2, m) >> s;
+#else
+  return (uint32_t)(((uint64_t)n2 * m) >> 32) >> s;
+#endif
+}
+
+// Constant of family (2): ceil(lam 2^64 / c) - 1 for 1 <= lam <= c < 2^31.
+__host__ __device__ inline uint64_t vb2_recip(uint32_t lam, uint32_t c) {
+  if (lam >= c) return ~0ull;  // lam = c: 2^64 - 1
+  uint64_t x = (uint64_t)lam << 32;  // < 2^63
+  uint64_t q1 = x / c, r1 = x % c;   // q1 < 2^32 because lam < c
+  uint64_t y = r1 << 32;             // r1 < c < 2^31
+  uint64_t q2 = y / c, r2 = y % c;   // q2 < 2^32
+  uint64_t fl = (q1 << 32) | q2;     // floor(lam 2^64 / c), >= 1
+  return r2 ? fl : fl - 1;
+}
+
+// ceil(a lam / c) - 1 for 1 <= a < 2^31 from R = vb2_recip(lam, c).
+__host__ __device__ inline uint32_t vb2_part(uint32_t a, uint32_t r_lo, uint32_t r_hi) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint32_t t = __umulhi(a, r_lo);
+#else
+  uint32_t t = (uint32_t)(((uint64_t)a * r_lo) >> 32);
+#endif
+  uint64_t s = (uint64_t)a * r_hi + t;
+  return (uint32_t)(s >> 32);
+}
+
+}  // namespace bpi

@@ -1,0 +1,105 @@
+// bp_internal.h -- data layout shared by the host planner and the gfx950 kernels.
+//
+// One "launch" checks a batch of instances (a single check is a batch of one).
+// Everything a kernel needs is reached from one device-resident LaunchDesc,
+// so the captured HIP graph of the pipeline is reused for every call: the
+// host rewrites the descriptor and the inputs, then replays the graph.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/bp.h"
+
+namespace bpi {
+
+enum : int { kL1 = 0, kL2, kMT, kRAD2, kFS1, kCCM1, kVB2, kBJ1, kNB };
+
+constexpr int kWave = 64;
+constexpr int kLPL = 2;                 // parameters per lane in a sweep tile
+constexpr int kTile = kWave * kLPL;     // parameters per sweep tile
+constexpr int kSmallThreads = 256;      // prep block for small instances
+constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
+constexpr int kLargeThreads = 512;      // prep block for one large instance
+constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
+
+// Input form of an instance.
+enum : int32_t { kFormItems = 0, kFormResidual = 1 };
+
+// Per-instance plan, written by the host, read-only on the device.
+struct InstPlan {
+  int64_t in_off;    // items form: offset of items[]; residual form: offset of unpacked[]
+  int64_t res_off;   // residual form: offset of residual[] (int32) in the same input arena
+  int64_t n_in;      // items form: r; residual form: number of unpacked items
+  int64_t k;         // bins
+  int64_t ws_off;    // offset of this instance's slice of the per-item workspaces
+  int64_t pre_off;   // offset of this instance's prefix-sum slice (r_cap + 1 entries)
+  int64_t lo[kNB];   // parameter ranges (lo > hi: empty)
+  int64_t hi[kNB];
+  int32_t m_res;     // residual form: number of bins given as residuals
+  int32_t C;
+  int32_t form;
+  int32_t r_cap;     // n_in + m_res: upper bound of the reduced count
+  uint32_t flags;    // kPlanClampVB2 | kPlanEarlyExit
+  int32_t large;     // 1: prepared by the large-instance block
+};
+constexpr uint32_t kPlanClampVB2 = 1u;
+constexpr uint32_t kPlanEarlyExit = 2u;
+
+// Per-instance state, written by the prep kernel.
+struct InstState {
+  int64_t sumW;      // sum of all reduced sizes
+  int64_t sumBig;    // sum over big, not full items (c/2 < w < c)
+  int64_t sumNZ;     // sum over items with 0 < w < c
+  int64_t hiEff[kNB];// effective upper ends (the VB2 cut applied)
+  int32_t r;         // reduced item count
+  int32_t nf;        // [0, nf) items of size c
+  int32_t nb;        // [nf, nb) big: c/2 < w < c
+  int32_t nm;        // [nb, nm) mid: 2w = c
+  int32_t nz;        // [nm, nz) small: 0 < 2w < c ; [nz, r) zero
+  int32_t maxw;
+  int32_t status;    // BP_OK or an error found on the device
+  int32_t pad;
+};
+
+// One (instance, bound) entry of the sweep schedule.  Its parameter range is
+// cut into tiles of kTile parameters; a task is tpt consecutive tiles.
+struct Entry {
+  int64_t task_begin;   // prefix of task counts over entries (LPT order)
+  int64_t lam0;         // first parameter of the entry
+  int64_t ntiles;
+  int32_t inst;
+  int32_t bound;        // kL2 .. kBJ1
+  int32_t tpt;          // tiles per task
+  int32_t pad;
+};
+
+// Stream record of one item in a class-sorted instance (scalar-loaded by the sweep).
+struct alignas(16) ItemRec {
+  uint32_t w;    // size
+  uint32_t a;    // c - w for big items, w otherwise
+  uint32_t a2;   // 2a
+  uint32_t w2;   // 2w
+};
+
+struct LaunchDesc {
+  // inputs
+  const int32_t *in;        // input arena (items or unpacked + residuals)
+  const InstPlan *plan;
+  const Entry *entries;
+  // workspaces
+  InstState *state;
+  int32_t *sorted;          // per-item, descending sizes
+  int64_t *pre;             // prefix sums of sorted sizes
+  ItemRec *rec;             // class-sorted stream records
+  unsigned long long *keys; // [count][kNB] packed (value, parameter) maxima
+  int32_t *refuted;         // [count] early-exit flags
+  unsigned long long *counter; // task counter of the persistent sweep
+  bp_bounds *out;           // [count] results
+  int64_t count;            // instances
+  int64_t nentries;
+  int64_t ntasks;
+  int32_t nlarge;           // instances [0, nlarge) use the large prep block
+  int32_t pad;
+};
+
+}  // namespace bpi

@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results, so the bar is equality of every field: each bound, its
+smallest maximising parameter, lb, the first bound attaining lb, the verdict.
+Full-size instances whose dense sweep is too slow for the oracle are checked
+on sampled outputs: exact bounds where the oracle has an exact fast path
+(L1, L2, MT, RAD2 at their piece starts; FS1 densely), and for CCM1, VB2, BJ1
+the oracle's value at the GPU's maximising parameter plus an upper-bound
+check at sampled parameters.
+"""
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2402_14821_amd as bp
+from golden_io import fig3, hand_bounds
+from paper_2402_14821_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+NAME2ID = {n: i for i, n in enumerate(O.NAMES)}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bp.Context(0)
+    yield c
+    c.close()
+
+
+def same(got, want, what=""):
+    assert got["status"] == 0, (what, got)
+    assert np.array_equal(got["value"], want["value"]), (what, got["value"], want["value"])
+    assert np.array_equal(got["argmax"], want["argmax"]), (what, got["argmax"], want["argmax"])
+    assert got["lb"] == want["lb"] and got["lb_arg"] == want["lb_arg"], (what, got, want)
+    assert got["verdict"] == want["verdict"], what
+
+
+def row_dict(row):
+    return bp.bounds_to_dict(row)
+
+
+def rand_instance(rng, cmax=300, nmax=40):
+    C = rng.randint(1, cmax)
+    n = rng.randint(0, nmax)
+    pool = [0, C, C // 2, (C + 1) // 2, 1, C - 1]
+    items = [rng.choice(pool) if rng.random() < 0.2 else rng.randint(0, C) for _ in range(n)]
+    items = [min(max(w, 0), C) for w in items]
+    return C, items
+
+
+def test_fig3_worked_example(ctx):
+    g = fig3()
+    C, k = g["C"][0], g["bins"][0]
+    say("fig3 feasible")
+    got = ctx.feasible(C, g["residual"], g["unpacked"], flags=bp.BP_NO_EARLY_EXIT)
+    assert got["value"].tolist() == g["bounds"]
+    assert got["verdict"] == g["verdict_k4"][0] and got["r"] == 6
+    got = ctx.lower_bounds(C, k - 1, g["reduced"])
+    assert got["verdict"] == g["verdict_k3"][0]
+    same(got, O.bounds(C, k - 1, g["reduced"]), "fig3 k=3")
+
+
+@pytest.mark.parametrize("row", hand_bounds(), ids=lambda r: r[0])
+def test_hand_bounds(ctx, row):
+    name, C, lam, want, want_l2, items = row
+    say("hand", name)
+    got = ctx.lower_bounds(C, len(items), items)
+    same(got, O.bounds(C, len(items), items), name)
+    assert got["value"][O.L2] == want_l2
+    if name != "L2ODD":
+        assert got["value"][NAME2ID[name]] == want
+
+
+def test_random_small_instances(ctx):
+    rng = random.Random(101)
+    for t in range(250):
+        C, items = rand_instance(rng)
+        k = rng.randint(0, len(items) + 1)
+        say("random", t, C, len(items))
+        same(ctx.lower_bounds(C, k, items), O.bounds(C, k, items), (C, k, items))
+
+
+def test_batch_matches_oracle_and_single(ctx):
+    rng = random.Random(202)
+    insts = [rand_instance(rng, cmax=2000, nmax=300) for _ in range(200)]
+    Cs = [c for c, _ in insts]
+    ks = [rng.randint(0, len(it) + 1) for _, it in insts]
+    say("batch of", len(insts))
+    out = ctx.lower_bounds_batch(Cs, ks, [it for _, it in insts])
+    want = O.bounds_many([(C, k, it) for (C, it), k in zip(insts, ks)])
+    for i in range(len(insts)):
+        same(row_dict(out[i]), want[i], ("batch", i))
+    for i in range(0, len(insts), 37):
+        same(ctx.lower_bounds(Cs[i], ks[i], insts[i][1]), want[i], ("single", i))
+
+
+def test_small_partial_packings(ctx):
+    for seed in range(40):
+        C, m, res, unp = W.small_partial_packing(seed)
+        say("config-1 seed", seed)
+        items = O.residual_reduce(C, res, unp)
+        want = O.bounds(C, m, items)
+        got = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+        same(got, want, ("cfg1", seed))
+        assert got["r"] == len(items)
+        early = ctx.feasible(C, res, unp)
+        assert early["verdict"] == want["verdict"]
+        if want["verdict"] == 0:
+            assert early["lb"] > m
+
+
+def test_small_partial_packings_tight_bins(ctx):
+    # fewer bins than the optimum needs: the check must refute
+    for seed in range(20):
+        C, m, res, unp = W.small_partial_packing(seed, m=12)
+        items = O.residual_reduce(C, res, unp)
+        want = O.bounds(C, m, items)
+        say("tight config-1 seed", seed)
+        got = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+        same(got, want, ("tight", seed))
+        assert ctx.feasible(C, res, unp)["verdict"] == want["verdict"]
+
+
+def test_large_residual_instance_sampled(ctx):
+    C, m, res, unp = W.large_residual(1)
+    say("config-2 full size")
+    got = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+    items = O.residual_reduce(C, res, unp)
+    assert got["r"] == len(items) and got["status"] == 0
+    v, a = got["value"], got["argmax"]
+    assert v[O.L1] == O.l1(C, items)
+    for kind in (O.L2, O.MT, O.RAD2):
+        assert (v[kind], a[kind]) == O.piecewise_bound(kind, C, items), O.NAMES[kind]
+    assert (v[O.FS1], a[O.FS1]) == O.dff_bound(O.FS1, C, items)
+    rng = random.Random(9)
+    for d in (O.CCM1, O.VB2, O.BJ1):
+        lo, hi = O.default_range(d, C)
+        assert lo <= a[d] <= hi
+        assert O.dff_bound(d, C, items, a[d], a[d])[0] == v[d], O.NAMES[d]
+        for lam in [lo, hi, lo + 1, hi - 1] + [rng.randint(lo, hi) for _ in range(12)]:
+            val = O.dff_bound(d, C, items, lam, lam)[0]
+            assert val <= v[d] and (val < v[d] or lam >= a[d]), (O.NAMES[d], lam)
+    assert got["evals"] == len(items) * 308_433
+    assert got["lb"] == max(v) and got["verdict"] == int(max(v) <= m)
+
+
+def test_sweep_subranges_and_vb2_clamp(ctx):
+    rng = random.Random(303)
+    for t in range(60):
+        C, items = rand_instance(rng, cmax=5000, nmax=60)
+        dlo, dhi = zip(*(O.default_range(b, C) for b in range(O.NB)))
+        lo, hi = list(dlo), list(dhi)
+        for b in range(1, O.NB):
+            if dlo[b] <= dhi[b] and rng.random() < 0.7:
+                x, y = sorted(rng.randint(dlo[b], dhi[b]) for _ in range(2))
+                lo[b], hi[b] = x, y
+            elif rng.random() < 0.1:
+                lo[b], hi[b] = 1, 0
+        say("subrange", t, C)
+        got = ctx.lower_bounds(C, 3, items, bp.make_sweep(lo, hi))
+        same(got, O.bounds(C, 3, items, lo, hi, l2_dense=True), ("sub", C, items, lo, hi))
+    # the paper's VB2 cut
+    for t in range(20):
+        C, items = rand_instance(rng, cmax=3000, nmax=200)
+        say("clamp", t)
+        maxw = max(items) if items else 0
+        sw = bp.default_sweep(C, len(items), maxw, bp.BP_SWEEP_PAPER_VB2_CLAMP)
+        lo = list(sw.lo)
+        hi = list(sw.hi)
+        got = ctx.lower_bounds(C, 3, items, sw)
+        same(got, O.bounds(C, 3, items, lo, hi), ("clamp", C))
+
+
+def test_huge_capacity_windows(ctx):
+    rng = random.Random(404)
+    for C in (2**31 - 1, 2**31 - 2, 1_999_999_973, 2**30 + 1, 2**25 + 3, 1_000_000):
+        for t in range(3):
+            n = rng.randint(1, 50)
+            pool = [C, C - 1, C // 2, C // 2 + 1, (C + 1) // 2, 1, C // 3, C // 4 + 1]
+            items = [rng.choice(pool) if rng.random() < 0.4 else rng.randint(0, C) for _ in range(n)]
+            for side in ("low", "high"):
+                lo, hi = [0] * O.NB, [-1] * O.NB
+                for b in range(1, O.NB):
+                    dlo, dhi = O.default_range(b, C)
+                    if b == O.L2:
+                        lo[b], hi[b] = dlo, dhi  # exact over the full range (piece starts)
+                        continue
+                    if dlo > dhi:
+                        lo[b], hi[b] = 1, 0
+                        continue
+                    w = 200
+                    lo[b], hi[b] = (dlo, min(dhi, dlo + w - 1)) if side == "low" else (max(dlo, dhi - w + 1), dhi)
+                say("huge C", C, t, side, n)
+                got = ctx.lower_bounds(C, n, items, bp.make_sweep(lo, hi))
+                same(got, O.bounds(C, n, items, lo, hi, l2_dense=False), ("huge", C, side, items))
+
+
+def test_edge_cases(ctx):
+    cases = [
+        (1, []), (1, [0]), (1, [1, 1, 0]), (2, [1, 1, 2]), (3, [1, 2, 3, 0]), (7, [7] * 5),
+        (10, [0] * 9), (10, [5] * 7), (11, [6, 5, 6, 5]), (2**31 - 1, []), (2**31 - 1, [2**31 - 1]),
+    ]
+    for C, items in cases:
+        for k in (0, len(items)):
+            say("edge", C, items, k)
+            same(ctx.lower_bounds(C, k, items), O.bounds(C, k, items), (C, items, k))
+    say("empty residual form")
+    got = ctx.feasible(10, [], [], flags=bp.BP_NO_EARLY_EXIT)
+    assert got["lb"] == 0 and got["verdict"] == 1 and got["r"] == 0
+    got = ctx.feasible(10, [10, 10, 10], [], flags=bp.BP_NO_EARLY_EXIT)
+    assert got["r"] == 0 and got["verdict"] == 1
+
+
+@pytest.mark.parametrize("r", [8191, 8192, 8193, 16384])
+def test_block_capacity_boundaries(ctx, r):
+    rng = np.random.default_rng(r)
+    C = 600
+    items = rng.integers(0, C + 1, size=r).astype(np.int32)
+    say("capacity boundary r =", r)
+    same(ctx.lower_bounds(C, r // 2, items), O.bounds(C, r // 2, items), ("cap", r))
+
+
+def test_limits_and_range_errors(ctx):
+    say("errors")
+    with pytest.raises(bp.BpError) as e:
+        ctx.lower_bounds(10, 1, np.ones(16385, np.int32))
+    assert e.value.status == bp.BP_ERR_LIMIT
+    with pytest.raises(bp.BpError) as e:
+        ctx.lower_bounds(10, 1, [3, 11])
+    assert e.value.status == bp.BP_ERR_RANGE
+    with pytest.raises(bp.BpError) as e:
+        ctx.feasible(10, [11], [1])
+    assert e.value.status == bp.BP_ERR_RANGE
+    with pytest.raises(bp.BpError) as e:
+        ctx.lower_bounds(10, 1, [3], bp.make_sweep([0] * 8, [5] * 8))  # MT beyond c/2 ... RAD2 outside its range
+    assert e.value.status == bp.BP_ERR_RANGE
+    # still usable after errors
+    same(ctx.lower_bounds(10, 1, [3, 9]), O.bounds(10, 1, [3, 9]), "after errors")
+
+
+def test_reductions(ctx):
+    rng = random.Random(505)
+    for t in range(30):
+        C = rng.randint(1, 100)
+        m = rng.randint(0, 30)
+        res = [rng.randint(0, C) for _ in range(m)]
+        unp = [rng.randint(0, C) for _ in range(rng.randint(0, 40))]
+        say("residual_reduce", t)
+        assert ctx.residual_reduce(C, res, unp).tolist() == O.residual_reduce(C, res, unp).tolist()
+    for t in range(30):
+        C = rng.randint(1, 100)
+        m = rng.randint(1, 10)
+        loads = [0] * m
+        size, bin_of = [], []
+        for _ in range(rng.randint(0, 40)):
+            w = rng.randint(0, C)
+            j = rng.randint(-1, m - 1)
+            if j >= 0 and loads[j] + w > C:
+                j = -1
+            if j >= 0:
+                loads[j] += w
+            size.append(w)
+            bin_of.append(j)
+        say("assignment_reduce", t)
+        got_items, got_res = ctx.assignment_reduce(C, m, size, bin_of)
+        want_items, want_res = O.assignment_reduce(C, m, size, bin_of)
+        assert got_items.tolist() == want_items.tolist()
+        assert got_res.tolist() == want_res.tolist()
+    with pytest.raises(bp.BpError):
+        ctx.assignment_reduce(10, 1, [6, 6], [0, 0])  # bin over capacity
+
+
+def test_device_pointer_paths(ctx):
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rng = random.Random(606)
+    C, items = rand_instance(rng, cmax=1000, nmax=300)
+    d_items = torch.tensor(items or [0], dtype=torch.int32, device=dev)
+    d_out = torch.zeros(bp.BOUNDS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    say("lower_bounds_dev")
+    ctx.lower_bounds_dev(C, 5, d_items.data_ptr(), len(items), d_out.data_ptr(), stream)
+    torch.cuda.synchronize()
+    got = row_dict(np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=bp.BOUNDS_DTYPE)[0])
+    same(got, O.bounds(C, 5, items), "dev single")
+    insts = [rand_instance(rng, cmax=3000, nmax=200) for _ in range(50)]
+    off = np.zeros(len(insts) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(it) for _, it in insts])
+    flat = np.concatenate([np.asarray(it, np.int32) for _, it in insts] + [np.zeros(1, np.int32)])
+    d_flat = torch.from_numpy(flat).to(dev)
+    d_outb = torch.zeros(len(insts) * bp.BOUNDS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    say("lower_bounds_batch_dev")
+    ctx.lower_bounds_batch_dev([c for c, _ in insts], [2] * len(insts), off, d_flat.data_ptr(), d_outb.data_ptr(),
+                               stream)
+    torch.cuda.synchronize()
+    rows = np.frombuffer(d_outb.cpu().numpy().tobytes(), dtype=bp.BOUNDS_DTYPE)
+    want = O.bounds_many([(c, 2, it) for c, it in insts])
+    for i in range(len(insts)):
+        same(row_dict(rows[i]), want[i], ("dev batch", i))
+    # device-side validation reports a bad size in the record
+    bad = torch.tensor([5, 12], dtype=torch.int32, device=dev)
+    ctx.lower_bounds_dev(10, 1, bad.data_ptr(), 2, d_out.data_ptr(), stream)
+    torch.cuda.synchronize()
+    got = row_dict(np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=bp.BOUNDS_DTYPE)[0])
+    assert got["status"] == bp.BP_ERR_RANGE
+
+
+def test_repeated_calls_reuse_the_graph(ctx):
+    rng = random.Random(707)
+    insts = [rand_instance(rng, cmax=500, nmax=100) for _ in range(12)]
+    want = [O.bounds(C, 4, it) for C, it in insts]
+    for rep in range(3):
+        for i, (C, it) in enumerate(insts):
+            say("replay", rep, i)
+            same(ctx.lower_bounds(C, 4, it), want[i], ("replay", rep, i))
+
+
+def test_feasible_batch(ctx):
+    b = W.uneven_batch(2, count=48, capacities=(1_000, 10_000), nmax=800)
+    say("feasible_batch")
+    v, lb = ctx.feasible_batch(b.C, b.k, [b.instance(i)[2] for i in range(len(b))])
+    for i in range(len(b)):
+        C, k, items = b.instance(i)
+        want = O.bounds(C, k, items)
+        assert v[i] == want["verdict"], i
+        assert v[i] == (0 if b.expect_fail[i] else 1)
+        if v[i] == 0:
+            assert lb[i] > k
+        else:
+            assert lb[i] == want["lb"]
