@@ -109,11 +109,30 @@ _SIGNATURES = {
 _lib = None
 
 
+def _preload_torch_hip_runtime():
+    """Keep one HIP runtime per process.
+
+    PyTorch-ROCm ships its own libamdhip64 with the same soname as the
+    system one.  If libbp loaded the system copy first, torch would later load
+    its own and see no GPU.  Loading torch's copy first (by path, without
+    importing torch) makes libbp and torch share it.
+    """
+    import importlib.util
+
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return
+    cand = os.path.join(list(spec.submodule_search_locations)[0], "lib", "libamdhip64.so")
+    if os.path.exists(cand):
+        ctypes.CDLL(cand, mode=ctypes.RTLD_GLOBAL)
+
+
 def load(path: str | None = None):
     """Load libbp.so (built in-tree by ``paper_2402_14821_amd.build``)."""
     global _lib
     if _lib is not None:
         return _lib
+    _preload_torch_hip_runtime()
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise BpLibraryMissing(f"{p} is not built; run `python -m paper_2402_14821_amd.build`")

@@ -32,6 +32,30 @@
 
 namespace bpi {
 
+// Address spaces.  Every pointer reaches the kernels through the descriptor in
+// device memory, so it arrives as a generic pointer, and the compiler must
+// treat loads through generic pointers as per-lane (they could address
+// scratch).  Data that a kernel only reads is therefore read through the
+// constant address space (scalar loads when the address is wave-uniform),
+// per-lane data through the global one.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BP_CONST __attribute__((address_space(4)))
+#define BP_GLOBAL __attribute__((address_space(1)))
+#else
+#define BP_CONST
+#define BP_GLOBAL
+#endif
+
+template <typename T>
+__device__ __forceinline__ const BP_CONST T *as_const(const T *p) {
+  return (const BP_CONST T *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ const BP_GLOBAL T *as_global(const T *p) {
+  return (const BP_GLOBAL T *)p;
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level primitives (wave64, DPP).
 
@@ -86,6 +110,14 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// |a - b| + acc in one instruction (v_sad_u32).
+// a is wave-uniform (an item size) and is passed in an SGPR.
+__device__ __forceinline__ uint32_t sad_u32(uint32_t a, uint32_t b, uint32_t acc) {
+  uint32_t r;
+  asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(acc));
+  return r;
+}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -206,7 +238,7 @@ __device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n
 
 template <int NT, int CAP>
 __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CAP> &sm) {
-  const InstPlan &p = d.plan[inst];
+  const BP_CONST InstPlan &p = as_const(d.plan)[inst];
   InstState *st = &d.state[inst];
   const int tid = threadIdx.x;
   const int32_t C = p.C;
@@ -219,7 +251,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     status = BP_ERR_LIMIT;
   } else {
     // Reduction into LDS: sort key = c - w (ascending key = decreasing size).
-    const int32_t *in = d.in + p.in_off;
+    const BP_GLOBAL int32_t *in = as_global(d.in + p.in_off);
     const int64_t n_in = p.n_in;
     for (int64_t i = tid; i < n_in; i += NT) {
       int32_t w = in[i];
@@ -229,7 +261,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     int64_t nfill = 0;
     if (p.form == kFormResidual) {
       // one virtual item of size c - residual per bin with residual < c (Fig. 3)
-      const int32_t *res = d.in + p.res_off;
+      const BP_GLOBAL int32_t *res = as_global(d.in + p.res_off);
       for (int base = 0; base < p.m_res; base += NT) {
         const int j = base + tid;
         int32_t rj = j < p.m_res ? res[j] : C;
@@ -314,7 +346,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
 
 // Second half of prep (thread 0): sums, effective ranges, cleared results.
 __device__ void prep_finish(const LaunchDesc &d, int64_t inst) {
-  const InstPlan &p = d.plan[inst];
+  const BP_CONST InstPlan &p = as_const(d.plan)[inst];
   InstState *st = &d.state[inst];
   const int64_t *pre = d.pre + p.pre_off;
   const int32_t r = st->r;
@@ -340,10 +372,10 @@ template <int NT, int CAP, int LARGE>
 __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   PrepSmem<NT, CAP> &sm = *reinterpret_cast<PrepSmem<NT, CAP> *>(smem_raw);
-  const LaunchDesc d = *dp;
+  const LaunchDesc d = *as_const(dp);
   if (blockIdx.x == 0 && threadIdx.x == 0 && !LARGE) *d.counter = 0ull;
   for (int64_t inst = blockIdx.x; inst < d.count; inst += gridDim.x) {
-    if (d.plan[inst].large != LARGE) continue;
+    if (as_const(d.plan)[inst].large != LARGE) continue;
     prep_instance<NT, CAP>(d, inst, sm);
     __syncthreads();
     if (threadIdx.x == 0) prep_finish(d, inst);
@@ -356,9 +388,9 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
 // Lanes past the end of the range compute with lam = lo and are dropped.
 
 struct TileArgs {
-  const ItemRec *rec;
-  const int32_t *sorted;
-  const int64_t *pre;
+  const BP_CONST ItemRec *rec;
+  const BP_GLOBAL int32_t *sorted;
+  const BP_GLOBAL int64_t *pre;
   int64_t lo, hi;        // effective range of the bound
   int64_t lam0;          // first parameter of the tile
   int64_t k;
@@ -609,14 +641,29 @@ __device__ void tile_bj1(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[k
   for (int i0 = t.nf; i0 < t.nz;) {
     const int e = i0 + min(t.nz - i0, L);  // i0 + L could overflow int
     uint32_t sq[kLPL] = {}, sa[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
+    // unrolled by hand: the inline v_sad_u32 keeps the compiler from unrolling
+    int i = i0;
+    for (; i + 4 <= e; i += 4) {
+      ItemRec it[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) it[u] = t.rec[i + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        for (int j = 0; j < kLPL; ++j) {
+          const uint32_t q = div_u31(it[u].w2, mg[j], sh[j]);
+          const uint32_t v = q * lam[j] + pm[j];
+          sq[j] += q;
+          sa[j] = sad_u32(it[u].w, v, sa[j]);
+        }
+      }
+    }
+    for (; i < e; ++i) {
       const ItemRec it = t.rec[i];
       for (int j = 0; j < kLPL; ++j) {
         const uint32_t q = div_u31(it.w2, mg[j], sh[j]);
         const uint32_t v = q * lam[j] + pm[j];
         sq[j] += q;
-        sa[j] += max(it.w, v) - min(it.w, v);
+        sa[j] = sad_u32(it.w, v, sa[j]);
       }
     }
     for (int j = 0; j < kLPL; ++j) {
@@ -636,7 +683,7 @@ __device__ void tile_bj1(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[k
 }
 
 // First index of the decreasing array s[0..r) whose value is <= x.
-__device__ __forceinline__ int32_t first_le(const int32_t *s, int32_t r, int64_t x) {
+__device__ __forceinline__ int32_t first_le(const BP_GLOBAL int32_t *s, int32_t r, int64_t x) {
   int32_t lo = 0, hi = r;
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
@@ -692,7 +739,7 @@ __device__ __forceinline__ void flush_tile(const LaunchDesc &d, int64_t inst, in
   const uint64_t wmax = wave_max_u64(key);
   if (lane_id() == 0 && wmax) {
     atomicMax(&d.keys[inst * kNB + bound], (unsigned long long)wmax);
-    if (d.plan[inst].flags & kPlanEarlyExit) {
+    if (as_const(d.plan)[inst].flags & kPlanEarlyExit) {
       const int64_t v = (int64_t)(wmax >> 32) + (bound == kL2 ? 0 : t.nf);
       if (v > t.k) d.refuted[inst] = 1;
     }
@@ -700,7 +747,7 @@ __device__ __forceinline__ void flush_tile(const LaunchDesc &d, int64_t inst, in
   (void)best;
 }
 
-__device__ __forceinline__ int64_t find_entry(const Entry *e, int64_t n, uint64_t task) {
+__device__ __forceinline__ int64_t find_entry(const BP_CONST Entry *e, int64_t n, uint64_t task) {
   int64_t lo = 0, hi = n - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
@@ -710,23 +757,26 @@ __device__ __forceinline__ int64_t find_entry(const Entry *e, int64_t n, uint64_
 }
 
 __global__ __launch_bounds__(64) void k_sweep(const LaunchDesc *__restrict__ dp) {
-  const LaunchDesc d = *dp;
+  const LaunchDesc d = *as_const(dp);
+  const BP_CONST Entry *entries = as_const(d.entries);
+  const BP_CONST InstState *states = as_const(d.state);
+  const BP_CONST InstPlan *plans = as_const(d.plan);
   for (;;) {
     unsigned long long task = 0;
     if (lane_id() == 0) task = atomicAdd(d.counter, 1ull);
-    task = (unsigned long long)__builtin_amdgcn_readfirstlane((int)(uint32_t)task) |
+    task = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)task) |
            ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(task >> 32)) << 32);
     if (task >= (unsigned long long)d.ntasks) return;
-    const int64_t ei = find_entry(d.entries, d.nentries, task);
-    const Entry e = d.entries[ei];
+    const int64_t ei = find_entry(entries, d.nentries, task);
+    const BP_CONST Entry &e = entries[ei];
     const int64_t inst = e.inst;
-    const InstState &st = d.state[inst];
+    const BP_CONST InstState &st = states[inst];
     if (st.status != BP_OK) continue;
-    const InstPlan &p = d.plan[inst];
+    const BP_CONST InstPlan &p = plans[inst];
     TileArgs t;
-    t.rec = d.rec + p.ws_off;
-    t.sorted = d.sorted + p.ws_off;
-    t.pre = d.pre + p.pre_off;
+    t.rec = as_const(d.rec + p.ws_off);
+    t.sorted = as_global(d.sorted + p.ws_off);
+    t.pre = as_global(d.pre + p.pre_off);
     t.lo = p.lo[e.bound];
     t.hi = st.hiEff[e.bound];
     t.k = p.k;
@@ -738,10 +788,11 @@ __global__ __launch_bounds__(64) void k_sweep(const LaunchDesc *__restrict__ dp)
     t.nz = st.nz;
     t.sumBig = st.sumBig;
     t.sumNZ = st.sumNZ;
+    const bool early = (p.flags & kPlanEarlyExit) != 0;
     const int64_t tile0 = ((int64_t)task - e.task_begin) * e.tpt;
     const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
     for (int64_t tl = tile0; tl < tile1; ++tl) {
-      if ((p.flags & kPlanEarlyExit) && *(volatile int32_t *)&d.refuted[inst]) break;
+      if (early && __builtin_amdgcn_readfirstlane(*(volatile int32_t *)&d.refuted[inst])) break;
       t.lam0 = e.lam0 + tl * kTile;
       int64_t lam[kLPL], lbp[kLPL];
       bool ok[kLPL];
@@ -769,10 +820,10 @@ __global__ __launch_bounds__(64) void k_sweep(const LaunchDesc *__restrict__ dp)
 // Finalize: one thread per instance.
 
 __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__ dp) {
-  const LaunchDesc d = *dp;
+  const LaunchDesc d = *as_const(dp);
   for (int64_t inst = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; inst < d.count;
        inst += (int64_t)gridDim.x * blockDim.x) {
-    const InstPlan &p = d.plan[inst];
+    const BP_CONST InstPlan &p = as_const(d.plan)[inst];
     const InstState &st = d.state[inst];
     bp_bounds o;
     o.k = p.k;

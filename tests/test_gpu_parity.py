@@ -207,12 +207,19 @@ def test_huge_capacity_windows(ctx):
 def test_edge_cases(ctx):
     cases = [
         (1, []), (1, [0]), (1, [1, 1, 0]), (2, [1, 1, 2]), (3, [1, 2, 3, 0]), (7, [7] * 5),
-        (10, [0] * 9), (10, [5] * 7), (11, [6, 5, 6, 5]), (2**31 - 1, []), (2**31 - 1, [2**31 - 1]),
+        (10, [0] * 9), (10, [5] * 7), (11, [6, 5, 6, 5]),
     ]
     for C, items in cases:
         for k in (0, len(items)):
             say("edge", C, items, k)
             same(ctx.lower_bounds(C, k, items), O.bounds(C, k, items), (C, items, k))
+    # the largest capacity: every range cut to its first 64 parameters (the oracle cannot sweep 2^31)
+    C = 2**31 - 1
+    lo = [O.default_range(b, C)[0] for b in range(O.NB)]
+    hi = [min(O.default_range(b, C)[1], lo[b] + 63) for b in range(O.NB)]
+    for items in ([], [C], [C, C, 0], [C // 2 + 1, C // 2, 1]):
+        say("edge max C", items)
+        same(ctx.lower_bounds(C, 1, items, bp.make_sweep(lo, hi)), O.bounds(C, 1, items, lo, hi), ("maxC", items))
     say("empty residual form")
     got = ctx.feasible(10, [], [], flags=bp.BP_NO_EARLY_EXIT)
     assert got["lb"] == 0 and got["verdict"] == 1 and got["r"] == 0

@@ -1,0 +1,137 @@
+"""Served checks: continuous batching through bp_queue_* on the GPU.
+
+A request's result must be the same whether it runs alone (bp_feasible) or
+inside a mix of overlapping batches; the admission limits and the injected
+launch failure are forced from the host."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2402_14821_amd as bp
+from paper_2402_14821_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bp.Context(0)
+    yield c
+    c.close()
+
+
+def drain(q, n, deadline_s=60.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < n:
+        assert time.time() - t0 < deadline_s, f"only {len(out)} of {n} results"
+        for r in q.poll(256, timeout_us=20000):
+            out[r.ticket] = r
+    return out
+
+
+def fields(b):
+    return (list(b.value), list(b.argmax_lambda), b.lb, b.lb_arg, b.verdict, b.r, b.status)
+
+
+def test_alone_equals_in_mix(ctx):
+    reqs = W.dfs_requests(3, rate=20000, duration=1.0, max_requests=80)
+    say("queue mix of", len(reqs))
+    q = bp.Queue(ctx, 8 << 30, 4096)
+    tickets = {}
+    for i, r in enumerate(reqs):
+        tickets[q.submit(r.C, r.residual, r.unpacked, tag=i, flags=bp.BP_NO_EARLY_EXIT)] = i
+    res = drain(q, len(reqs))
+    st = q.stats()
+    q.close()
+    assert st["completed"] == len(reqs) and st["batches"] >= 1
+    for t, r in res.items():
+        i = tickets[t]
+        assert r.tag == i and r.status == 0
+        alone = ctx.feasible(reqs[i].C, reqs[i].residual, reqs[i].unpacked, flags=bp.BP_NO_EARLY_EXIT)
+        assert fields(r.bounds) == (list(alone["value"]), list(alone["argmax"]), alone["lb"], alone["lb_arg"],
+                                    alone["verdict"], alone["r"], 0), i
+        assert r.submit_us <= r.start_us <= r.done_us
+    # the oracle on the smallest few
+    small = sorted(range(len(reqs)), key=lambda i: len(reqs[i].unpacked))[:2]
+    for i in small:
+        items = O.residual_reduce(reqs[i].C, reqs[i].residual, reqs[i].unpacked)
+        want = O.bounds(reqs[i].C, len(reqs[i].residual), items)
+        got = [r for r in res.values() if r.tag == i][0].bounds
+        assert list(got.value) == want["value"].tolist() and got.verdict == want["verdict"]
+
+
+def test_early_exit_verdicts_in_mix(ctx):
+    reqs = W.dfs_requests(4, rate=200000, duration=1.0, max_requests=60)
+    say("queue early exit", len(reqs))
+    q = bp.Queue(ctx, 8 << 30, 4096)
+    tickets = {q.submit(r.C, r.residual, r.unpacked, tag=i): i for i, r in enumerate(reqs)}
+    res = drain(q, len(reqs))
+    q.close()
+    for t, r in res.items():
+        i = tickets[t]
+        full = ctx.feasible(reqs[i].C, reqs[i].residual, reqs[i].unpacked, flags=bp.BP_NO_EARLY_EXIT)
+        assert r.verdict == full["verdict"]
+        if r.verdict == 1:
+            assert r.lb == full["lb"]
+        else:
+            assert r.lb > len(reqs[i].residual)
+
+
+def test_admission_limits(ctx):
+    C, m, res, unp = W.large_residual(1)
+    q = bp.Queue(ctx, 1000, 4)
+    say("request larger than the budget")
+    with pytest.raises(bp.BpError) as e:
+        q.submit(C, res, unp)
+    assert e.value.status == bp.BP_ERR_LIMIT
+    q.close()
+    q = bp.Queue(ctx, 1 << 30, 1)
+    t1 = q.submit(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+    rejected = 0
+    t2 = None
+    t0 = time.time()
+    while t2 is None:
+        t2 = q.try_submit(150, [10, 20], [100, 50])
+        if t2 is None:
+            rejected += 1
+            time.sleep(0.0002)
+        assert time.time() - t0 < 30
+    out = drain(q, 2)
+    assert q.stats()["rejected"] == rejected
+    q.close()
+    assert out[t1].status == 0 and out[t2].status == 0
+    alone = ctx.feasible(150, [10, 20], [100, 50], flags=bp.BP_NO_EARLY_EXIT)
+    assert out[t2].lb == alone["lb"]
+
+
+def test_injected_launch_failure(ctx, monkeypatch):
+    monkeypatch.setenv("BP_TEST_FAIL_LAUNCH", "1")
+    q = bp.Queue(ctx, 1 << 30, 64)
+    monkeypatch.delenv("BP_TEST_FAIL_LAUNCH")
+    say("injected failure")
+    t1 = q.submit(150, [10], [100, 60])
+    r1 = drain(q, 1)[t1]
+    assert r1.status == bp.BP_ERR_DEVICE
+    t2 = q.submit(150, [10], [100, 60], flags=bp.BP_NO_EARLY_EXIT)
+    r2 = drain(q, 1)[t2]
+    q.close()
+    assert r2.status == 0
+    assert r2.lb == ctx.feasible(150, [10], [100, 60], flags=bp.BP_NO_EARLY_EXIT)["lb"]
+
+
+def test_destroy_while_busy(ctx):
+    C, m, res, unp = W.large_residual(2)
+    q = bp.Queue(ctx, 1 << 30, 64)
+    for i in range(6):
+        q.submit(C, res, unp, tag=i)
+    say("destroy while busy")
+    q.close()  # must finish or drain without hanging
