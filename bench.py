@@ -48,16 +48,18 @@ def cpu_baseline(C, items, target_s: float):
 
     O._load()
     threads = min(16, os.cpu_count() or 1)
-    # rate probe: one parameter of each function
-    t0 = time.perf_counter()
-    ev = 0
-    for d in O.DFFS:
-        lo, hi = O.default_range(d, C)
-        ev += O.dff_bound_strided(d, C, items, lo, lo, 1)[2]
-    rate1 = ev / max(time.perf_counter() - t0, 1e-9)
-    total_params = sum(max(0, O.default_range(d, C)[1] - O.default_range(d, C)[0] + 1) for d in O.DFFS)
-    want_evals = rate1 * threads * target_s
-    stride = max(1, int(total_params * len(items) / max(want_evals, 1)))
+    ranges = [(d, *O.default_range(d, C)) for d in O.DFFS]
+    ranges = [(d, lo, hi) for d, lo, hi in ranges if lo <= hi]
+
+    def pass_evals(stride):
+        t0 = time.perf_counter()
+        ev = sum(O.dff_bound_strided(d, C, items, lo, hi, stride)[2] for d, lo, hi in ranges)
+        return ev, time.perf_counter() - t0
+
+    # probe on every 1024th parameter (single thread), then size the sample to about target_s core-seconds
+    ev_probe, t_probe = pass_evals(1024)
+    full_core_s = t_probe * 1024
+    stride = max(1, int(round(full_core_s / target_s)))
     jobs = []
     for d in O.DFFS:
         lo, hi = O.default_range(d, C)
@@ -83,8 +85,111 @@ def cpu_baseline(C, items, target_s: float):
         evals = sum(ex.map(run, jobs))
     dt = time.perf_counter() - t0
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th parameter of each of the six sweeps of this instance "
-                      f"({evals} evaluations, {dt:.1f} s on {threads} threads)"}
+            "sample": f"every {stride}th parameter of each of the six sweeps of the same instance "
+                      f"({evals} (item, parameter) evaluations in {dt:.2f} s wall on {threads} threads; "
+                      f"a single-thread probe puts the whole instance at {full_core_s:.1f} core-s)"}
+
+
+def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, plain_max: int = 4096):
+    """Uneven batch: one batched call vs one plain call per instance (host in, host out)."""
+    import numpy as np
+
+    b = W.uneven_batch(seed, count=count)
+    items_list = [b.instance(i)[2] for i in range(len(b))]
+    Cs, ks = b.C, b.k
+    out = ctx.lower_bounds_batch(Cs, ks, items_list)  # warm-up (sizes the workspaces, captures the graph)
+    assert (out["status"] == 0).all()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = ctx.lower_bounds_batch(Cs, ks, items_list)
+        ts.append(time.perf_counter() - t0)
+    t_batch = min(ts)
+    evals = int(out["evals"].sum())
+    fails = int((out["verdict"] == 0).sum())
+    assert np.array_equal(out["verdict"] == 0, b.expect_fail), "batched verdicts differ from the construction"
+    # plain: one call per instance, each synchronous
+    n_plain = min(plain_max, len(b))
+    per = np.zeros(n_plain)
+    for i in range(n_plain):
+        C, k, it = b.instance(i)
+        t0 = time.perf_counter()
+        ctx.lower_bounds(C, k, it)
+        per[i] = time.perf_counter() - t0
+    classes = {}
+    for c in sorted(set(int(x) for x in Cs)):
+        idx = np.flatnonzero(Cs[:n_plain] == c)
+        classes[str(c)] = {"instances": int(len(idx)), "plain_checks_per_s": float(len(idx) / per[idx].sum()),
+                           "plain_mean_us": float(per[idx].mean() * 1e6)}
+    plain_rate = n_plain / per.sum()
+    return {"workload": f"{count} instances, n lognormal(median 400, sigma 1) clipped to [50, 5000], "
+                        "C in {1e3, 1e4, 1e6}, sizes U[1, C], 40% built to fail; host in/out",
+            "batched_s": t_batch, "batched_checks_per_s": len(b) / t_batch, "batched_evals_per_s": evals / t_batch,
+            "plain_checks_per_s": plain_rate, "batched_over_plain": (len(b) / t_batch) / plain_rate,
+            "evals": evals, "fails": fails, "per_class_plain": classes}
+
+
+def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30):
+    """Open-loop Poisson arrivals of DFS requests into a bp_queue; latency from the library's clock."""
+    import ctypes
+    import threading
+
+    import numpy as np
+
+    reqs = W.dfs_requests(seed, rate=rate, duration=duration)
+    lib = bp.load()
+    structs, keep = [], []
+    for i, r in enumerate(reqs):
+        res = np.ascontiguousarray(r.residual, dtype=np.int32)
+        unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
+        keep.append((res, unp))
+        structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
+                                     unp.ctypes.data_as(bp._P32), i, 0, 0))
+    q = bp.Queue(ctx, budget, 1 << 20)
+    results = []
+    done = threading.Event()
+
+    def poller():
+        arr = (bp.bp_result * 4096)()
+        got = ctypes.c_int32(0)
+        while True:
+            lib.bp_queue_poll(q.handle, ctypes.cast(arr, ctypes.c_void_p), 4096, ctypes.byref(got), 2000)
+            for j in range(got.value):
+                results.append((arr[j].tag, arr[j].submit_us, arr[j].done_us, arr[j].status, arr[j].bounds.evals))
+            if done.is_set() and len(results) + rejected[0] >= len(structs):
+                return
+
+    rejected = [0]
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    ticket = ctypes.c_uint64(0)
+    t0 = time.perf_counter()
+    late = 0.0
+    for i, r in enumerate(reqs):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= r.t:
+                break
+        late = max(late, now - r.t)
+        st = lib.bp_queue_submit(q.handle, ctypes.byref(structs[i]), 0, ctypes.byref(ticket))
+        if st == bp.BP_ERR_AGAIN:
+            rejected[0] += 1
+        elif st != 0:
+            raise bp.BpError(st, lib.bp_last_error().decode())
+    done.set()
+    th.join(timeout=120)
+    t_end = time.perf_counter() - t0
+    stats = q.stats()
+    q.close()
+    lat = np.array([d - s for _, s, d, st, _ in results if st == 0])
+    evals = sum(e for *_, st, e in results if st == 0)
+    return {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "completed": int(len(lat)),
+            "rejected": rejected[0], "checks_per_s": len(lat) / t_end, "evals_per_s": evals / t_end,
+            "p50_us": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_us": float(np.percentile(lat, 99)) if len(lat) else None,
+            "batches": stats["batches"], "peak_bytes": stats["bytes_peak"], "max_submit_lateness_s": late,
+            "workload": "DFS requests: roots n~U[200,5000], sizes U[C/20,C/2], C=10000, children commit 1-3 "
+                        "items by decreasing best fit; early exit on; HBM budget 8 GB"}
 
 
 def main():
@@ -92,9 +197,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="core-seconds of oracle work to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-checks", type=int, default=2000)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=0.25)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device copies of MIB MiB (scale for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -103,6 +213,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 5, "read_bytes_per_copy": n, "write_bytes_per_copy": n}))
+        return
 
     import paper_2402_14821_amd as bp
     from paper_2402_14821_amd import workloads as W
@@ -190,6 +310,11 @@ def main():
                                  "workload": "n=50 sizes U[20,100], m=20, C=150, 30% pre-packed; host in/out"},
         "verdict": rec["verdict"], "lb": rec["lb"],
     }
+    if not args.no_batched:
+        line["batched"] = bench_batched(bp, W, ctx)
+    if not args.no_served:
+        line["served"] = [bench_served(bp, W, ctx, rate, args.served_seconds, seed)
+                          for rate, seed in ((20_000.0, 3), (200_000.0, 4))]
     if not args.no_cpu_baseline:
         import oracle as O
         items = O.residual_reduce(C, residual, unpacked)

@@ -166,11 +166,7 @@ bp_status Ctx::init(int dev) {
   HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
   for (hipEvent_t &e : tev) HIP_TRY(hipEventCreate(&e));
-  bp_status st = desc_buf.reserve(sizeof(LaunchDesc));
-  if (st) return st;
-  st = counter_buf.reserve(256);
-  if (st) return st;
-  st = desc_host.reserve(sizeof(LaunchDesc));
+  bp_status st = counter_buf.reserve(256);
   if (st) return st;
   grid_sweep = num_cu * sweep_waves_per_cu;
   grid_prep_small = num_cu * 2;
@@ -188,10 +184,10 @@ void Ctx::destroy() {
   if (graph) (void)hipGraphDestroy(graph);
   graph_exec = nullptr;
   graph = nullptr;
-  for (DevBuf *b : {&desc_buf, &counter_buf, &in_buf, &plan_buf, &entry_buf, &state_buf, &sorted_buf, &pre_buf,
-                    &rec_buf, &keys_buf, &ref_buf, &out_buf, &red_buf})
+  for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
+                    &acc_buf, &cnt_buf, &out_buf, &red_buf})
     b->release();
-  for (HostBuf *b : {&desc_host, &in_host, &plan_host, &entry_host, &out_host, &red_host}) b->release();
+  for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (staged) (void)hipEventDestroy(staged);
   if (done) (void)hipEventDestroy(done);
   for (hipEvent_t &e : tev) {
@@ -204,11 +200,10 @@ void Ctx::destroy() {
 }
 
 // Captures the four-kernel pipeline once; every call replays it.
-bp_status Ctx::ensure_graph() {
+bp_status Ctx::ensure_graph(const LaunchDesc *d_desc) {
   if (!use_graph || graph_exec) return BP_OK;
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_pipeline((const LaunchDesc *)desc_buf.p, grid_prep_small, grid_prep_large, grid_sweep,
-                                  grid_fin, stream);
+  hipError_t le = launch_pipeline(d_desc, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
   if (le != hipSuccess) {
@@ -227,15 +222,20 @@ bp_status Ctx::ensure_graph() {
   return BP_OK;
 }
 
-// Build InstPlan + Entry tables into the pinned staging buffers.
+// Staging layout (one pinned block, copied to the device in one transfer):
+// [LaunchDesc][InstPlan x count][Entry x nentries][input int32 ...], each part
+// aligned to 256 bytes.
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Build InstPlan + Entry tables into the pinned staging block.
 bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   const int64_t count = (int64_t)pin.size();
-  bp_status st = plan_host.reserve(sizeof(InstPlan) * std::max<int64_t>(count, 1));
-  if (st) return st;
-  InstPlan *pl = (InstPlan *)plan_host.p;
+  std::vector<InstPlan> &pl = plan_vec;
+  pl.assign((size_t)count, InstPlan{});
   int64_t ws = 0, pre = 0;
   std::vector<Entry> ent;
   std::vector<double> tile_cost_v;
+  std::vector<int64_t> rcap_v;
   ent.reserve((size_t)count * 7);
   double total = 0;
   for (int64_t i = 0; i < count; ++i) {
@@ -285,84 +285,123 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       total += tc * (double)e.ntiles;
       ent.push_back(e);
       tile_cost_v.push_back(tc);
+      rcap_v.push_back(rcap);
     }
   }
   ws_items = ws;
   pre_items = pre;
-  // Task size: at least one tile; about 8 tasks per resident wave overall.
-  const double target = total / (8.0 * (double)grid_sweep);
+  // Task size: about 8 tasks per resident wave over the whole launch.  A tile
+  // cheaper than that is grouped with its neighbours; a dearer one is split
+  // into item chunks of at least kMinChunk items.
+  constexpr int64_t kMinChunk = 384;
+  const double target = std::max(1.0, total / (8.0 * (double)grid_sweep));
   std::vector<double> task_cost(ent.size());
+  int64_t acc = 0, cnt = 0;
   for (size_t j = 0; j < ent.size(); ++j) {
-    double tpt = std::floor(target / tile_cost_v[j]);
-    if (tpt < 1) tpt = 1;
-    if (tpt > (double)ent[j].ntiles) tpt = (double)ent[j].ntiles;
-    if (tpt > 1e9) tpt = 1e9;
-    ent[j].tpt = (int32_t)tpt;
-    task_cost[j] = tile_cost_v[j] * tpt;
+    Entry &e = ent[j];
+    const double tc = tile_cost_v[j];
+    if (tc <= target || e.bound == kL2) {
+      double tpt = std::floor(target / tc);
+      tpt = std::min(std::max(tpt, 1.0), std::min((double)e.ntiles, 1e9));
+      e.tpt = (int32_t)tpt;
+      e.nchunks = 1;
+      task_cost[j] = tc * tpt;
+    } else {
+      const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / kMinChunk);
+      const int64_t want = (int64_t)std::ceil(tc / target);
+      e.nchunks = (int32_t)std::min<int64_t>(std::min<int64_t>(want, maxch), 64);
+      e.tpt = 1;
+      task_cost[j] = tc / e.nchunks;
+    }
+    if (e.nchunks > 1) {
+      e.acc_base = acc;
+      e.cnt_base = cnt;
+      acc += e.ntiles * kTile;
+      cnt += e.ntiles;
+    }
   }
+  acc_len = acc;
+  cnt_len = cnt;
   std::vector<size_t> order(ent.size());
   for (size_t j = 0; j < order.size(); ++j) order[j] = j;
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_cost[a] > task_cost[b]; });
-  st = entry_host.reserve(sizeof(Entry) * std::max<size_t>(ent.size(), 1));
-  if (st) return st;
-  Entry *eo = (Entry *)entry_host.p;
+  entry_vec.resize(std::max<size_t>(ent.size(), 1));
+  memset(entry_vec.data(), 0, sizeof(Entry) * entry_vec.size());
   int64_t tb = 0;
   for (size_t j = 0; j < order.size(); ++j) {
     Entry e = ent[order[j]];
     e.task_begin = tb;
-    tb += (e.ntiles + e.tpt - 1) / e.tpt;
-    eo[j] = e;
+    tb += ((e.ntiles + e.tpt - 1) / e.tpt) * e.nchunks;
+    entry_vec[j] = e;
   }
   nentries = (int64_t)ent.size();
-  if (nentries == 0) {
-    memset(eo, 0, sizeof(Entry));
-  }
   *ntasks_out = tb;
   return BP_OK;
 }
 
-// Runs one planned launch.  in_dev: device input arena (already filled);
-// out_dev: device result array; s: stream to queue on.
-bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *in_dev, bp_bounds *out_dev, hipStream_t s) {
+// Runs one planned launch.  host_in (optional): input arena to stage with the
+// tables; else in_dev is the device input arena.  out_dev: device result
+// array; s: stream to queue on.
+bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len,
+                   const int32_t *in_dev, bp_bounds *out_dev, hipStream_t s) {
   bp_status st;
-  const size_t nplan = sizeof(InstPlan) * (size_t)count;
-  const size_t nent = sizeof(Entry) * (size_t)std::max<int64_t>(nentries, 1);
-  if ((st = plan_buf.reserve(nplan))) return st;
-  if ((st = entry_buf.reserve(nent))) return st;
+  const size_t off_plan = align256(sizeof(LaunchDesc));
+  const size_t off_ent = off_plan + align256(sizeof(InstPlan) * (size_t)count);
+  const size_t off_in = off_ent + align256(sizeof(Entry) * entry_vec.size());
+  const size_t total = off_in + (host_in ? align256(sizeof(int32_t) * (size_t)std::max<int64_t>(host_in_len, 1)) : 0);
+  if ((st = stage_host.reserve(total))) return st;
+  void *old_dev = stage_buf.p;
+  if ((st = stage_buf.reserve(total))) return st;
+  if (stage_buf.p != old_dev && graph_exec) {
+    // the graph holds the descriptor's address: capture again
+    (void)hipGraphExecDestroy(graph_exec);
+    (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   if ((st = state_buf.reserve(sizeof(InstState) * count))) return st;
   if ((st = sorted_buf.reserve(sizeof(int32_t) * ws_items))) return st;
-  if ((st = rec_buf.reserve(sizeof(ItemRec) * ws_items))) return st;
+  if ((st = rec_buf.reserve(sizeof(uint32_t) * ws_items))) return st;
   if ((st = pre_buf.reserve(sizeof(int64_t) * pre_items))) return st;
   if ((st = keys_buf.reserve(sizeof(unsigned long long) * kNB * count))) return st;
   if ((st = ref_buf.reserve(sizeof(int32_t) * count))) return st;
-  LaunchDesc *d = (LaunchDesc *)desc_host.p;
-  d->in = in_dev;
-  d->plan = (const InstPlan *)plan_buf.p;
-  d->entries = (const Entry *)entry_buf.p;
+  if ((st = acc_buf.reserve(sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
+  if ((st = cnt_buf.reserve(sizeof(uint32_t) * (size_t)std::max<int64_t>(cnt_len, 1)))) return st;
+  char *h = (char *)stage_host.p;
+  char *dv = (char *)stage_buf.p;
+  LaunchDesc *d = (LaunchDesc *)h;
+  memset(d, 0, sizeof *d);
+  d->in = host_in ? (const int32_t *)(dv + off_in) : in_dev;
+  d->plan = (const InstPlan *)(dv + off_plan);
+  d->entries = (const Entry *)(dv + off_ent);
   d->state = (InstState *)state_buf.p;
   d->sorted = (int32_t *)sorted_buf.p;
   d->pre = (int64_t *)pre_buf.p;
-  d->rec = (ItemRec *)rec_buf.p;
+  d->av = (uint32_t *)rec_buf.p;
   d->keys = (unsigned long long *)keys_buf.p;
   d->refuted = (int32_t *)ref_buf.p;
   d->counter = (unsigned long long *)counter_buf.p;
+  d->acc = (long long *)acc_buf.p;
+  d->tile_cnt = (uint32_t *)cnt_buf.p;
   d->out = out_dev;
   d->count = count;
   d->nentries = nentries;
   d->ntasks = ntasks;
-  HIP_TRY(hipMemcpyAsync(plan_buf.p, plan_host.p, nplan, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(entry_buf.p, entry_host.p, nent, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(desc_buf.p, desc_host.p, sizeof(LaunchDesc), hipMemcpyHostToDevice, s));
+  d->acc_len = acc_len;
+  d->cnt_len = cnt_len;
+  memcpy(h + off_plan, plan_vec.data(), sizeof(InstPlan) * (size_t)count);
+  memcpy(h + off_ent, entry_vec.data(), sizeof(Entry) * entry_vec.size());
+  if (host_in && host_in_len > 0) memcpy(h + off_in, host_in, sizeof(int32_t) * (size_t)host_in_len);
+  HIP_TRY(hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(staged, s));
+  const LaunchDesc *d_desc = (const LaunchDesc *)dv;
   if (timing) {
-    HIP_TRY(launch_pipeline_timed((const LaunchDesc *)desc_buf.p, grid_prep_small, grid_prep_large, grid_sweep,
-                                  grid_fin, s, tev));
+    HIP_TRY(launch_pipeline_timed(d_desc, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, s, tev));
   } else if (use_graph) {
-    if ((st = ensure_graph())) return st;
+    if ((st = ensure_graph(d_desc))) return st;
     HIP_TRY(hipGraphLaunch(graph_exec, s));
   } else {
-    HIP_TRY(launch_pipeline((const LaunchDesc *)desc_buf.p, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
-                            s));
+    HIP_TRY(launch_pipeline(d_desc, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, s));
   }
   return BP_OK;
 }
@@ -545,7 +584,6 @@ bp_status launch_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
   if ((st = c->in_host.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return st;
-  if ((st = c->in_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return st;
   if ((st = c->out_host.reserve(sizeof(bp_bounds) * count))) return st;
   if ((st = c->out_buf.reserve(sizeof(bp_bounds) * count))) return st;
   int32_t *h = (int32_t *)c->in_host.p;
@@ -553,9 +591,7 @@ bp_status launch_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<
     if (pin[i].n_in) memcpy(h + pin[i].in_off, src_a[i], sizeof(int32_t) * (size_t)pin[i].n_in);
     if (pin[i].m_res) memcpy(h + pin[i].res_off, src_b[i], sizeof(int32_t) * (size_t)pin[i].m_res);
   }
-  HIP_TRY(hipMemcpyAsync(c->in_buf.p, h, sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1), hipMemcpyHostToDevice,
-                         c->stream));
-  if ((st = c->run(count, ntasks, (const int32_t *)c->in_buf.p, (bp_bounds *)c->out_buf.p, c->stream))) return st;
+  if ((st = c->run(count, ntasks, h, tot, nullptr, (bp_bounds *)c->out_buf.p, c->stream))) return st;
   HIP_TRY(hipMemcpyAsync(c->out_host.p, c->out_buf.p, sizeof(bp_bounds) * count, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipEventRecord(c->done, c->stream));
   return BP_OK;
@@ -632,7 +668,7 @@ bp_status bp_lower_bounds_dev(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *
   if ((st = c->plan(pin, &ntasks))) return st;
   static const int32_t *dummy = nullptr;
   (void)dummy;
-  return c->run(1, ntasks, d_items, d_out, (hipStream_t)stream);
+  return c->run(1, ntasks, nullptr, 0, d_items, d_out, (hipStream_t)stream);
 }
 
 bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *unpacked, int64_t n,
@@ -671,7 +707,7 @@ bp_status bp_feasible_dev(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *d_re
   if ((st = c->wait_staging())) return st;
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
-  return c->run(1, ntasks, base, d_out, (hipStream_t)stream);
+  return c->run(1, ntasks, nullptr, 0, base, d_out, (hipStream_t)stream);
 }
 
 static bp_status check_batch(const bp_batch *b) {
@@ -728,7 +764,7 @@ bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const in
   if ((st = c->wait_staging())) return st;
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
-  return c->run(batch->count, ntasks, d_items, d_out, (hipStream_t)stream);
+  return c->run(batch->count, ntasks, nullptr, 0, d_items, d_out, (hipStream_t)stream);
 }
 
 bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb) {

@@ -59,19 +59,22 @@ struct Ctx {
   hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  int sweep_waves_per_cu = 24;
+  int sweep_waves_per_cu = 32;
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_fin = 0;
-  int64_t ws_items = 0, pre_items = 0, nentries = 0;
+  int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, cnt_len = 0;
+  std::vector<InstPlan> plan_vec;
+  std::vector<Entry> entry_vec;
 
-  DevBuf desc_buf, counter_buf, in_buf, plan_buf, entry_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf,
-      ref_buf, out_buf, red_buf;
-  HostBuf desc_host, in_host, plan_host, entry_host, out_host, red_host;
+  DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, cnt_buf,
+      out_buf, red_buf;
+  HostBuf stage_host, in_host, out_host, red_host;
 
   bp_status init(int dev);
   void destroy();
-  bp_status ensure_graph();
+  bp_status ensure_graph(const LaunchDesc *d_desc);
   bp_status plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out);
-  bp_status run(int64_t count, int64_t ntasks, const int32_t *in_dev, bp_bounds *out_dev, hipStream_t s);
+  bp_status run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len, const int32_t *in_dev,
+                bp_bounds *out_dev, hipStream_t s);
   bp_status wait_staging();
 };
 

@@ -62,23 +62,18 @@ struct InstState {
 };
 
 // One (instance, bound) entry of the sweep schedule.  Its parameter range is
-// cut into tiles of kTile parameters; a task is tpt consecutive tiles.
+// cut into tiles of kTile parameters.  A task is either tpt consecutive tiles
+// over all items (nchunks = 1) or one of nchunks item chunks of one tile.
 struct Entry {
   int64_t task_begin;   // prefix of task counts over entries (LPT order)
   int64_t lam0;         // first parameter of the entry
   int64_t ntiles;
+  int64_t acc_base;     // nchunks > 1: this entry's per-parameter accumulators
+  int64_t cnt_base;     // nchunks > 1: this entry's per-tile chunk counters
   int32_t inst;
   int32_t bound;        // kL2 .. kBJ1
   int32_t tpt;          // tiles per task
-  int32_t pad;
-};
-
-// Stream record of one item in a class-sorted instance (scalar-loaded by the sweep).
-struct alignas(16) ItemRec {
-  uint32_t w;    // size
-  uint32_t a;    // c - w for big items, w otherwise
-  uint32_t a2;   // 2a
-  uint32_t w2;   // 2w
+  int32_t nchunks;      // item chunks per tile
 };
 
 struct LaunchDesc {
@@ -90,16 +85,18 @@ struct LaunchDesc {
   InstState *state;
   int32_t *sorted;          // per-item, descending sizes
   int64_t *pre;             // prefix sums of sorted sizes
-  ItemRec *rec;             // class-sorted stream records
+  uint32_t *av;             // per item: c - w for big items, w otherwise
   unsigned long long *keys; // [count][kNB] packed (value, parameter) maxima
   int32_t *refuted;         // [count] early-exit flags
   unsigned long long *counter; // task counter of the persistent sweep
+  long long *acc;           // chunk accumulators (one per parameter of split tiles)
+  uint32_t *tile_cnt;       // finished chunks per split tile
   bp_bounds *out;           // [count] results
   int64_t count;            // instances
   int64_t nentries;
   int64_t ntasks;
-  int32_t nlarge;           // instances [0, nlarge) use the large prep block
-  int32_t pad;
+  int64_t acc_len;
+  int64_t cnt_len;
 };
 
 }  // namespace bpi

@@ -311,17 +311,11 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     __syncthreads();
     const int nf = sm.flags[1], nb = sm.flags[2], nm = sm.flags[3], nz = sm.flags[4];
     int32_t *sorted = d.sorted + p.ws_off;
-    ItemRec *rec = d.rec + p.ws_off;
+    uint32_t *av = d.av + p.ws_off;
     for (int i = tid; i < r; i += NT) {
       const uint32_t w = sz[i];
       sorted[i] = (int32_t)w;
-      const uint32_t a = (2ull * w > uC) ? uC - w : w;
-      ItemRec ir;
-      ir.w = w;
-      ir.a = a;
-      ir.a2 = 2u * a;
-      ir.w2 = 2u * w;
-      rec[i] = ir;
+      av[i] = (2ull * w > uC) ? uC - w : w;  // c - w for big items, w otherwise
     }
     int64_t *pre = d.pre + p.pre_off;
     block_prefix<NT, CAP>(sm, sz, (int)r, pre);
@@ -373,7 +367,6 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   PrepSmem<NT, CAP> &sm = *reinterpret_cast<PrepSmem<NT, CAP> *>(smem_raw);
   const LaunchDesc d = *as_const(dp);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !LARGE) *d.counter = 0ull;
   for (int64_t inst = blockIdx.x; inst < d.count; inst += gridDim.x) {
     if (as_const(d.plan)[inst].large != LARGE) continue;
     prep_instance<NT, CAP>(d, inst, sm);
@@ -384,17 +377,27 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
 }
 
 // ---------------------------------------------------------------------------
-// Sweep tiles.  Each lane holds kLPL parameters lam = lam0 + lane + 64 j.
-// Lanes past the end of the range compute with lam = lo and are dropped.
+// Sweep tiles.  Each lane holds kLPL parameters lam = lam0 + lane + 64 j;
+// lanes past the end of the range compute with lam = lo and are dropped.
+//
+// A tile's items may be split into chunks run by different waves.  Every
+// function's per-parameter sum is an instance constant plus a part that is a
+// plain sum over the streamed items, so a chunk computes that part exactly
+// (int64) over its items; parts of different chunks are added with 64-bit
+// atomics and the wave that finishes a tile's last chunk finalises it.
+// Streamed items are [nf, nz); functions with a class split stream
+// [nf, nb) (big) and [nm, nz) (small) and count the mid items.
 
 struct TileArgs {
-  const BP_CONST ItemRec *rec;
-  const BP_GLOBAL int32_t *sorted;
+  const BP_CONST uint32_t *wv;     // sizes, decreasing (scalar stream)
+  const BP_CONST uint32_t *av;     // c - w for big items, w otherwise (scalar stream)
+  const BP_GLOBAL int32_t *sorted; // sizes again, for per-lane binary search
   const BP_GLOBAL int64_t *pre;
   int64_t lo, hi;        // effective range of the bound
   int64_t lam0;          // first parameter of the tile
   int64_t k;
   int32_t C, r, nf, nb, nm, nz;
+  int32_t i0, i1;        // streamed item range of this chunk, inside [nf, nz)
   int64_t sumBig, sumNZ;
 };
 
@@ -408,104 +411,140 @@ __device__ __forceinline__ int chunk_len(uint64_t maxinc) {
 
 __device__ __forceinline__ int64_t ceil_div_i64(int64_t a, int64_t b) { return a / b + (a % b != 0); }
 
-// f_MT: big items add c when c - w < lambda (else w, summed in sumBig);
-// mid items add c/2; small items add w when w >= lambda.
-__device__ void tile_mt(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL]) {
-  uint32_t lam[kLPL];
-  for (int j = 0; j < kLPL; ++j) {
-    int64_t L = t.lam0 + lane_id() + 64 * j;
-    lam_out[j] = L;
-    lam[j] = (uint32_t)(L <= t.hi ? L : t.lo);
-  }
-  uint64_t acc[kLPL] = {};
-  const int L = chunk_len((uint64_t)t.C / 2 + 1);
-  for (int i0 = t.nf; i0 < t.nb;) {
-    const int e = i0 + min(t.nb - i0, L);  // i0 + L could overflow int
-    uint32_t s[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
-      const uint32_t a = t.rec[i].a;
-      for (int j = 0; j < kLPL; ++j) s[j] += a < lam[j] ? a : 0u;
+// Calls f(p[i]) for i in [i0, i1) in order.  Every lane uses the same item,
+// so items are read with scalar loads, 8 at a time, and the next block's
+// loads are issued before the current block is processed: the stream is
+// larger than the scalar cache, and this hides the latency of its misses.
+template <typename F>
+__device__ __forceinline__ void stream_u32(const BP_CONST uint32_t *p, int i0, int i1, F &&f) {
+  constexpr int U = 8;
+  int i = i0;
+  if (i1 - i >= U) {
+    uint32_t cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = p[i + u];
+    i += U;
+    for (; i + U <= i1; i += U) {
+      uint32_t nxt[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) nxt[u] = p[i + u];
+#pragma unroll
+      for (int u = 0; u < U; ++u) f(cur[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
-    for (int j = 0; j < kLPL; ++j) acc[j] += s[j];
-    i0 = e;
+#pragma unroll
+    for (int u = 0; u < U; ++u) f(cur[u]);
   }
-  for (int i0 = t.nm; i0 < t.nz;) {
-    const int e = i0 + min(t.nz - i0, L);  // i0 + L could overflow int
+  for (; i < i1; ++i) f(p[i]);
+}
+
+// Sums over [i0, i1) in segments of at most L items so that 32-bit partial
+// sums cannot wrap; flushes each segment into the 64-bit totals.
+template <typename F>
+__device__ __forceinline__ void stream_chunked(const BP_CONST uint32_t *p, int i0, int i1, int L,
+                                               uint64_t tot[kLPL], F &&f) {
+  for (int a = i0; a < i1;) {
+    const int e = a + min(i1 - a, L);  // a + L could overflow int
     uint32_t s[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
-      const uint32_t w = t.rec[i].w;
-      for (int j = 0; j < kLPL; ++j) s[j] += w >= lam[j] ? w : 0u;
-    }
-    for (int j = 0; j < kLPL; ++j) acc[j] += s[j];
-    i0 = e;
-  }
-  const int64_t nmid = t.nm - t.nb;
-  for (int j = 0; j < kLPL; ++j) {
-    const int64_t S = t.sumBig + (int64_t)acc[j] + nmid * (int64_t)(t.C / 2);
-    lbp[j] = ceil_div_i64(S, (int64_t)t.C);
+    stream_u32(p, a, e, [&](uint32_t x) { f(x, s); });
+    for (int j = 0; j < kLPL; ++j) tot[j] += s[j];
+    a = e;
   }
 }
 
-// f_RAD2 (c/4 < lambda <= c/3), counts of threshold crossings:
+__device__ __forceinline__ void tile_lams(const TileArgs &t, int64_t lam_out[kLPL], uint32_t lam[kLPL]) {
+  for (int j = 0; j < kLPL; ++j) {
+    const int64_t L = t.lam0 + lane_id() + 64 * j;
+    lam_out[j] = L;
+    lam[j] = (uint32_t)(L <= t.hi ? L : t.lo);
+  }
+}
+
+// Class-split item ranges of this chunk.
+__device__ __forceinline__ void split_ranges(const TileArgs &t, int &b0, int &b1, int &s0, int &s1) {
+  b0 = max(t.i0, t.nf);
+  b1 = min(t.i1, t.nb);
+  s0 = max(t.i0, t.nm);
+  s1 = min(t.i1, t.nz);
+}
+
+// f_MT.  part = sum_big [c - w < lambda] (c - w) + sum_small [w >= lambda] w;
+// S = sum_big w + n_mid c/2 + part.  The conditions are sign bits of 32-bit
+// differences (all operands < 2^31), turned into masks: no compare, no select.
+__device__ void part_mt(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+  int b0, b1, s0, s1;
+  split_ranges(t, b0, b1, s0, s1);
+  uint32_t lm1[kLPL];
+  for (int j = 0; j < kLPL; ++j) lm1[j] = lam[j] - 1u;  // lambda - 1 (wraps to -1 for lambda = 0)
+  uint64_t acc[kLPL] = {};
+  const int L = chunk_len((uint64_t)t.C / 2 + 1);
+  stream_chunked(t.av, b0, b1, L, acc, [&](uint32_t a, uint32_t *s) {
+    for (int j = 0; j < kLPL; ++j) s[j] += (uint32_t)((int32_t)(a - lam[j]) >> 31) & a;
+  });
+  stream_chunked(t.wv, s0, s1, L, acc, [&](uint32_t w, uint32_t *s) {
+    for (int j = 0; j < kLPL; ++j) s[j] += (uint32_t)((int32_t)(lm1[j] - w) >> 31) & w;
+  });
+  for (int j = 0; j < kLPL; ++j) part[j] = (int64_t)acc[j];
+}
+
+__device__ __forceinline__ int64_t fin_mt(const TileArgs &t, int64_t lam, int64_t part) {
+  const int64_t S = t.sumBig + (int64_t)(t.nm - t.nb) * (int64_t)(t.C / 2) + part;
+  return ceil_div_i64(S, (int64_t)t.C);
+}
+
+// f_RAD2 (c/4 < lambda <= c/3), from counts of threshold crossings:
 //   small: c3 [w >= lambda] + (c2 - c3) [w > c - 2 lambda]
 //   big:   c2 + (c - c2 - c3) [w >= 2 lambda] + c3 [w > c - lambda]
 //   mid:   c2
-__device__ void tile_rad2(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL]) {
-  uint32_t t1[kLPL], t2[kLPL], t3[kLPL], t4[kLPL];
+// part = the count terms; S = (n_big + n_mid) c2 + part.
+__device__ void part_rad2(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+  int b0, b1, s0, s1;
+  split_ranges(t, b0, b1, s0, s1);
+  // w >= t  <=>  (t - 1) - w < 0: count the sign bits (thresholds <= c, sizes < 2^31)
+  uint32_t u1[kLPL], u2[kLPL], u3[kLPL], u4[kLPL];
   for (int j = 0; j < kLPL; ++j) {
-    int64_t L = t.lam0 + lane_id() + 64 * j;
-    lam_out[j] = L;
-    const uint32_t l = (uint32_t)(L <= t.hi ? L : t.lo);
-    t1[j] = l;
-    t2[j] = (uint32_t)t.C - 2u * l + 1u;
-    t3[j] = 2u * l;
-    t4[j] = (uint32_t)t.C - l + 1u;
+    u1[j] = lam[j] - 1u;                        // w >= lambda
+    u2[j] = (uint32_t)t.C - 2u * lam[j];        // w >= c - 2 lambda + 1
+    u3[j] = 2u * lam[j] - 1u;                   // w >= 2 lambda
+    u4[j] = (uint32_t)t.C - lam[j];             // w >= c - lambda + 1
   }
   uint32_t n1[kLPL] = {}, n2[kLPL] = {}, n3[kLPL] = {}, n4[kLPL] = {};
-#pragma unroll 8
-  for (int i = t.nm; i < t.nz; ++i) {
-    const uint32_t w = t.rec[i].w;
+  stream_u32(t.wv, s0, s1, [&](uint32_t w) {
     for (int j = 0; j < kLPL; ++j) {
-      n1[j] += w >= t1[j];
-      n2[j] += w >= t2[j];
+      n1[j] += (u1[j] - w) >> 31;
+      n2[j] += (u2[j] - w) >> 31;
     }
-  }
-#pragma unroll 8
-  for (int i = t.nf; i < t.nb; ++i) {
-    const uint32_t w = t.rec[i].w;
+  });
+  stream_u32(t.wv, b0, b1, [&](uint32_t w) {
     for (int j = 0; j < kLPL; ++j) {
-      n3[j] += w >= t3[j];
-      n4[j] += w >= t4[j];
+      n3[j] += (u3[j] - w) >> 31;
+      n4[j] += (u4[j] - w) >> 31;
     }
-  }
+  });
   const int64_t C = t.C, c3 = C / 3, c2 = C / 2;
-  const int64_t nbig = t.nb - t.nf, nmid = t.nm - t.nb;
-  for (int j = 0; j < kLPL; ++j) {
-    const int64_t S = (nbig + nmid) * c2 + c3 * n1[j] + (c2 - c3) * n2[j] + (C - c2 - c3) * n3[j] + c3 * n4[j];
-    lbp[j] = ceil_div_i64(S, C);
-  }
+  for (int j = 0; j < kLPL; ++j)
+    part[j] = c3 * n1[j] + (c2 - c3) * n2[j] + (C - c2 - c3) * n3[j] + c3 * n4[j];
+}
+
+__device__ __forceinline__ int64_t fin_rad2(const TileArgs &t, int64_t lam, int64_t part) {
+  const int64_t S = (int64_t)(t.nm - t.nf) * (int64_t)(t.C / 2) + part;
+  return ceil_div_i64(S, (int64_t)t.C);
 }
 
 // f_FS1 (1 <= lambda <= 100): with n = w (lambda + 1) and q = floor(n / c),
 // f = q c - w [c divides n].  Evaluated in fp64, exact: n < 2^38, and
 // q = floor((n + 0.5) / c) is computed from (n + 0.5) * (1/c) whose relative
 // error (2^-52) is below the distance 0.5/c of (n + 0.5)/c to an integer;
-// the remainder fma(-q, c, n) is exact.
-__device__ void tile_fs1(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL]) {
+// the remainder fma(-q, c, n) is exact.  part = S = c sum q - sum_{c | n} w.
+__device__ void part_fs1(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
   double l1[kLPL];
-  for (int j = 0; j < kLPL; ++j) {
-    int64_t L = t.lam0 + lane_id() + 64 * j;
-    lam_out[j] = L;
-    l1[j] = (double)((L <= t.hi ? L : t.lo) + 1);
-  }
+  for (int j = 0; j < kLPL; ++j) l1[j] = (double)(lam[j] + 1u);
   const double Cd = (double)t.C;
   const double rc = 1.0 / Cd;
   double Q[kLPL] = {}, D[kLPL] = {};
-#pragma unroll 4
-  for (int i = t.nf; i < t.nz; ++i) {
-    const double w = (double)t.rec[i].w;
+  stream_u32(t.wv, max(t.i0, t.nf), min(t.i1, t.nz), [&](uint32_t wi) {
+    const double w = (double)wi;
     for (int j = 0; j < kLPL; ++j) {
       const double n = w * l1[j];
       const double q = floor((n + 0.5) * rc);
@@ -513,172 +552,134 @@ __device__ void tile_fs1(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[k
       Q[j] += q;
       D[j] += rem == 0.0 ? w : 0.0;
     }
-  }
-  for (int j = 0; j < kLPL; ++j) {
-    const int64_t lam = (int64_t)l1[j] - 1;
-    const int64_t S = (int64_t)Q[j] * (int64_t)t.C - (int64_t)D[j];
-    lbp[j] = ceil_div_i64(S, (int64_t)t.C * lam);
-  }
+  });
+  for (int j = 0; j < kLPL; ++j) part[j] = (int64_t)Q[j] * (int64_t)t.C - (int64_t)D[j];
+}
+
+__device__ __forceinline__ int64_t fin_fs1(const TileArgs &t, int64_t lam, int64_t part) {
+  return ceil_div_i64(part, (int64_t)t.C * lam);
 }
 
 // f_CCM1 (1 <= lambda <= c/2), K = floor(c / lambda):
 //   big 2K - 2 floor((c - w)/lambda), mid K, small 2 floor(w / lambda).
-__device__ void tile_ccm1(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL]) {
-  uint32_t mg[kLPL], sh[kLPL], lmin = 0xffffffffu;
+// part = 2 (sum_small floor(w/lambda) - sum_big floor((c-w)/lambda));
+// S = 2K n_big + K n_mid + part.
+__device__ void part_ccm1(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+  int b0, b1, s0, s1;
+  split_ranges(t, b0, b1, s0, s1);
+  uint32_t mg[kLPL], sh[kLPL];
   for (int j = 0; j < kLPL; ++j) {
-    int64_t L = t.lam0 + lane_id() + 64 * j;
-    lam_out[j] = L;
-    const uint32_t l = (uint32_t)(L <= t.hi ? L : t.lo);
-    const MagicU31 g = magic_u31(l);
+    const MagicU31 g = magic_u31(lam[j]);
     mg[j] = g.m;
     sh[j] = g.s;
-    lmin = min(lmin, l);
   }
-  lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max((int64_t)t.lo, t.lam0));
+  const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
   uint64_t hb[kLPL] = {}, hs[kLPL] = {};
   const int L = chunk_len(((uint64_t)t.C / 2) / lmin + 1);
-  for (int i0 = t.nf; i0 < t.nb;) {
-    const int e = i0 + min(t.nb - i0, L);  // i0 + L could overflow int
-    uint32_t s[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
-      const uint32_t a2 = t.rec[i].a2;
-      for (int j = 0; j < kLPL; ++j) s[j] += div_u31(a2, mg[j], sh[j]);
-    }
-    for (int j = 0; j < kLPL; ++j) hb[j] += s[j];
-    i0 = e;
-  }
-  for (int i0 = t.nm; i0 < t.nz;) {
-    const int e = i0 + min(t.nz - i0, L);  // i0 + L could overflow int
-    uint32_t s[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
-      const uint32_t a2 = t.rec[i].a2;
-      for (int j = 0; j < kLPL; ++j) s[j] += div_u31(a2, mg[j], sh[j]);
-    }
-    for (int j = 0; j < kLPL; ++j) hs[j] += s[j];
-    i0 = e;
-  }
-  const int64_t nbig = t.nb - t.nf, nmid = t.nm - t.nb;
-  for (int j = 0; j < kLPL; ++j) {
-    const int64_t lam = lam_out[j] <= t.hi ? lam_out[j] : t.lo;
-    const int64_t K = (int64_t)t.C / lam;
-    const int64_t S = 2 * K * nbig - 2 * (int64_t)hb[j] + K * nmid + 2 * (int64_t)hs[j];
-    lbp[j] = ceil_div_i64(S, 2 * K);
-  }
+  auto body = [&](uint32_t a, uint32_t *s) {
+    const uint32_t a2 = 2u * a;
+    for (int j = 0; j < kLPL; ++j) s[j] += div_u31(a2, mg[j], sh[j]);
+  };
+  stream_chunked(t.av, b0, b1, L, hb, body);
+  stream_chunked(t.av, s0, s1, L, hs, body);
+  for (int j = 0; j < kLPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
+}
+
+__device__ __forceinline__ int64_t fin_ccm1(const TileArgs &t, int64_t lam, int64_t part) {
+  const int64_t K = (int64_t)t.C / lam;
+  const int64_t S = 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
+  return ceil_div_i64(S, 2 * K);
 }
 
 // f_VB2 (2 <= lambda <= c), h(a) = ceil(a lambda / c) - 1 for a >= 1:
 //   big 2(lambda - 1) - 2 h(c - w), mid lambda - 1, small 2 h(w).
-__device__ void tile_vb2(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL]) {
+// part = 2 (sum_small h(w) - sum_big h(c - w));
+// S = 2 (lambda - 1) n_big + (lambda - 1) n_mid + part.
+__device__ void part_vb2(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+  int b0, b1, s0, s1;
+  split_ranges(t, b0, b1, s0, s1);
   uint32_t rlo[kLPL], rhi[kLPL];
-  uint32_t lmax = 0;
   for (int j = 0; j < kLPL; ++j) {
-    int64_t L = t.lam0 + lane_id() + 64 * j;
-    lam_out[j] = L;
-    const uint32_t l = (uint32_t)(L <= t.hi ? L : t.lo);
-    const uint64_t R = vb2_recip(l, (uint32_t)t.C);
+    const uint64_t R = vb2_recip(lam[j], (uint32_t)t.C);
     rlo[j] = (uint32_t)R;
     rhi[j] = (uint32_t)(R >> 32);
   }
-  lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + kTile - 1));
+  const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + kTile - 1));
   uint64_t hb[kLPL] = {}, hs[kLPL] = {};
   // h(a) <= a lambda / c <= lambda / 2 for a <= c/2
   const int L = chunk_len((uint64_t)lmax / 2 + 1);
-  for (int i0 = t.nf; i0 < t.nb;) {
-    const int e = i0 + min(t.nb - i0, L);  // i0 + L could overflow int
-    uint32_t s[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
-      const uint32_t a = t.rec[i].a;
-      for (int j = 0; j < kLPL; ++j) s[j] += vb2_part(a, rlo[j], rhi[j]);
-    }
-    for (int j = 0; j < kLPL; ++j) hb[j] += s[j];
-    i0 = e;
-  }
-  for (int i0 = t.nm; i0 < t.nz;) {
-    const int e = i0 + min(t.nz - i0, L);  // i0 + L could overflow int
-    uint32_t s[kLPL] = {};
-#pragma unroll 8
-    for (int i = i0; i < e; ++i) {
-      const uint32_t a = t.rec[i].a;
-      for (int j = 0; j < kLPL; ++j) s[j] += vb2_part(a, rlo[j], rhi[j]);
-    }
-    for (int j = 0; j < kLPL; ++j) hs[j] += s[j];
-    i0 = e;
-  }
-  const int64_t nbig = t.nb - t.nf, nmid = t.nm - t.nb;
-  for (int j = 0; j < kLPL; ++j) {
-    const int64_t lam = lam_out[j] <= t.hi ? lam_out[j] : t.lo;
-    const int64_t K = lam - 1;
-    const int64_t S = 2 * K * nbig - 2 * (int64_t)hb[j] + K * nmid + 2 * (int64_t)hs[j];
-    lbp[j] = ceil_div_i64(S, 2 * K);
-  }
+  auto body = [&](uint32_t a, uint32_t *s) {
+    for (int j = 0; j < kLPL; ++j) s[j] += vb2_part(a, rlo[j], rhi[j]);
+  };
+  stream_chunked(t.av, b0, b1, L, hb, body);
+  stream_chunked(t.av, s0, s1, L, hs, body);
+  for (int j = 0; j < kLPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
+}
+
+__device__ __forceinline__ int64_t fin_vb2(const TileArgs &t, int64_t lam, int64_t part) {
+  const int64_t K = lam - 1;
+  const int64_t S = 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
+  return ceil_div_i64(S, 2 * K);
 }
 
 // f_BJ1 (1 <= lambda <= c), p = c mod lambda, q = floor(w / lambda),
 // rem = w - q lambda:  f = q (lambda - p) + max(0, rem - p)
 //                        = q (lambda - p) + (rem - p + |rem - p|) / 2.
-// Per item the lane keeps Q += q and A += |w - (q lambda + p)| = |rem - p|;
-// then  S = (lambda - p) Q + (W - lambda Q - n p + A) / 2  with W = sum w.
-__device__ void tile_bj1(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL]) {
-  uint32_t mg[kLPL], sh[kLPL], lam[kLPL], pm[kLPL];
+// Per item the lane keeps Q += q and A += |w - (q lambda + p)| = |rem - p|.
+// Over items 2S = (lambda - 2p) Q + A + W - n p with W = sum w, n = #items,
+// so part = (lambda - 2p) Q + A and S = (part + W - n p) / 2.
+__device__ void part_bj1(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+  uint32_t mg[kLPL], sh[kLPL], pm[kLPL];
   for (int j = 0; j < kLPL; ++j) {
-    int64_t L = t.lam0 + lane_id() + 64 * j;
-    lam_out[j] = L;
-    const uint32_t l = (uint32_t)(L <= t.hi ? L : t.lo);
-    const MagicU31 g = magic_u31(l);
+    const MagicU31 g = magic_u31(lam[j]);
     mg[j] = g.m;
     sh[j] = g.s;
-    lam[j] = l;
-    pm[j] = (uint32_t)t.C % l;
+    pm[j] = (uint32_t)t.C % lam[j];
   }
-  const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max((int64_t)t.lo, t.lam0));
+  const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
   const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + kTile - 1));
   uint64_t Q[kLPL] = {}, A[kLPL] = {};
   const uint64_t inc = max((uint64_t)((uint32_t)t.C / lmin), (uint64_t)lmax) + 1;
   const int L = chunk_len(inc);
-  for (int i0 = t.nf; i0 < t.nz;) {
-    const int e = i0 + min(t.nz - i0, L);  // i0 + L could overflow int
+  const int a0 = max(t.i0, t.nf), a1 = min(t.i1, t.nz);
+  for (int i0 = a0; i0 < a1;) {
+    const int e = i0 + min(a1 - i0, L);  // i0 + L could overflow int
     uint32_t sq[kLPL] = {}, sa[kLPL] = {};
-    // unrolled by hand: the inline v_sad_u32 keeps the compiler from unrolling
-    int i = i0;
-    for (; i + 4 <= e; i += 4) {
-      ItemRec it[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) it[u] = t.rec[i + u];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        for (int j = 0; j < kLPL; ++j) {
-          const uint32_t q = div_u31(it[u].w2, mg[j], sh[j]);
-          const uint32_t v = q * lam[j] + pm[j];
-          sq[j] += q;
-          sa[j] = sad_u32(it[u].w, v, sa[j]);
-        }
-      }
-    }
-    for (; i < e; ++i) {
-      const ItemRec it = t.rec[i];
+    stream_u32(t.wv, i0, e, [&](uint32_t w) {
+      const uint32_t w2 = 2u * w;
       for (int j = 0; j < kLPL; ++j) {
-        const uint32_t q = div_u31(it.w2, mg[j], sh[j]);
+        const uint32_t q = div_u31(w2, mg[j], sh[j]);
         const uint32_t v = q * lam[j] + pm[j];
         sq[j] += q;
-        sa[j] = sad_u32(it.w, v, sa[j]);
+        sa[j] = sad_u32(w, v, sa[j]);
       }
-    }
+    });
     for (int j = 0; j < kLPL; ++j) {
       Q[j] += sq[j];
       A[j] += sa[j];
     }
     i0 = e;
   }
+  for (int j = 0; j < kLPL; ++j)
+    part[j] = ((int64_t)lam[j] - 2 * (int64_t)pm[j]) * (int64_t)Q[j] + (int64_t)A[j];
+}
+
+__device__ __forceinline__ int64_t fin_bj1(const TileArgs &t, int64_t lam, int64_t part) {
+  const int64_t p = (int64_t)t.C % lam;
   const int64_t n = t.nz - t.nf;
-  for (int j = 0; j < kLPL; ++j) {
-    const int64_t l = lam[j], p = pm[j];
-    const int64_t q = (int64_t)Q[j];
-    const int64_t S = (l - p) * q + (t.sumNZ - l * q - n * p + (int64_t)A[j]) / 2;
-    const int64_t fc = ((int64_t)t.C / l) * (l - p);
-    lbp[j] = ceil_div_i64(S, fc);
+  const int64_t S = (part + t.sumNZ - n * p) / 2;
+  const int64_t fc = ((int64_t)t.C / lam) * (lam - p);
+  return ceil_div_i64(S, fc);
+}
+
+__device__ __forceinline__ int64_t fin_bound(int bound, const TileArgs &t, int64_t lam, int64_t part) {
+  switch (bound) {
+    case kMT: return fin_mt(t, lam, part);
+    case kRAD2: return fin_rad2(t, lam, part);
+    case kFS1: return fin_fs1(t, lam, part);
+    case kCCM1: return fin_ccm1(t, lam, part);
+    case kVB2: return fin_vb2(t, lam, part);
+    default: return fin_bj1(t, lam, part);
   }
 }
 
@@ -725,26 +726,19 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kL
 }
 
 __device__ __forceinline__ void flush_tile(const LaunchDesc &d, int64_t inst, int bound, const TileArgs &t,
-                                           const int64_t lam[kLPL], const int64_t lbp[kLPL], const bool *okp) {
+                                           const int64_t lam[kLPL], const int64_t lbp[kLPL], const bool ok[kLPL],
+                                           bool early) {
   uint64_t key = 0;
-  int64_t best = -1;
-  for (int j = 0; j < kLPL; ++j) {
-    const bool ok = okp ? okp[j] : (lam[j] >= t.lo && lam[j] <= t.hi);
-    if (ok) {
-      const uint64_t kk = pack_key(lbp[j], lam[j]);
-      key = umax64(key, kk);
-      best = max(best, lbp[j]);
-    }
-  }
+  for (int j = 0; j < kLPL; ++j)
+    if (ok[j]) key = umax64(key, pack_key(lbp[j], lam[j]));
   const uint64_t wmax = wave_max_u64(key);
   if (lane_id() == 0 && wmax) {
     atomicMax(&d.keys[inst * kNB + bound], (unsigned long long)wmax);
-    if (as_const(d.plan)[inst].flags & kPlanEarlyExit) {
+    if (early) {
       const int64_t v = (int64_t)(wmax >> 32) + (bound == kL2 ? 0 : t.nf);
       if (v > t.k) d.refuted[inst] = 1;
     }
   }
-  (void)best;
 }
 
 __device__ __forceinline__ int64_t find_entry(const BP_CONST Entry *e, int64_t n, uint64_t task) {
@@ -756,63 +750,104 @@ __device__ __forceinline__ int64_t find_entry(const BP_CONST Entry *e, int64_t n
   return lo;
 }
 
-__global__ __launch_bounds__(64) void k_sweep(const LaunchDesc *__restrict__ dp) {
+// Clears the chunk accumulators, the tile counters and the task counter.
+__global__ __launch_bounds__(256) void k_zero(const LaunchDesc *__restrict__ dp) {
   const LaunchDesc d = *as_const(dp);
-  const BP_CONST Entry *entries = as_const(d.entries);
-  const BP_CONST InstState *states = as_const(d.state);
-  const BP_CONST InstPlan *plans = as_const(d.plan);
-  for (;;) {
-    unsigned long long task = 0;
-    if (lane_id() == 0) task = atomicAdd(d.counter, 1ull);
-    task = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)task) |
-           ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(task >> 32)) << 32);
-    if (task >= (unsigned long long)d.ntasks) return;
-    const int64_t ei = find_entry(entries, d.nentries, task);
-    const BP_CONST Entry &e = entries[ei];
-    const int64_t inst = e.inst;
-    const BP_CONST InstState &st = states[inst];
-    if (st.status != BP_OK) continue;
-    const BP_CONST InstPlan &p = plans[inst];
-    TileArgs t;
-    t.rec = as_const(d.rec + p.ws_off);
-    t.sorted = as_global(d.sorted + p.ws_off);
-    t.pre = as_global(d.pre + p.pre_off);
-    t.lo = p.lo[e.bound];
-    t.hi = st.hiEff[e.bound];
-    t.k = p.k;
-    t.C = p.C;
-    t.r = st.r;
-    t.nf = st.nf;
-    t.nb = st.nb;
-    t.nm = st.nm;
-    t.nz = st.nz;
-    t.sumBig = st.sumBig;
-    t.sumNZ = st.sumNZ;
-    const bool early = (p.flags & kPlanEarlyExit) != 0;
-    const int64_t tile0 = ((int64_t)task - e.task_begin) * e.tpt;
-    const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
-    for (int64_t tl = tile0; tl < tile1; ++tl) {
-      if (early && __builtin_amdgcn_readfirstlane(*(volatile int32_t *)&d.refuted[inst])) break;
-      t.lam0 = e.lam0 + tl * kTile;
-      int64_t lam[kLPL], lbp[kLPL];
-      bool ok[kLPL];
-      if (e.bound == kL2) {
-        // tiles of L2 run over candidate indices, not parameters
-        tile_l2(t, lam, lbp, ok);
-        flush_tile(d, inst, kL2, t, lam, lbp, ok);
-        continue;
-      }
-      if (t.lam0 > t.hi) break;
-      switch (e.bound) {
-        case kMT: tile_mt(t, lam, lbp); break;
-        case kRAD2: tile_rad2(t, lam, lbp); break;
-        case kFS1: tile_fs1(t, lam, lbp); break;
-        case kCCM1: tile_ccm1(t, lam, lbp); break;
-        case kVB2: tile_vb2(t, lam, lbp); break;
-        default: tile_bj1(t, lam, lbp); break;
-      }
-      flush_tile(d, inst, e.bound, t, lam, lbp, nullptr);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < d.acc_len; i += stride) d.acc[i] = 0;
+  for (int64_t i = t0; i < d.cnt_len; i += stride) d.tile_cnt[i] = 0;
+  if (t0 == 0) *d.counter = 0ull;
+}
+
+__device__ void run_task(const LaunchDesc &d, uint64_t task) {
+  const BP_CONST Entry &e = as_const(d.entries)[find_entry(as_const(d.entries), d.nentries, task)];
+  const int64_t inst = e.inst;
+  const BP_CONST InstState &st = as_const(d.state)[inst];
+  if (st.status != BP_OK) return;
+  const BP_CONST InstPlan &p = as_const(d.plan)[inst];
+  const int bound = e.bound;
+  TileArgs t;
+  t.wv = as_const((const uint32_t *)d.sorted + p.ws_off);
+  t.av = as_const((const uint32_t *)d.av + p.ws_off);
+  t.sorted = as_global(d.sorted + p.ws_off);
+  t.pre = as_global(d.pre + p.pre_off);
+  t.lo = p.lo[bound];
+  t.hi = st.hiEff[bound];
+  t.k = p.k;
+  t.C = p.C;
+  t.r = st.r;
+  t.nf = st.nf;
+  t.nb = st.nb;
+  t.nm = st.nm;
+  t.nz = st.nz;
+  t.sumBig = st.sumBig;
+  t.sumNZ = st.sumNZ;
+  const bool early = (p.flags & kPlanEarlyExit) != 0;
+  const int64_t local = (int64_t)task - e.task_begin;
+  const int32_t nch = e.nchunks;
+  const int64_t tile0 = (local / nch) * e.tpt;
+  const int32_t chunk = (int32_t)(local % nch);
+  // this chunk's share of the streamed items [nf, nz)
+  const int64_t span = (int64_t)t.nz - t.nf;
+  t.i0 = t.nf + (int32_t)(span * chunk / nch);
+  t.i1 = t.nf + (int32_t)(span * (chunk + 1) / nch);
+  const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
+  for (int64_t tl = tile0; tl < tile1; ++tl) {
+    if (early && __builtin_amdgcn_readfirstlane(*(volatile int32_t *)&d.refuted[inst])) return;
+    t.lam0 = e.lam0 + tl * kTile;
+    int64_t lam[kLPL], lbp[kLPL];
+    bool ok[kLPL];
+    if (bound == kL2) {
+      // tiles of L2 run over candidate indices, not parameters
+      tile_l2(t, lam, lbp, ok);
+      flush_tile(d, inst, kL2, t, lam, lbp, ok, early);
+      continue;
     }
+    if (t.lam0 > t.hi) return;
+    uint32_t l32[kLPL];
+    tile_lams(t, lam, l32);
+    int64_t part[kLPL];
+    switch (bound) {
+      case kMT: part_mt(t, l32, part); break;
+      case kRAD2: part_rad2(t, l32, part); break;
+      case kFS1: part_fs1(t, l32, part); break;
+      case kCCM1: part_ccm1(t, l32, part); break;
+      case kVB2: part_vb2(t, l32, part); break;
+      default: part_bj1(t, l32, part); break;
+    }
+    for (int j = 0; j < kLPL; ++j) ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
+    if (nch > 1) {
+      // add this chunk's parts; the wave that completes the tile finalises it
+      long long *acc = d.acc + e.acc_base + (tl * kTile);
+      for (int j = 0; j < kLPL; ++j)
+        if (ok[j]) atomicAdd((unsigned long long *)&acc[lane_id() + 64 * j], (unsigned long long)part[j]);
+      __threadfence();
+      uint32_t prev = 0;
+      if (lane_id() == 0) prev = atomicAdd(&d.tile_cnt[e.cnt_base + tl], 1u);
+      prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)prev);
+      if (prev != (uint32_t)(nch - 1)) continue;
+      __threadfence();
+      for (int j = 0; j < kLPL; ++j)
+        part[j] = ok[j] ? (int64_t)atomicAdd((unsigned long long *)&acc[lane_id() + 64 * j], 0ull) : 0;
+    }
+    for (int j = 0; j < kLPL; ++j) lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
+    flush_tile(d, inst, bound, t, lam, lbp, ok, early);
+  }
+}
+
+// Persistent sweep: wave b starts with task b, then takes tasks from one
+// atomic counter (offset by the grid size) until none is left.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep(const LaunchDesc *__restrict__ dp) {
+  const LaunchDesc d = *as_const(dp);
+  uint64_t task = blockIdx.x;
+  while (task < (uint64_t)d.ntasks) {
+    run_task(d, task);
+    unsigned long long nxt = 0;
+    if (lane_id() == 0) nxt = atomicAdd(d.counter, 1ull);
+    nxt = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nxt) |
+          ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(nxt >> 32)) << 32);
+    task = (uint64_t)gridDim.x + nxt;
   }
 }
 
@@ -945,20 +980,18 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int grid_prep_small, int gr
                      prep_smem_small(), s, d_desc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (grid_prep_large > 0) {
-    hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
-                       prep_smem_large(), s, d_desc);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+  hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
+                     prep_smem_large(), s, d_desc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, d_desc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_sweep, dim3(grid_sweep), dim3(64), 0, s, d_desc);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   return hipGetLastError();
 }
 
-// The same four launches with events around the stages (diagnostic timing).
+// The same launches with events around the stages (diagnostic timing).
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
                                  int grid_fin, hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipEventRecord(ev[0], s);
@@ -968,6 +1001,8 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int grid_prep_small, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
                      prep_smem_large(), s, d_desc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_sweep, dim3(grid_sweep), dim3(64), 0, s, d_desc);

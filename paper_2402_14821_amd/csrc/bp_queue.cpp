@@ -60,7 +60,7 @@ struct Slot {
 // sizes, prefix sums and stream records, and its per-instance records.
 size_t request_bytes(int64_t n, int64_t m) {
   const int64_t r = n + m;
-  return (size_t)(4 * r + 4 * r + 8 * (r + 1) + (int64_t)sizeof(ItemRec) * r) + sizeof(InstPlan) +
+  return (size_t)(4 * r + 4 * r + 8 * (r + 1) + 4 * r) + sizeof(InstPlan) +
          sizeof(InstState) + kNB * 8 + sizeof(bp_bounds) + 7 * sizeof(Entry) + 64;
 }
 
