@@ -111,6 +111,25 @@ typedef struct bp_ctx bp_ctx;
 bp_status bp_ctx_create(int device, bp_ctx **out);
 bp_status bp_ctx_destroy(bp_ctx *ctx);
 
+/* Launch shape of the parameter sweep, held per context.  Results do not
+ * depend on it; only the speed does.
+ *   lanes_params   parameters per lane in a sweep tile: 1, 2 or 4 (a tile is
+ *                  64 x lanes_params consecutive parameters of one bound);
+ *   waves_per_cu   resident waves of the persistent sweep kernel per compute
+ *                  unit: 4 .. 32;
+ *   tasks_per_wave tasks per resident wave the planner aims at; tiles dearer
+ *                  than a task are split into item chunks: 1 .. 64;
+ *   min_chunk      fewest items in one chunk of a split tile: 64 .. 65536. */
+typedef struct bp_tuning {
+  int32_t lanes_params;
+  int32_t waves_per_cu;
+  int32_t tasks_per_wave;
+  int32_t min_chunk;
+} bp_tuning;
+bp_status bp_ctx_get_tuning(bp_ctx *ctx, bp_tuning *out);
+bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning);
+
+
 /* Stage timing for diagnostics.  With enable = 1 the context launches the
  * pipeline kernels one by one instead of replaying its graph and records HIP
  * events around each on the call's stream; bp_ctx_stage_times waits for the
@@ -185,6 +204,14 @@ bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const in
 /* Batched feasibility check of reduced instances with k[i] bins each;
  * flags as in bp_feasible.  verdict[count], lb[count]. */
 bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb);
+
+/* Autotuner: times the sweep of this batch (host pointers, as
+ * bp_lower_bounds_batch) under candidate shapes, one knob at a time starting
+ * from the context's current shape, reps runs each (best of), and leaves the
+ * fastest shape set on the context.  *best and *best_ms (sweep milliseconds)
+ * may be NULL. */
+bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, int32_t reps,
+                            bp_tuning *best, double *best_ms);
 
 /* ---- served checks (continuous batching) -------------------------------- */
 

@@ -58,6 +58,10 @@ class bp_result(ctypes.Structure):
                 ("bounds", bp_bounds)]
 
 
+class bp_tuning(ctypes.Structure):
+    _fields_ = [("lanes_params", _i32), ("waves_per_cu", _i32), ("tasks_per_wave", _i32), ("min_chunk", _i32)]
+
+
 class bp_queue_stats(ctypes.Structure):
     _fields_ = [("submitted", _u64), ("completed", _u64), ("rejected", _u64), ("batches", _u64),
                 ("in_flight", _u64), ("bytes_in_use", _u64), ("bytes_peak", _u64), ("budget", _u64),
@@ -94,6 +98,10 @@ _SIGNATURES = {
     "bp_feasible": ([_VP, _i32, _i32, _P32, _P32, _i64, _u32, _P32, _P64, ctypes.POINTER(bp_bounds)], _i32),
     "bp_feasible_dev": ([_VP, _i32, _i32, _VP, _VP, _i64, _u32, _VP, _VP], _i32),
     "bp_ctx_set_timing": ([_VP, _i32], _i32),
+    "bp_ctx_get_tuning": ([_VP, ctypes.POINTER(bp_tuning)], _i32),
+    "bp_ctx_set_tuning": ([_VP, ctypes.POINTER(bp_tuning)], _i32),
+    "bp_autotune_batch": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _i32,
+                           ctypes.POINTER(bp_tuning), ctypes.POINTER(ctypes.c_double)], _i32),
     "bp_ctx_stage_times": ([_VP, ctypes.POINTER(ctypes.c_double)], _i32),
     "bp_lower_bounds_batch": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _VP], _i32),
     "bp_lower_bounds_batch_dev": ([_VP, ctypes.POINTER(bp_batch), _VP, ctypes.POINTER(bp_sweep), _VP, _VP], _i32),
@@ -286,6 +294,27 @@ class Context:
 
     def set_timing(self, enable: bool):
         _check(self._lib.bp_ctx_set_timing(self.handle, int(enable)))
+
+    def get_tuning(self) -> dict:
+        t = bp_tuning()
+        _check(self._lib.bp_ctx_get_tuning(self.handle, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in bp_tuning._fields_}
+
+    def set_tuning(self, lanes_params: int, waves_per_cu: int, tasks_per_wave: int, min_chunk: int):
+        t = bp_tuning(lanes_params, waves_per_cu, tasks_per_wave, min_chunk)
+        _check(self._lib.bp_ctx_set_tuning(self.handle, ctypes.byref(t)))
+
+    def autotune_batch(self, Cs, ks, items_list, reps: int = 2, sweeps=None):
+        """Pick the fastest sweep shape for this batch; returns (tuning dict, sweep ms)."""
+        b = _Batch(Cs, ks, items_list)
+        sw = None
+        if sweeps is not None:
+            arr = (bp_sweep * len(sweeps))(*sweeps)
+            sw = ctypes.cast(arr, ctypes.POINTER(bp_sweep))
+        t = bp_tuning()
+        ms = ctypes.c_double(0)
+        _check(self._lib.bp_autotune_batch(self.handle, ctypes.byref(b.s), sw, reps, ctypes.byref(t), ctypes.byref(ms)))
+        return {f: getattr(t, f) for f, _ in bp_tuning._fields_}, ms.value
 
     def stage_times(self):
         """Durations (ms) of prep, sweep and finalize of the last call (timing mode)."""

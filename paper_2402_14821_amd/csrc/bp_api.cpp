@@ -168,7 +168,7 @@ bp_status Ctx::init(int dev) {
   for (hipEvent_t &e : tev) HIP_TRY(hipEventCreate(&e));
   bp_status st = counter_buf.reserve(256);
   if (st) return st;
-  grid_sweep = num_cu * sweep_waves_per_cu;
+  apply_tuning();
   grid_prep_small = num_cu * 2;
   grid_prep_large = std::max(1, num_cu / 4);
   grid_fin = 64;
@@ -199,11 +199,22 @@ void Ctx::destroy() {
   stream = nullptr;
 }
 
-// Captures the four-kernel pipeline once; every call replays it.
+void Ctx::apply_tuning() { grid_sweep = num_cu * tune.waves_per_cu; }
+
+// Captures the pipeline once per shape (parameters per lane, sweep grid);
+// every call replays it.
 bp_status Ctx::ensure_graph(const LaunchDesc *d_desc) {
-  if (!use_graph || graph_exec) return BP_OK;
+  if (!use_graph) return BP_OK;
+  if (graph_exec && (graph_lpl != tune.lanes_params || graph_grid != grid_sweep)) {
+    (void)hipGraphExecDestroy(graph_exec);
+    (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+  if (graph_exec) return BP_OK;
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_pipeline(d_desc, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, stream);
+  hipError_t le = launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
+                                  stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
   if (le != hipSuccess) {
@@ -219,6 +230,8 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc) {
   }
   graph = g;
   graph_exec = ex;
+  graph_lpl = tune.lanes_params;
+  graph_grid = grid_sweep;
   return BP_OK;
 }
 
@@ -238,6 +251,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   std::vector<int64_t> rcap_v;
   ent.reserve((size_t)count * 7);
   double total = 0;
+  const int64_t tile = 64 * (int64_t)tune.lanes_params;
   for (int64_t i = 0; i < count; ++i) {
     const PlanIn &q = pin[i];
     InstPlan &p = pl[i];
@@ -274,13 +288,13 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       if (b == kL2) {
         const int64_t cand = 2 * rcap + 1;
         e.lam0 = 0;
-        e.ntiles = (cand + kTile - 1) / kTile;
-        tc = (double)kTile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0);
+        e.ntiles = (cand + tile - 1) / tile;
+        tc = (double)tile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0);
       } else {
         const int64_t nl = q.hi[b] - q.lo[b] + 1;
         e.lam0 = q.lo[b];
-        e.ntiles = (nl + kTile - 1) / kTile;
-        tc = (double)kTile * ((double)rcap * unit_cost(b) + 60.0);
+        e.ntiles = (nl + tile - 1) / tile;
+        tc = (double)tile * ((double)rcap * unit_cost(b) + 60.0);
       }
       total += tc * (double)e.ntiles;
       ent.push_back(e);
@@ -290,11 +304,11 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   }
   ws_items = ws;
   pre_items = pre;
-  // Task size: about 8 tasks per resident wave over the whole launch.  A tile
-  // cheaper than that is grouped with its neighbours; a dearer one is split
-  // into item chunks of at least kMinChunk items.
-  constexpr int64_t kMinChunk = 384;
-  const double target = std::max(1.0, total / (8.0 * (double)grid_sweep));
+  // Task size: about tasks_per_wave tasks per resident wave over the whole
+  // launch.  A tile cheaper than that is grouped with its neighbours; a dearer
+  // one is split into item chunks of at least min_chunk items.
+  const int64_t min_chunk = tune.min_chunk;
+  const double target = std::max(1.0, total / ((double)tune.tasks_per_wave * (double)grid_sweep));
   std::vector<double> task_cost(ent.size());
   int64_t acc = 0, cnt = 0;
   for (size_t j = 0; j < ent.size(); ++j) {
@@ -307,7 +321,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       e.nchunks = 1;
       task_cost[j] = tc * tpt;
     } else {
-      const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / kMinChunk);
+      const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / min_chunk);
       const int64_t want = (int64_t)std::ceil(tc / target);
       e.nchunks = (int32_t)std::min<int64_t>(std::min<int64_t>(want, maxch), 64);
       e.tpt = 1;
@@ -316,7 +330,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
     if (e.nchunks > 1) {
       e.acc_base = acc;
       e.cnt_base = cnt;
-      acc += e.ntiles * kTile;
+      acc += e.ntiles * tile;
       cnt += e.ntiles;
     }
   }
@@ -396,12 +410,13 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   HIP_TRY(hipEventRecord(staged, s));
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
   if (timing) {
-    HIP_TRY(launch_pipeline_timed(d_desc, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, s, tev));
+    HIP_TRY(launch_pipeline_timed(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
+                                  s, tev));
   } else if (use_graph) {
     if ((st = ensure_graph(d_desc))) return st;
     HIP_TRY(hipGraphLaunch(graph_exec, s));
   } else {
-    HIP_TRY(launch_pipeline(d_desc, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, s));
+    HIP_TRY(launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, s));
   }
   return BP_OK;
 }
@@ -476,6 +491,36 @@ bp_status bp_ctx_set_timing(bp_ctx *ctx, int32_t enable) {
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
   c->timing = enable != 0;
+  return BP_OK;
+}
+
+static bp_status check_tuning(const bp_tuning *t) {
+  if (!t) return fail(BP_ERR_ARG, "tuning is NULL");
+  if (t->lanes_params != 1 && t->lanes_params != 2 && t->lanes_params != 4)
+    return fail(BP_ERR_ARG, "lanes_params must be 1, 2 or 4");
+  if (t->waves_per_cu < 4 || t->waves_per_cu > 32) return fail(BP_ERR_ARG, "waves_per_cu outside [4, 32]");
+  if (t->tasks_per_wave < 1 || t->tasks_per_wave > 64) return fail(BP_ERR_ARG, "tasks_per_wave outside [1, 64]");
+  if (t->min_chunk < 64 || t->min_chunk > 65536) return fail(BP_ERR_ARG, "min_chunk outside [64, 65536]");
+  return BP_OK;
+}
+
+bp_status bp_ctx_get_tuning(bp_ctx *ctx, bp_tuning *out) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if (!out) return fail(BP_ERR_ARG, "out is NULL");
+  *out = c->tune;
+  return BP_OK;
+}
+
+bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((st = check_tuning(tuning))) return st;
+  if ((st = c->wait_staging())) return st;
+  c->tune = *tuning;
+  c->apply_tuning();
   return BP_OK;
 }
 
@@ -788,6 +833,74 @@ bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, 
     if (verdict) verdict[i] = o[i].verdict;
     if (lb) lb[i] = o[i].lb;
   }
+  return BP_OK;
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, int32_t reps,
+                            bp_tuning *best, double *best_ms) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((st = check_batch(batch))) return st;
+  if (batch->count == 0 || !batch->items) return fail(BP_ERR_ARG, "empty batch");
+  if (reps < 1) reps = 1;
+  std::vector<PlanIn> pin;
+  if ((st = batch_plan_in(batch, per_inst, false, pin))) return st;
+  std::vector<const int32_t *> a(batch->count), b(batch->count, nullptr);
+  for (int32_t i = 0; i < batch->count; ++i) {
+    a[i] = batch->items + batch->off[i];
+    if ((st = host_validate_items(batch->C[i], a[i], pin[i].n_in))) return st;
+  }
+  const bool was_timing = c->timing;
+  c->timing = true;
+  std::vector<bp_bounds> out(batch->count);
+  auto measure = [&](const bp_tuning &t, double *ms) -> bp_status {
+    c->tune = t;
+    c->apply_tuning();
+    double bestv = 1e300;
+    for (int32_t r = 0; r < reps; ++r) {
+      std::vector<PlanIn> p2 = pin;
+      bp_status s2 = launch_host_batch(c, p2, a, b);
+      if (s2) return s2;
+      if ((s2 = collect_host_batch(c, batch->count, out.data(), true))) return s2;
+      float t_ms = 0;
+      hipError_t e = hipEventElapsedTime(&t_ms, c->tev[1], c->tev[2]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      bestv = std::min(bestv, (double)t_ms);
+    }
+    *ms = bestv;
+    return BP_OK;
+  };
+  bp_tuning cur = c->tune;
+  double cur_ms = 0;
+  if ((st = measure(cur, &cur_ms))) { c->timing = was_timing; return st; }
+  const int32_t lpls[] = {1, 2, 4};
+  const int32_t waves[] = {8, 16, 24, 32};
+  const int32_t tasks[] = {1, 2, 4, 8, 16};
+  const int32_t chunks[] = {128, 384, 1024, 4096};
+  for (int knob = 0; knob < 4; ++knob) {
+    const int32_t *vals = knob == 0 ? lpls : knob == 1 ? waves : knob == 2 ? tasks : chunks;
+    const int nv = knob == 0 ? 3 : knob == 1 ? 4 : knob == 2 ? 5 : 4;
+    for (int v = 0; v < nv; ++v) {
+      bp_tuning t = cur;
+      int32_t *field = knob == 0 ? &t.lanes_params : knob == 1 ? &t.waves_per_cu : knob == 2 ? &t.tasks_per_wave : &t.min_chunk;
+      if (*field == vals[v]) continue;
+      *field = vals[v];
+      double ms = 0;
+      if ((st = measure(t, &ms))) { c->timing = was_timing; return st; }
+      if (ms < cur_ms) {
+        cur_ms = ms;
+        cur = t;
+      }
+    }
+  }
+  c->timing = was_timing;
+  c->tune = cur;
+  c->apply_tuning();
+  if (best) *best = cur;
+  if (best_ms) *best_ms = cur_ms;
   return BP_OK;
 }
 

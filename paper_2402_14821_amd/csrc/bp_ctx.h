@@ -17,10 +17,10 @@ void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]);
 
 // kernels (bp_kernels.hip)
 hipError_t set_kernel_attrs();
-hipError_t launch_pipeline(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
+hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
                            int grid_fin, hipStream_t s);
-hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                                 int grid_fin, hipStream_t s, hipEvent_t ev[4]);
+hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
+                                 int grid_sweep, int grid_fin, hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
                          int64_t n, unsigned long long *loads, int32_t *out, int64_t *out_r, int32_t *out_residual,
                          int32_t *bad, hipStream_t s);
@@ -59,8 +59,9 @@ struct Ctx {
   hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  int sweep_waves_per_cu = 32;
+  bp_tuning tune = {2, 32, 8, 384};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_fin = 0;
+  int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
   int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, cnt_len = 0;
   std::vector<InstPlan> plan_vec;
   std::vector<Entry> entry_vec;
@@ -76,6 +77,7 @@ struct Ctx {
   bp_status run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len, const int32_t *in_dev,
                 bp_bounds *out_dev, hipStream_t s);
   bp_status wait_staging();
+  void apply_tuning();
 };
 
 bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,

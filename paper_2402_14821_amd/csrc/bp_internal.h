@@ -15,8 +15,6 @@ namespace bpi {
 enum : int { kL1 = 0, kL2, kMT, kRAD2, kFS1, kCCM1, kVB2, kBJ1, kNB };
 
 constexpr int kWave = 64;
-constexpr int kLPL = 2;                 // parameters per lane in a sweep tile
-constexpr int kTile = kWave * kLPL;     // parameters per sweep tile
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
 constexpr int kLargeThreads = 512;      // prep block for one large instance
@@ -62,7 +60,7 @@ struct InstState {
 };
 
 // One (instance, bound) entry of the sweep schedule.  Its parameter range is
-// cut into tiles of kTile parameters.  A task is either tpt consecutive tiles
+// cut into tiles of 64 x (parameters per lane) parameters.  A task is either tpt consecutive tiles
 // over all items (nchunks = 1) or one of nchunks item chunks of one tile.
 struct Entry {
   int64_t task_begin;   // prefix of task counts over entries (LPT order)

@@ -7,7 +7,7 @@
 //       (DPP wave scans), class boundaries and the class-sorted item stream.
 //   k_sweep  persistent: waves pull tasks (instance, bound, run of parameter
 //       tiles) from one atomic counter, in longest-first order.  A tile gives
-//       each lane kLPL parameters; the wave reads the item stream with scalar
+//       each lane LPL parameters; the wave reads the item stream with scalar
 //       loads (every lane uses the same item) and accumulates
 //       sum_w f(w, lambda) per lane (Alg. 2's inner loop, Alg. 4's per-thread
 //       loop), then ceil(sum / f(c, lambda)) and a DPP wave max of packed
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
 }
 
 // ---------------------------------------------------------------------------
-// Sweep tiles.  Each lane holds kLPL parameters lam = lam0 + lane + 64 j;
+// Sweep tiles.  Each lane holds LPL parameters lam = lam0 + lane + 64 j;
 // lanes past the end of the range compute with lam = lo and are dropped.
 //
 // A tile's items may be split into chunks run by different waves.  Every
@@ -441,20 +441,21 @@ __device__ __forceinline__ void stream_u32(const BP_CONST uint32_t *p, int i0, i
 
 // Sums over [i0, i1) in segments of at most L items so that 32-bit partial
 // sums cannot wrap; flushes each segment into the 64-bit totals.
-template <typename F>
+template <int LPL, typename F>
 __device__ __forceinline__ void stream_chunked(const BP_CONST uint32_t *p, int i0, int i1, int L,
-                                               uint64_t tot[kLPL], F &&f) {
+                                               uint64_t tot[LPL], F &&f) {
   for (int a = i0; a < i1;) {
     const int e = a + min(i1 - a, L);  // a + L could overflow int
-    uint32_t s[kLPL] = {};
+    uint32_t s[LPL] = {};
     stream_u32(p, a, e, [&](uint32_t x) { f(x, s); });
-    for (int j = 0; j < kLPL; ++j) tot[j] += s[j];
+    for (int j = 0; j < LPL; ++j) tot[j] += s[j];
     a = e;
   }
 }
 
-__device__ __forceinline__ void tile_lams(const TileArgs &t, int64_t lam_out[kLPL], uint32_t lam[kLPL]) {
-  for (int j = 0; j < kLPL; ++j) {
+template <int LPL>
+__device__ __forceinline__ void tile_lams(const TileArgs &t, int64_t lam_out[LPL], uint32_t lam[LPL]) {
+  for (int j = 0; j < LPL; ++j) {
     const int64_t L = t.lam0 + lane_id() + 64 * j;
     lam_out[j] = L;
     lam[j] = (uint32_t)(L <= t.hi ? L : t.lo);
@@ -472,20 +473,21 @@ __device__ __forceinline__ void split_ranges(const TileArgs &t, int &b0, int &b1
 // f_MT.  part = sum_big [c - w < lambda] (c - w) + sum_small [w >= lambda] w;
 // S = sum_big w + n_mid c/2 + part.  The conditions are sign bits of 32-bit
 // differences (all operands < 2^31), turned into masks: no compare, no select.
-__device__ void part_mt(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+template <int LPL>
+__device__ void part_mt(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
   int b0, b1, s0, s1;
   split_ranges(t, b0, b1, s0, s1);
-  uint32_t lm1[kLPL];
-  for (int j = 0; j < kLPL; ++j) lm1[j] = lam[j] - 1u;  // lambda - 1 (wraps to -1 for lambda = 0)
-  uint64_t acc[kLPL] = {};
+  uint32_t lm1[LPL];
+  for (int j = 0; j < LPL; ++j) lm1[j] = lam[j] - 1u;  // lambda - 1 (wraps to -1 for lambda = 0)
+  uint64_t acc[LPL] = {};
   const int L = chunk_len((uint64_t)t.C / 2 + 1);
-  stream_chunked(t.av, b0, b1, L, acc, [&](uint32_t a, uint32_t *s) {
-    for (int j = 0; j < kLPL; ++j) s[j] += (uint32_t)((int32_t)(a - lam[j]) >> 31) & a;
+  stream_chunked<LPL>(t.av, b0, b1, L, acc, [&](uint32_t a, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] += (uint32_t)((int32_t)(a - lam[j]) >> 31) & a;
   });
-  stream_chunked(t.wv, s0, s1, L, acc, [&](uint32_t w, uint32_t *s) {
-    for (int j = 0; j < kLPL; ++j) s[j] += (uint32_t)((int32_t)(lm1[j] - w) >> 31) & w;
+  stream_chunked<LPL>(t.wv, s0, s1, L, acc, [&](uint32_t w, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] += (uint32_t)((int32_t)(lm1[j] - w) >> 31) & w;
   });
-  for (int j = 0; j < kLPL; ++j) part[j] = (int64_t)acc[j];
+  for (int j = 0; j < LPL; ++j) part[j] = (int64_t)acc[j];
 }
 
 __device__ __forceinline__ int64_t fin_mt(const TileArgs &t, int64_t lam, int64_t part) {
@@ -498,32 +500,33 @@ __device__ __forceinline__ int64_t fin_mt(const TileArgs &t, int64_t lam, int64_
 //   big:   c2 + (c - c2 - c3) [w >= 2 lambda] + c3 [w > c - lambda]
 //   mid:   c2
 // part = the count terms; S = (n_big + n_mid) c2 + part.
-__device__ void part_rad2(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+template <int LPL>
+__device__ void part_rad2(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
   int b0, b1, s0, s1;
   split_ranges(t, b0, b1, s0, s1);
   // w >= t  <=>  (t - 1) - w < 0: count the sign bits (thresholds <= c, sizes < 2^31)
-  uint32_t u1[kLPL], u2[kLPL], u3[kLPL], u4[kLPL];
-  for (int j = 0; j < kLPL; ++j) {
+  uint32_t u1[LPL], u2[LPL], u3[LPL], u4[LPL];
+  for (int j = 0; j < LPL; ++j) {
     u1[j] = lam[j] - 1u;                        // w >= lambda
     u2[j] = (uint32_t)t.C - 2u * lam[j];        // w >= c - 2 lambda + 1
     u3[j] = 2u * lam[j] - 1u;                   // w >= 2 lambda
     u4[j] = (uint32_t)t.C - lam[j];             // w >= c - lambda + 1
   }
-  uint32_t n1[kLPL] = {}, n2[kLPL] = {}, n3[kLPL] = {}, n4[kLPL] = {};
+  uint32_t n1[LPL] = {}, n2[LPL] = {}, n3[LPL] = {}, n4[LPL] = {};
   stream_u32(t.wv, s0, s1, [&](uint32_t w) {
-    for (int j = 0; j < kLPL; ++j) {
+    for (int j = 0; j < LPL; ++j) {
       n1[j] += (u1[j] - w) >> 31;
       n2[j] += (u2[j] - w) >> 31;
     }
   });
   stream_u32(t.wv, b0, b1, [&](uint32_t w) {
-    for (int j = 0; j < kLPL; ++j) {
+    for (int j = 0; j < LPL; ++j) {
       n3[j] += (u3[j] - w) >> 31;
       n4[j] += (u4[j] - w) >> 31;
     }
   });
   const int64_t C = t.C, c3 = C / 3, c2 = C / 2;
-  for (int j = 0; j < kLPL; ++j)
+  for (int j = 0; j < LPL; ++j)
     part[j] = c3 * n1[j] + (c2 - c3) * n2[j] + (C - c2 - c3) * n3[j] + c3 * n4[j];
 }
 
@@ -537,15 +540,16 @@ __device__ __forceinline__ int64_t fin_rad2(const TileArgs &t, int64_t lam, int6
 // q = floor((n + 0.5) / c) is computed from (n + 0.5) * (1/c) whose relative
 // error (2^-52) is below the distance 0.5/c of (n + 0.5)/c to an integer;
 // the remainder fma(-q, c, n) is exact.  part = S = c sum q - sum_{c | n} w.
-__device__ void part_fs1(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
-  double l1[kLPL];
-  for (int j = 0; j < kLPL; ++j) l1[j] = (double)(lam[j] + 1u);
+template <int LPL>
+__device__ void part_fs1(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
+  double l1[LPL];
+  for (int j = 0; j < LPL; ++j) l1[j] = (double)(lam[j] + 1u);
   const double Cd = (double)t.C;
   const double rc = 1.0 / Cd;
-  double Q[kLPL] = {}, D[kLPL] = {};
+  double Q[LPL] = {}, D[LPL] = {};
   stream_u32(t.wv, max(t.i0, t.nf), min(t.i1, t.nz), [&](uint32_t wi) {
     const double w = (double)wi;
-    for (int j = 0; j < kLPL; ++j) {
+    for (int j = 0; j < LPL; ++j) {
       const double n = w * l1[j];
       const double q = floor((n + 0.5) * rc);
       const double rem = fma(-q, Cd, n);
@@ -553,7 +557,7 @@ __device__ void part_fs1(const TileArgs &t, const uint32_t lam[kLPL], int64_t pa
       D[j] += rem == 0.0 ? w : 0.0;
     }
   });
-  for (int j = 0; j < kLPL; ++j) part[j] = (int64_t)Q[j] * (int64_t)t.C - (int64_t)D[j];
+  for (int j = 0; j < LPL; ++j) part[j] = (int64_t)Q[j] * (int64_t)t.C - (int64_t)D[j];
 }
 
 __device__ __forceinline__ int64_t fin_fs1(const TileArgs &t, int64_t lam, int64_t part) {
@@ -564,25 +568,26 @@ __device__ __forceinline__ int64_t fin_fs1(const TileArgs &t, int64_t lam, int64
 //   big 2K - 2 floor((c - w)/lambda), mid K, small 2 floor(w / lambda).
 // part = 2 (sum_small floor(w/lambda) - sum_big floor((c-w)/lambda));
 // S = 2K n_big + K n_mid + part.
-__device__ void part_ccm1(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+template <int LPL>
+__device__ void part_ccm1(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
   int b0, b1, s0, s1;
   split_ranges(t, b0, b1, s0, s1);
-  uint32_t mg[kLPL], sh[kLPL];
-  for (int j = 0; j < kLPL; ++j) {
+  uint32_t mg[LPL], sh[LPL];
+  for (int j = 0; j < LPL; ++j) {
     const MagicU31 g = magic_u31(lam[j]);
     mg[j] = g.m;
     sh[j] = g.s;
   }
   const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
-  uint64_t hb[kLPL] = {}, hs[kLPL] = {};
+  uint64_t hb[LPL] = {}, hs[LPL] = {};
   const int L = chunk_len(((uint64_t)t.C / 2) / lmin + 1);
   auto body = [&](uint32_t a, uint32_t *s) {
     const uint32_t a2 = 2u * a;
-    for (int j = 0; j < kLPL; ++j) s[j] += div_u31(a2, mg[j], sh[j]);
+    for (int j = 0; j < LPL; ++j) s[j] += div_u31(a2, mg[j], sh[j]);
   };
-  stream_chunked(t.av, b0, b1, L, hb, body);
-  stream_chunked(t.av, s0, s1, L, hs, body);
-  for (int j = 0; j < kLPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
+  stream_chunked<LPL>(t.av, b0, b1, L, hb, body);
+  stream_chunked<LPL>(t.av, s0, s1, L, hs, body);
+  for (int j = 0; j < LPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
 }
 
 __device__ __forceinline__ int64_t fin_ccm1(const TileArgs &t, int64_t lam, int64_t part) {
@@ -595,25 +600,26 @@ __device__ __forceinline__ int64_t fin_ccm1(const TileArgs &t, int64_t lam, int6
 //   big 2(lambda - 1) - 2 h(c - w), mid lambda - 1, small 2 h(w).
 // part = 2 (sum_small h(w) - sum_big h(c - w));
 // S = 2 (lambda - 1) n_big + (lambda - 1) n_mid + part.
-__device__ void part_vb2(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
+template <int LPL>
+__device__ void part_vb2(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
   int b0, b1, s0, s1;
   split_ranges(t, b0, b1, s0, s1);
-  uint32_t rlo[kLPL], rhi[kLPL];
-  for (int j = 0; j < kLPL; ++j) {
+  uint32_t rlo[LPL], rhi[LPL];
+  for (int j = 0; j < LPL; ++j) {
     const uint64_t R = vb2_recip(lam[j], (uint32_t)t.C);
     rlo[j] = (uint32_t)R;
     rhi[j] = (uint32_t)(R >> 32);
   }
-  const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + kTile - 1));
-  uint64_t hb[kLPL] = {}, hs[kLPL] = {};
+  const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + (64 * LPL) - 1));
+  uint64_t hb[LPL] = {}, hs[LPL] = {};
   // h(a) <= a lambda / c <= lambda / 2 for a <= c/2
   const int L = chunk_len((uint64_t)lmax / 2 + 1);
   auto body = [&](uint32_t a, uint32_t *s) {
-    for (int j = 0; j < kLPL; ++j) s[j] += vb2_part(a, rlo[j], rhi[j]);
+    for (int j = 0; j < LPL; ++j) s[j] += vb2_part(a, rlo[j], rhi[j]);
   };
-  stream_chunked(t.av, b0, b1, L, hb, body);
-  stream_chunked(t.av, s0, s1, L, hs, body);
-  for (int j = 0; j < kLPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
+  stream_chunked<LPL>(t.av, b0, b1, L, hb, body);
+  stream_chunked<LPL>(t.av, s0, s1, L, hs, body);
+  for (int j = 0; j < LPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
 }
 
 __device__ __forceinline__ int64_t fin_vb2(const TileArgs &t, int64_t lam, int64_t part) {
@@ -628,39 +634,40 @@ __device__ __forceinline__ int64_t fin_vb2(const TileArgs &t, int64_t lam, int64
 // Per item the lane keeps Q += q and A += |w - (q lambda + p)| = |rem - p|.
 // Over items 2S = (lambda - 2p) Q + A + W - n p with W = sum w, n = #items,
 // so part = (lambda - 2p) Q + A and S = (part + W - n p) / 2.
-__device__ void part_bj1(const TileArgs &t, const uint32_t lam[kLPL], int64_t part[kLPL]) {
-  uint32_t mg[kLPL], sh[kLPL], pm[kLPL];
-  for (int j = 0; j < kLPL; ++j) {
+template <int LPL>
+__device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
+  uint32_t mg[LPL], sh[LPL], pm[LPL];
+  for (int j = 0; j < LPL; ++j) {
     const MagicU31 g = magic_u31(lam[j]);
     mg[j] = g.m;
     sh[j] = g.s;
     pm[j] = (uint32_t)t.C % lam[j];
   }
   const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
-  const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + kTile - 1));
-  uint64_t Q[kLPL] = {}, A[kLPL] = {};
+  const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + (64 * LPL) - 1));
+  uint64_t Q[LPL] = {}, A[LPL] = {};
   const uint64_t inc = max((uint64_t)((uint32_t)t.C / lmin), (uint64_t)lmax) + 1;
   const int L = chunk_len(inc);
   const int a0 = max(t.i0, t.nf), a1 = min(t.i1, t.nz);
   for (int i0 = a0; i0 < a1;) {
     const int e = i0 + min(a1 - i0, L);  // i0 + L could overflow int
-    uint32_t sq[kLPL] = {}, sa[kLPL] = {};
+    uint32_t sq[LPL] = {}, sa[LPL] = {};
     stream_u32(t.wv, i0, e, [&](uint32_t w) {
       const uint32_t w2 = 2u * w;
-      for (int j = 0; j < kLPL; ++j) {
+      for (int j = 0; j < LPL; ++j) {
         const uint32_t q = div_u31(w2, mg[j], sh[j]);
         const uint32_t v = q * lam[j] + pm[j];
         sq[j] += q;
         sa[j] = sad_u32(w, v, sa[j]);
       }
     });
-    for (int j = 0; j < kLPL; ++j) {
+    for (int j = 0; j < LPL; ++j) {
       Q[j] += sq[j];
       A[j] += sa[j];
     }
     i0 = e;
   }
-  for (int j = 0; j < kLPL; ++j)
+  for (int j = 0; j < LPL; ++j)
     part[j] = ((int64_t)lam[j] - 2 * (int64_t)pm[j]) * (int64_t)Q[j] + (int64_t)A[j];
 }
 
@@ -700,10 +707,11 @@ __device__ __forceinline__ int32_t first_le(const BP_GLOBAL int32_t *s, int32_t 
 //   n1 = #{w > c - lambda}, n2 = nbig - n1, sum W2 = pre[nbig] - pre[n1],
 //   W3 = {lambda <= w <= c/2} = sorted[nbig, j3) with j3 = #{w >= lambda},
 //   L2(lambda) = nbig + max(0, ceil((sum W3 - (c n2 - sum W2)) / c)).
-__device__ void tile_l2(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kLPL], bool ok[kLPL]) {
+template <int LPL>
+__device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL], bool ok[LPL]) {
   const int64_t C = t.C;
   const int32_t nbig = t.nb;  // includes the items of size c
-  for (int j = 0; j < kLPL; ++j) {
+  for (int j = 0; j < LPL; ++j) {
     const int64_t cidx = t.lam0 + lane_id() + 64 * j;
     int64_t lam = -1;
     if (cidx == 0) lam = t.lo;
@@ -725,11 +733,12 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[kLPL], int64_t lbp[kL
   }
 }
 
+template <int LPL>
 __device__ __forceinline__ void flush_tile(const LaunchDesc &d, int64_t inst, int bound, const TileArgs &t,
-                                           const int64_t lam[kLPL], const int64_t lbp[kLPL], const bool ok[kLPL],
+                                           const int64_t lam[LPL], const int64_t lbp[LPL], const bool ok[LPL],
                                            bool early) {
   uint64_t key = 0;
-  for (int j = 0; j < kLPL; ++j)
+  for (int j = 0; j < LPL; ++j)
     if (ok[j]) key = umax64(key, pack_key(lbp[j], lam[j]));
   const uint64_t wmax = wave_max_u64(key);
   if (lane_id() == 0 && wmax) {
@@ -760,6 +769,7 @@ __global__ __launch_bounds__(256) void k_zero(const LaunchDesc *__restrict__ dp)
   if (t0 == 0) *d.counter = 0ull;
 }
 
+template <int LPL>
 __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   const BP_CONST Entry &e = as_const(d.entries)[find_entry(as_const(d.entries), d.nentries, task)];
   const int64_t inst = e.inst;
@@ -795,32 +805,32 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
     if (early && __builtin_amdgcn_readfirstlane(*(volatile int32_t *)&d.refuted[inst])) return;
-    t.lam0 = e.lam0 + tl * kTile;
-    int64_t lam[kLPL], lbp[kLPL];
-    bool ok[kLPL];
+    t.lam0 = e.lam0 + tl * (64 * LPL);
+    int64_t lam[LPL], lbp[LPL];
+    bool ok[LPL];
     if (bound == kL2) {
       // tiles of L2 run over candidate indices, not parameters
-      tile_l2(t, lam, lbp, ok);
-      flush_tile(d, inst, kL2, t, lam, lbp, ok, early);
+      tile_l2<LPL>(t, lam, lbp, ok);
+      flush_tile<LPL>(d, inst, kL2, t, lam, lbp, ok, early);
       continue;
     }
     if (t.lam0 > t.hi) return;
-    uint32_t l32[kLPL];
-    tile_lams(t, lam, l32);
-    int64_t part[kLPL];
+    uint32_t l32[LPL];
+    tile_lams<LPL>(t, lam, l32);
+    int64_t part[LPL];
     switch (bound) {
-      case kMT: part_mt(t, l32, part); break;
-      case kRAD2: part_rad2(t, l32, part); break;
-      case kFS1: part_fs1(t, l32, part); break;
-      case kCCM1: part_ccm1(t, l32, part); break;
-      case kVB2: part_vb2(t, l32, part); break;
-      default: part_bj1(t, l32, part); break;
+      case kMT: part_mt<LPL>(t, l32, part); break;
+      case kRAD2: part_rad2<LPL>(t, l32, part); break;
+      case kFS1: part_fs1<LPL>(t, l32, part); break;
+      case kCCM1: part_ccm1<LPL>(t, l32, part); break;
+      case kVB2: part_vb2<LPL>(t, l32, part); break;
+      default: part_bj1<LPL>(t, l32, part); break;
     }
-    for (int j = 0; j < kLPL; ++j) ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
+    for (int j = 0; j < LPL; ++j) ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
     if (nch > 1) {
       // add this chunk's parts; the wave that completes the tile finalises it
-      long long *acc = d.acc + e.acc_base + (tl * kTile);
-      for (int j = 0; j < kLPL; ++j)
+      long long *acc = d.acc + e.acc_base + (tl * (64 * LPL));
+      for (int j = 0; j < LPL; ++j)
         if (ok[j]) atomicAdd((unsigned long long *)&acc[lane_id() + 64 * j], (unsigned long long)part[j]);
       __threadfence();
       uint32_t prev = 0;
@@ -828,21 +838,22 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)prev);
       if (prev != (uint32_t)(nch - 1)) continue;
       __threadfence();
-      for (int j = 0; j < kLPL; ++j)
+      for (int j = 0; j < LPL; ++j)
         part[j] = ok[j] ? (int64_t)atomicAdd((unsigned long long *)&acc[lane_id() + 64 * j], 0ull) : 0;
     }
-    for (int j = 0; j < kLPL; ++j) lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
-    flush_tile(d, inst, bound, t, lam, lbp, ok, early);
+    for (int j = 0; j < LPL; ++j) lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
+    flush_tile<LPL>(d, inst, bound, t, lam, lbp, ok, early);
   }
 }
 
 // Persistent sweep: wave b starts with task b, then takes tasks from one
 // atomic counter (offset by the grid size) until none is left.
+template <int LPL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep(const LaunchDesc *__restrict__ dp) {
   const LaunchDesc d = *as_const(dp);
   uint64_t task = blockIdx.x;
   while (task < (uint64_t)d.ntasks) {
-    run_task(d, task);
+    run_task<LPL>(d, task);
     unsigned long long nxt = 0;
     if (lane_id() == 0) nxt = atomicAdd(d.counter, 1ull);
     nxt = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nxt) |
@@ -974,7 +985,16 @@ hipError_t set_kernel_attrs() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)prep_smem_large());
 }
 
-hipError_t launch_pipeline(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
+static hipError_t launch_sweep(const LaunchDesc *d_desc, int lpl, int grid_sweep, hipStream_t s) {
+  switch (lpl) {
+    case 1: hipLaunchKernelGGL(k_sweep<1>, dim3(grid_sweep), dim3(64), 0, s, d_desc); break;
+    case 4: hipLaunchKernelGGL(k_sweep<4>, dim3(grid_sweep), dim3(64), 0, s, d_desc); break;
+    default: hipLaunchKernelGGL(k_sweep<2>, dim3(grid_sweep), dim3(64), 0, s, d_desc); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
                            int grid_fin, hipStream_t s) {
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
                      prep_smem_small(), s, d_desc);
@@ -985,15 +1005,14 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int grid_prep_small, int gr
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sweep, dim3(grid_sweep), dim3(64), 0, s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   return hipGetLastError();
 }
 
 // The same launches with events around the stages (diagnostic timing).
-hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                                 int grid_fin, hipStream_t s, hipEvent_t ev[4]) {
+hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
+                                 int grid_sweep, int grid_fin, hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipEventRecord(ev[0], s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
@@ -1005,8 +1024,7 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int grid_prep_small, 
   hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sweep, dim3(grid_sweep), dim3(64), 0, s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;

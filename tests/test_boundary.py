@@ -73,6 +73,8 @@ def test_argument_errors_without_device():
     items = np.array([1, 2], dtype=np.int32)
     assert lib.bp_lower_bounds(None, 10, 1, items.ctypes.data_as(bp._P32), 2, None, ctypes.byref(out)) == bp.BP_ERR_STATE
     assert lib.bp_queue_destroy(None) == bp.BP_ERR_STATE
+    t = bp.bp_tuning(2, 32, 8, 384)
+    assert lib.bp_ctx_set_tuning(None, ctypes.byref(t)) == bp.BP_ERR_STATE
     assert lib.bp_queue_poll(None, None, 0, None, 0) == bp.BP_ERR_STATE
 
 

@@ -344,3 +344,38 @@ def test_feasible_batch(ctx):
             assert lb[i] > k
         else:
             assert lb[i] == want["lb"]
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 1, 64), (4, 32, 16, 128), (2, 16, 4, 1024), (4, 4, 64, 65536)])
+def test_results_do_not_depend_on_the_sweep_shape(ctx, shape):
+    rng = random.Random(808)
+    insts = [rand_instance(rng, cmax=20000, nmax=700) for _ in range(40)]
+    insts.append((100_000, list(W.large_residual(1)[3][:3000])))
+    ks = [len(it) // 3 for _, it in insts]
+    want = O.bounds_many([(C, k, it) for (C, it), k in zip(insts, ks)])
+    old = ctx.get_tuning()
+    try:
+        ctx.set_tuning(*shape)
+        say("shape", shape)
+        out = ctx.lower_bounds_batch([c for c, _ in insts], ks, [it for _, it in insts])
+        for i in range(len(insts)):
+            same(row_dict(out[i]), want[i], ("shape", shape, i))
+    finally:
+        ctx.set_tuning(**old)
+
+
+def test_autotuner_keeps_results(ctx):
+    rng = random.Random(909)
+    insts = [rand_instance(rng, cmax=50000, nmax=400) for _ in range(24)]
+    ks = [len(it) // 2 for _, it in insts]
+    old = ctx.get_tuning()
+    try:
+        say("autotune")
+        best, ms = ctx.autotune_batch([c for c, _ in insts], ks, [it for _, it in insts], reps=1)
+        assert best == ctx.get_tuning() and ms > 0
+        out = ctx.lower_bounds_batch([c for c, _ in insts], ks, [it for _, it in insts])
+        want = O.bounds_many([(C, k, it) for (C, it), k in zip(insts, ks)])
+        for i in range(len(insts)):
+            same(row_dict(out[i]), want[i], ("tuned", i))
+    finally:
+        ctx.set_tuning(**old)
