@@ -27,9 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Full-rate VALU issue slots per (item, parameter) evaluation of each sweep,
-# from the instruction sequences of the inner loops (32-bit add, sub and
-# shift-right issue at twice the full rate on gfx950 and count 1/2).
-OPS_PER_EVAL = {"MT": 2.5, "RAD2": 3.0, "FS1": 9.0, "CCM1": 2.0, "VB2": 2.5, "BJ1": 4.0}
+# counted in the inner loops of the sweep kernel as built for gfx950 with 4
+# parameters per lane (32-bit add, sub, logic and shifts issue at twice the
+# full rate and count 1/2; mul_hi, mad_u64_u32, add3, sad and fp64 count 1).
+OPS_PER_EVAL = {"MT": 2.0, "RAD2": 3.0, "FS1": 10.25, "CCM1": 2.0, "VB2": 2.5, "BJ1": 4.0}
 PEAK_VALU = 256 * 64 * 2.4e9  # full-rate lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 DFF_NAMES = ("MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1")
 
@@ -90,6 +91,37 @@ def cpu_baseline(C, items, target_s: float):
                       f"a single-thread probe puts the whole instance at {full_core_s:.1f} core-s)"}
 
 
+def sweep_ops(O, C, r):
+    """Algorithmic VALU slots of the six sweeps of one instance (exact ranges)."""
+    ops = 0.0
+    for name, d in zip(DFF_NAMES, O.DFFS):
+        lo, hi = O.default_range(d, C)
+        ops += OPS_PER_EVAL[name] * r * max(0, hi - lo + 1)
+    return ops
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch of a kernel, from the counter summary in profiles/,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2402_14821_amd", "csrc", "bp_kernels.hip")
+    with open(src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != digest or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
 def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, plain_max: int = 4096):
     """Uneven batch: one batched call vs one plain call per instance (host in, host out)."""
     import numpy as np
@@ -106,6 +138,14 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
         ts.append(time.perf_counter() - t0)
     t_batch = min(ts)
     evals = int(out["evals"].sum())
+    # the sweep kernel of the same batch, timed with HIP events on the context's stream
+    import oracle as O  # ranges only
+    ctx.set_timing(True)
+    for _ in range(reps):
+        ctx.lower_bounds_batch(Cs, ks, items_list)
+    (prep_ms, sweep_ms, fin_ms), runs = ctx.stage_times(with_runs=True)
+    ctx.set_timing(False)
+    ops = sum(sweep_ops(O, int(c), int(r)) for c, r in zip(Cs, out["r"]))
     fails = int((out["verdict"] == 0).sum())
     assert np.array_equal(out["verdict"] == 0, b.expect_fail), "batched verdicts differ from the construction"
     # plain: one call per instance, each synchronous
@@ -126,7 +166,11 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
                         "C in {1e3, 1e4, 1e6}, sizes U[1, C], 40% built to fail; host in/out",
             "batched_s": t_batch, "batched_checks_per_s": len(b) / t_batch, "batched_evals_per_s": evals / t_batch,
             "plain_checks_per_s": plain_rate, "batched_over_plain": (len(b) / t_batch) / plain_rate,
-            "evals": evals, "fails": fails, "per_class_plain": classes}
+            "evals": evals, "fails": fails, "per_class_plain": classes,
+            "stages_ms": {"prep": prep_ms, "sweep": sweep_ms, "finalize": fin_ms, "runs": runs},
+            "sweep_roofline": {"bound": "alu", "achieved": ops / (sweep_ms * 1e-3) / 1e12, "peak": PEAK_VALU / 1e12,
+                               "unit": "TOP/s", "frac": ops / (sweep_ms * 1e-3) / PEAK_VALU},
+            "tuning": ctx.get_tuning()}
 
 
 def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30):
@@ -248,7 +292,10 @@ def main():
     r = rec["r"]
     evals_per_step = rec["evals"]
 
-    # timed region: K whole steps, inputs resident in HBM
+    # timed region: K whole steps, inputs resident in HBM.  The kernels run
+    # one by one with HIP events around each on this stream, so the sweep
+    # kernel's mean duration over exactly these K steps is known.
+    ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -256,25 +303,22 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
-
-    # stage timing of the same step (kernels launched one by one, HIP events on this stream)
-    ctx.set_timing(True)
-    prep_ms, sweep_ms, fin_ms = [], [], []
-    for _ in range(max(5, args.steps // 2)):
-        step()
-        a, b, c = ctx.stage_times()
-        prep_ms.append(a)
-        sweep_ms.append(b)
-        fin_ms.append(c)
+    (prep_avg, sweep_avg, fin_avg), runs = ctx.stage_times(with_runs=True)
     ctx.set_timing(False)
-    sweep_avg = float(np.mean(sweep_ms))
+    assert runs == args.steps, (runs, args.steps)
+
+    # the same steps replayed as one HIP graph each (the default launch path)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step_graph = (time.perf_counter() - t1) * 1e3 / args.steps
 
     import oracle as O  # ranges only (the bench's oracle leg)
-    ops = 0.0
-    for name, d in zip(DFF_NAMES, O.DFFS):
-        lo, hi = O.default_range(d, C)
-        ops += OPS_PER_EVAL[name] * r * max(0, hi - lo + 1)
+    ops = sweep_ops(O, C, r)
     achieved = ops / (sweep_avg * 1e-3)
+    traffic = load_traffic("k_sweep")
 
     # plain single-check latency on the small partial packing (host in, host out)
     lat = []
@@ -302,10 +346,11 @@ def main():
                                "m=4000 residual capacities U[C/2,C], full parameter sweeps (exact, no VB2 cut)",
                    "r": r, "evals_per_step": evals_per_step, "parallelism": "single GPU"},
         "checks_per_s": args.steps / dt,
-        "stages_ms": {"prep": float(np.mean(prep_ms)), "sweep": sweep_avg, "finalize": float(np.mean(fin_ms))},
+        "ms_per_step_graph": ms_per_step_graph,
+        "stages_ms": {"prep": prep_avg, "sweep": sweep_avg, "finalize": fin_avg, "runs": runs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_VALU, "traffic": None, "kernel": "k_sweep",
-                     "ops_per_eval": OPS_PER_EVAL},
+                     "frac": achieved / PEAK_VALU, "traffic": traffic, "kernel": "k_sweep",
+                     "ops_per_eval": OPS_PER_EVAL, "tuning": ctx.get_tuning()},
         "plain_small_check_us": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "n": len(lat),
                                  "workload": "n=50 sizes U[20,100], m=20, C=150, 30% pre-packed; host in/out"},
         "verdict": rec["verdict"], "lb": rec["lb"],

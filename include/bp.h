@@ -119,7 +119,8 @@ bp_status bp_ctx_destroy(bp_ctx *ctx);
  *                  unit: 4 .. 32;
  *   tasks_per_wave tasks per resident wave the planner aims at; tiles dearer
  *                  than a task are split into item chunks: 1 .. 64;
- *   min_chunk      fewest items in one chunk of a split tile: 64 .. 65536. */
+ *   min_chunk      fewest items in one chunk of a split tile: 64 .. 65536.
+ * A new context starts with {4, 32, 32, 1024}. */
 typedef struct bp_tuning {
   int32_t lanes_params;
   int32_t waves_per_cu;
@@ -130,13 +131,17 @@ bp_status bp_ctx_get_tuning(bp_ctx *ctx, bp_tuning *out);
 bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning);
 
 
-/* Stage timing for diagnostics.  With enable = 1 the context launches the
- * pipeline kernels one by one instead of replaying its graph and records HIP
- * events around each on the call's stream; bp_ctx_stage_times waits for the
- * last call and returns its durations in milliseconds:
- * ms[0] reduction + sort + prefix (prep), ms[1] sweeps, ms[2] finalize. */
+/* Stage timing for diagnostics and measurement.  With enable = 1 the context
+ * launches the pipeline kernels one by one instead of replaying its graph and
+ * records HIP events around each on the call's stream.  bp_ctx_stage_times
+ * waits for every call made since timing was last switched on (set_timing
+ * restarts the count) and returns the mean durations in milliseconds:
+ * ms[0] reduction + sort + prefix (prep), ms[1] sweeps, ms[2] finalize;
+ * *runs (optional) receives the number of calls averaged.  BP_ERR_STATE if
+ * timing is off or no call was timed.  Every 64th timed call waits for the
+ * oldest pending one, so long timed runs stay bounded in memory. */
 bp_status bp_ctx_set_timing(bp_ctx *ctx, int32_t enable);
-bp_status bp_ctx_stage_times(bp_ctx *ctx, double ms[3]);
+bp_status bp_ctx_stage_times(bp_ctx *ctx, double ms[3], int64_t *runs);
 
 /* Reduction of a partial packing (Sec. 3, Fig. 3), run on the device.
  * residual[m] are the remaining capacities of the k = m bins, unpacked[n] the

@@ -102,7 +102,7 @@ _SIGNATURES = {
     "bp_ctx_set_tuning": ([_VP, ctypes.POINTER(bp_tuning)], _i32),
     "bp_autotune_batch": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _i32,
                            ctypes.POINTER(bp_tuning), ctypes.POINTER(ctypes.c_double)], _i32),
-    "bp_ctx_stage_times": ([_VP, ctypes.POINTER(ctypes.c_double)], _i32),
+    "bp_ctx_stage_times": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], _i32),
     "bp_lower_bounds_batch": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _VP], _i32),
     "bp_lower_bounds_batch_dev": ([_VP, ctypes.POINTER(bp_batch), _VP, ctypes.POINTER(bp_sweep), _VP, _VP], _i32),
     "bp_feasible_batch": ([_VP, ctypes.POINTER(bp_batch), _u32, _P32, _P64], _i32),
@@ -316,11 +316,13 @@ class Context:
         _check(self._lib.bp_autotune_batch(self.handle, ctypes.byref(b.s), sw, reps, ctypes.byref(t), ctypes.byref(ms)))
         return {f: getattr(t, f) for f, _ in bp_tuning._fields_}, ms.value
 
-    def stage_times(self):
-        """Durations (ms) of prep, sweep and finalize of the last call (timing mode)."""
+    def stage_times(self, with_runs: bool = False):
+        """Mean durations (ms) of prep, sweep and finalize over the calls made
+        since timing was switched on; with_runs also returns how many."""
         ms = (ctypes.c_double * 3)()
-        _check(self._lib.bp_ctx_stage_times(self.handle, ms))
-        return list(ms)
+        runs = ctypes.c_int64(0)
+        _check(self._lib.bp_ctx_stage_times(self.handle, ms, ctypes.byref(runs)))
+        return (list(ms), runs.value) if with_runs else list(ms)
 
     # -- batches --
     def lower_bounds_batch(self, Cs, ks, items_list, sweeps=None) -> np.ndarray:

@@ -165,7 +165,8 @@ bp_status Ctx::init(int dev) {
   HIP_TRY(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-  for (hipEvent_t &e : tev) HIP_TRY(hipEventCreate(&e));
+  for (auto &set : tev)
+    for (hipEvent_t &e : set) HIP_TRY(hipEventCreate(&e));
   bp_status st = counter_buf.reserve(256);
   if (st) return st;
   apply_tuning();
@@ -190,10 +191,11 @@ void Ctx::destroy() {
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (staged) (void)hipEventDestroy(staged);
   if (done) (void)hipEventDestroy(done);
-  for (hipEvent_t &e : tev) {
-    if (e) (void)hipEventDestroy(e);
-    e = nullptr;
-  }
+  for (auto &set : tev)
+    for (hipEvent_t &e : set) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   if (stream) (void)hipStreamDestroy(stream);
   staged = done = nullptr;
   stream = nullptr;
@@ -410,8 +412,10 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   HIP_TRY(hipEventRecord(staged, s));
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
   if (timing) {
+    hipEvent_t *ev = nullptr;
+    if ((st = timing_slot(&ev))) return st;
     HIP_TRY(launch_pipeline_timed(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
-                                  s, tev));
+                                  s, ev));
   } else if (use_graph) {
     if ((st = ensure_graph(d_desc))) return st;
     HIP_TRY(hipGraphLaunch(graph_exec, s));
@@ -486,11 +490,49 @@ static bp_status get_ctx(bp_ctx *ctx, Ctx **c) {
   return BP_OK;
 }
 
+void Ctx::timing_reset() {
+  t_runs = t_folded = 0;
+  t_sum[0] = t_sum[1] = t_sum[2] = 0;
+}
+
+static bp_status fold_set(hipEvent_t *ev, double sum[3]) {
+  HIP_TRY(hipEventSynchronize(ev[3]));
+  for (int i = 0; i < 3; ++i) {
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+    sum[i] += t;
+  }
+  return BP_OK;
+}
+
+bp_status Ctx::timing_slot(hipEvent_t **ev) {
+  if (t_runs - t_folded == kTimingRing) {
+    bp_status st = fold_set(tev[t_folded % kTimingRing], t_sum);
+    if (st) return st;
+    ++t_folded;
+  }
+  *ev = tev[t_runs % kTimingRing];
+  ++t_runs;
+  return BP_OK;
+}
+
+bp_status Ctx::timing_mean(double ms[3], int64_t *runs) {
+  for (; t_folded < t_runs; ++t_folded) {
+    bp_status st = fold_set(tev[t_folded % kTimingRing], t_sum);
+    if (st) return st;
+  }
+  if (runs) *runs = t_runs;
+  if (t_runs == 0) return fail(BP_ERR_STATE, "no timed call since timing was switched on");
+  for (int i = 0; i < 3; ++i) ms[i] = t_sum[i] / (double)t_runs;
+  return BP_OK;
+}
+
 bp_status bp_ctx_set_timing(bp_ctx *ctx, int32_t enable) {
   Ctx *c;
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
   c->timing = enable != 0;
+  c->timing_reset();
   return BP_OK;
 }
 
@@ -524,19 +566,13 @@ bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning) {
   return BP_OK;
 }
 
-bp_status bp_ctx_stage_times(bp_ctx *ctx, double ms[3]) {
+bp_status bp_ctx_stage_times(bp_ctx *ctx, double ms[3], int64_t *runs) {
   Ctx *c;
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
   if (!ms) return fail(BP_ERR_ARG, "ms is NULL");
   if (!c->timing) return fail(BP_ERR_STATE, "timing is off");
-  HIP_TRY(hipEventSynchronize(c->tev[3]));
-  for (int i = 0; i < 3; ++i) {
-    float t = 0;
-    HIP_TRY(hipEventElapsedTime(&t, c->tev[i], c->tev[i + 1]));
-    ms[i] = t;
-  }
-  return BP_OK;
+  return c->timing_mean(ms, runs);
 }
 
 // ---- reduction ----------------------------------------------------------
@@ -861,14 +897,14 @@ bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *
     c->apply_tuning();
     double bestv = 1e300;
     for (int32_t r = 0; r < reps; ++r) {
+      c->timing_reset();
       std::vector<PlanIn> p2 = pin;
       bp_status s2 = launch_host_batch(c, p2, a, b);
       if (s2) return s2;
       if ((s2 = collect_host_batch(c, batch->count, out.data(), true))) return s2;
-      float t_ms = 0;
-      hipError_t e = hipEventElapsedTime(&t_ms, c->tev[1], c->tev[2]);
-      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-      bestv = std::min(bestv, (double)t_ms);
+      double t_ms[3];
+      if ((s2 = c->timing_mean(t_ms, nullptr))) return s2;
+      bestv = std::min(bestv, t_ms[1]);
     }
     *ms = bestv;
     return BP_OK;
@@ -878,11 +914,11 @@ bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *
   if ((st = measure(cur, &cur_ms))) { c->timing = was_timing; return st; }
   const int32_t lpls[] = {1, 2, 4};
   const int32_t waves[] = {8, 16, 24, 32};
-  const int32_t tasks[] = {1, 2, 4, 8, 16};
+  const int32_t tasks[] = {1, 2, 4, 8, 16, 32, 64};
   const int32_t chunks[] = {128, 384, 1024, 4096};
   for (int knob = 0; knob < 4; ++knob) {
     const int32_t *vals = knob == 0 ? lpls : knob == 1 ? waves : knob == 2 ? tasks : chunks;
-    const int nv = knob == 0 ? 3 : knob == 1 ? 4 : knob == 2 ? 5 : 4;
+    const int nv = knob == 0 ? 3 : knob == 1 ? 4 : knob == 2 ? 7 : 4;
     for (int v = 0; v < nv; ++v) {
       bp_tuning t = cur;
       int32_t *field = knob == 0 ? &t.lanes_params : knob == 1 ? &t.waves_per_cu : knob == 2 ? &t.tasks_per_wave : &t.min_chunk;
@@ -897,6 +933,7 @@ bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *
     }
   }
   c->timing = was_timing;
+  c->timing_reset();
   c->tune = cur;
   c->apply_tuning();
   if (best) *best = cur;

@@ -56,10 +56,15 @@ struct Ctx {
   hipEvent_t done = nullptr;
   bool use_graph = true;
   bool timing = false;
-  hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Stage timing: one set of 4 events per timed run, reused round-robin; a
+  // set is folded into the sums (waiting for it) before it is reused.
+  static constexpr int kTimingRing = 64;
+  hipEvent_t tev[kTimingRing][4] = {};
+  int64_t t_runs = 0, t_folded = 0;
+  double t_sum[3] = {0, 0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  bp_tuning tune = {2, 32, 8, 384};  // parameters per lane, waves per CU, tasks per wave, min chunk
+  bp_tuning tune = {4, 32, 32, 1024};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_fin = 0;
   int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
   int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, cnt_len = 0;
@@ -78,6 +83,9 @@ struct Ctx {
                 bp_bounds *out_dev, hipStream_t s);
   bp_status wait_staging();
   void apply_tuning();
+  void timing_reset();
+  bp_status timing_slot(hipEvent_t **ev);
+  bp_status timing_mean(double ms[3], int64_t *runs);
 };
 
 bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,

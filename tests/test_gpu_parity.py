@@ -379,3 +379,21 @@ def test_autotuner_keeps_results(ctx):
             same(row_dict(out[i]), want[i], ("tuned", i))
     finally:
         ctx.set_tuning(**old)
+
+
+def test_stage_timing_averages_every_timed_call(ctx):
+    rng = random.Random(1212)
+    C, items = rand_instance(rng, cmax=5000, nmax=300)
+    ctx.set_timing(True)
+    try:
+        for _ in range(70):  # more calls than the context keeps event sets for
+            ctx.lower_bounds(C, len(items), items)
+        ms, runs = ctx.stage_times(with_runs=True)
+        assert runs == 70 and all(t > 0 for t in ms)
+        ctx.set_timing(True)  # restarts the count
+        with pytest.raises(bp.BpError):
+            ctx.stage_times()
+        ctx.lower_bounds(C, len(items), items)
+        assert ctx.stage_times(with_runs=True)[1] == 1
+    finally:
+        ctx.set_timing(False)
