@@ -120,7 +120,7 @@ bp_status bp_ctx_destroy(bp_ctx *ctx);
  *   tasks_per_wave tasks per resident wave the planner aims at; tiles dearer
  *                  than a task are split into item chunks: 1 .. 64;
  *   min_chunk      fewest items in one chunk of a split tile: 64 .. 65536.
- * A new context starts with {4, 32, 32, 1024}. */
+ * A new context starts with {2, 32, 32, 2048}. */
 typedef struct bp_tuning {
   int32_t lanes_params;
   int32_t waves_per_cu;

@@ -340,7 +340,14 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   cnt_len = cnt;
   std::vector<size_t> order(ent.size());
   for (size_t j = 0; j < order.size(); ++j) order[j] = j;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_cost[a] > task_cost[b]; });
+  // Longest task first, except that L2 tasks go first of all: they are cheap
+  // in issue slots but wait on chains of dependent loads, and started early
+  // they overlap the sweeps of other waves instead of trailing the launch.
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    const bool la = ent[a].bound == kL2, lb = ent[b].bound == kL2;
+    if (la != lb) return la;
+    return task_cost[a] > task_cost[b];
+  });
   entry_vec.resize(std::max<size_t>(ent.size(), 1));
   memset(entry_vec.data(), 0, sizeof(Entry) * entry_vec.size());
   int64_t tb = 0;

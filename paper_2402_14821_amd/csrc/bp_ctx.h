@@ -64,7 +64,7 @@ struct Ctx {
   double t_sum[3] = {0, 0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  bp_tuning tune = {4, 32, 32, 1024};  // parameters per lane, waves per CU, tasks per wave, min chunk
+  bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_fin = 0;
   int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
   int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, cnt_len = 0;

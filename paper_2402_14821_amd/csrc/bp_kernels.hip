@@ -147,93 +147,124 @@ struct PrepSmem {
   int32_t flags[8];
 };
 
-// Stable LSD radix sort (8-bit digits) of n keys in LDS, ascending.  Each
-// round places NT keys: a key's rank among equal digits of its wave comes
-// from eight ballots (the lanes that share its digit), the offset of earlier
-// waves and earlier rounds from per-(wave, digit) counts.  Returns the buffer
-// index holding the result.
+// Stable LSD radix sort (8-bit digits) of n keys in LDS, ascending.  Wave w
+// owns the keys [w 64 K, (w + 1) 64 K), K = CAP / NT, and holds them in
+// registers, key k of a lane at w 64 K + 64 k + lane.  Per digit pass each
+// wave ranks its keys in that order: a key's peers (lanes with the same
+// digit) come from ballots over the digit's bits, its rank is the wave's
+// running count of the digit plus the peers below it.  One block-wide scan
+// over (digit, wave) counts then gives every key its place.  Keys are <= c,
+// so a pass looks only at the bits below `bits`.  Returns the buffer index
+// holding the result.
 template <int NT, int CAP>
 __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
   constexpr int NW = NT / 64;
+  constexpr int K = CAP / NT;
+  static_assert(K * NT == CAP, "capacity must be a multiple of the block size");
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wbase = wave * 64 * K;
+  // number of key rows of this wave that hold any key (wave-uniform)
+  const int rows = n > wbase ? min(K, (n - wbase + 63) >> 6) : 0;
   int src = 0;
   for (int sh = 0; sh < bits; sh += 8) {
-    uint32_t *a = sm.keys[src];
+    const uint32_t *a = sm.keys[src];
     uint32_t *b = sm.keys[src ^ 1];
-    for (int i = tid; i < 256; i += NT) sm.hist[i] = 0;
-    for (int i = tid; i < NW * 256; i += NT) (&sm.wcnt[0][0])[i] = 0;
+    const int dbits = min(8, bits - sh);
+    for (int i = lane; i < 256; i += 64) sm.wcnt[wave][i] = 0;
+    uint32_t key[K], rank[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      key[k] = 0;
+      rank[k] = 0;
+      if (k < rows) {
+        const int i = wbase + 64 * k + lane;
+        const bool valid = i < n;
+        key[k] = valid ? a[i] : 0xffffffffu;
+        const uint32_t d = (key[k] >> sh) & 255u;
+        uint64_t peers = ballot64(valid);
+        for (int bit = 0; bit < dbits; ++bit) {
+          const bool set = (d >> bit) & 1u;
+          const uint64_t m = ballot64(valid && set);
+          peers &= set ? m : ~m;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
+        // the wave's LDS accesses complete in program order: every lane reads
+        // the count before the group's lowest lane writes the new one
+        const uint32_t prior = valid ? sm.wcnt[wave][d] : 0u;
+        rank[k] = prior + below;
+        if (valid && below == 0) sm.wcnt[wave][d] = prior + (uint32_t)__popcll(peers);
+      }
+    }
     __syncthreads();
-    for (int i = tid; i < n; i += NT) atomicAdd(&sm.hist[(a[i] >> sh) & 255u], 1u);
+    // offsets: digit-major, then wave
+    for (int dg = tid; dg < 256; dg += NT) {
+      uint32_t run = 0;
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t c = sm.wcnt[w][dg];
+        sm.woff[w][dg] = run;
+        run += c;
+      }
+      sm.hist[dg] = run;
+    }
     __syncthreads();
-    // exclusive scan of the 256 digit counts by wave 0 (4 digits per lane)
     if (tid < 64) {
-      uint32_t c0 = sm.hist[4 * tid], c1 = sm.hist[4 * tid + 1], c2 = sm.hist[4 * tid + 2], c3 = sm.hist[4 * tid + 3];
-      uint32_t tot = c0 + c1 + c2 + c3;
-      uint32_t excl = wave_incl_scan_u32(tot) - tot;
+      const uint32_t c0 = sm.hist[4 * tid], c1 = sm.hist[4 * tid + 1], c2 = sm.hist[4 * tid + 2],
+                     c3 = sm.hist[4 * tid + 3];
+      const uint32_t tot = c0 + c1 + c2 + c3;
+      const uint32_t excl = wave_incl_scan_u32(tot) - tot;
       sm.hist[4 * tid] = excl;
       sm.hist[4 * tid + 1] = excl + c0;
       sm.hist[4 * tid + 2] = excl + c0 + c1;
       sm.hist[4 * tid + 3] = excl + c0 + c1 + c2;
     }
     __syncthreads();
-    for (int base = 0; base < n; base += NT) {
-      const int i = base + tid;
-      const bool valid = i < n;
-      const uint32_t key = valid ? a[i] : 0u;
-      const uint32_t d = (key >> sh) & 255u;
-      uint64_t peers = ballot64(valid);
 #pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
-        const bool set = (d >> bit) & 1u;
-        const uint64_t m = ballot64(valid && set);
-        peers &= set ? m : ~m;
+    for (int k = 0; k < K; ++k) {
+      if (k < rows && wbase + 64 * k + lane < n) {
+        const uint32_t d = (key[k] >> sh) & 255u;
+        b[sm.hist[d] + sm.woff[wave][d] + rank[k]] = key[k];
       }
-      const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-      if (valid && rank == 0) sm.wcnt[wave][d] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      // per digit: offsets of the waves of this round, then advance the digit base
-      for (int dg = tid; dg < 256; dg += NT) {
-        uint32_t run = sm.hist[dg];
-        for (int w = 0; w < NW; ++w) {
-          uint32_t c = sm.wcnt[w][dg];
-          sm.woff[w][dg] = run;
-          sm.wcnt[w][dg] = 0;
-          run += c;
-        }
-        sm.hist[dg] = run;
-      }
-      __syncthreads();
-      if (valid) b[sm.woff[wave][d] + rank] = key;
-      __syncthreads();
     }
+    __syncthreads();
     src ^= 1;
   }
   return src;
 }
 
-// Exclusive prefix sums of the sorted sizes into pre[0..n], block-wide.
+// Exclusive prefix sums of the sorted sizes into pre[0..n], block-wide, in
+// the same wave-striped layout as the sort: each wave first sums its keys,
+// then scans them row by row from its offset.
 template <int NT, int CAP>
 __device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n, int64_t *pre) {
   constexpr int NW = NT / 64;
+  constexpr int K = CAP / NT;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
-  uint64_t carry = 0;
-  if (tid == 0) pre[0] = 0;
-  for (int base = 0; base < n; base += NT) {
-    const int i = base + tid;
-    const uint64_t v = i < n ? sizes[i] : 0u;
-    const uint64_t incl = wave_incl_scan_u64(v);
-    if ((tid & 63) == 63) sm.wtot[wave] = incl;
-    __syncthreads();
-    uint64_t before = carry;
-    for (int w = 0; w < wave; ++w) before += sm.wtot[w];
-    if (i < n) pre[i + 1] = (int64_t)(before + incl);
-    uint64_t all = 0;
-    for (int w = 0; w < NW; ++w) all += sm.wtot[w];
-    carry += all;
-    __syncthreads();
+  const int lane = tid & 63;
+  const int wbase = wave * 64 * K;
+  const int rows = n > wbase ? min(K, (n - wbase + 63) >> 6) : 0;
+  uint64_t mine = 0;
+  for (int k = 0; k < rows; ++k) {
+    const int i = wbase + 64 * k + lane;
+    mine += i < n ? sizes[i] : 0u;
   }
+  const uint64_t tot = wave_incl_scan_u64(mine);
+  if (lane == 63) sm.wtot[wave] = tot;
+  __syncthreads();
+  uint64_t carry = 0;
+  for (int w = 0; w < wave; ++w) carry += sm.wtot[w];
+  if (tid == 0) pre[0] = 0;
+  for (int k = 0; k < rows; ++k) {
+    const int i = wbase + 64 * k + lane;
+    const uint64_t v = i < n ? sizes[i] : 0u;
+    const uint64_t incl = wave_incl_scan_u64(v) + carry;
+    if (i < n) pre[i + 1] = (int64_t)incl;
+    carry = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, 63) |
+            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(incl >> 32), 63) << 32);
+  }
+  (void)NW;
 }
 
 template <int NT, int CAP>
@@ -251,35 +282,70 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     status = BP_ERR_LIMIT;
   } else {
     // Reduction into LDS: sort key = c - w (ascending key = decreasing size).
+    // Inputs are read in the wave-striped layout of the sort, every load of a
+    // lane issued before the first store, so the block waits for one memory
+    // round trip per array rather than one per row.
+    constexpr int K = CAP / NT;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wbase = wave * 64 * K;
     const BP_GLOBAL int32_t *in = as_global(d.in + p.in_off);
-    const int64_t n_in = p.n_in;
-    for (int64_t i = tid; i < n_in; i += NT) {
-      int32_t w = in[i];
-      if (w < 0 || w > C) { sm.flags[0] = 1; w = 0; }
-      sm.keys[0][i] = uC - (uint32_t)w;
+    const int n_in = (int)p.n_in;
+    {
+      int32_t v[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = wbase + 64 * k + lane;
+        v[k] = i < n_in ? in[i] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = wbase + 64 * k + lane;
+        if (i < n_in) {
+          int32_t w = v[k];
+          if (w < 0 || w > C) { sm.flags[0] = 1; w = 0; }
+          sm.keys[0][i] = uC - (uint32_t)w;
+        }
+      }
     }
     int64_t nfill = 0;
     if (p.form == kFormResidual) {
-      // one virtual item of size c - residual per bin with residual < c (Fig. 3)
+      // one virtual item of size c - residual per bin with residual < c
+      // (Fig. 3), appended in bin order: a stable compaction of the loaded bins
       const BP_GLOBAL int32_t *res = as_global(d.in + p.res_off);
-      for (int base = 0; base < p.m_res; base += NT) {
-        const int j = base + tid;
-        int32_t rj = j < p.m_res ? res[j] : C;
-        if (rj < 0 || rj > C) { sm.flags[0] = 1; rj = C; }
-        const bool take = rj < C;
-        // stable compaction of the loaded bins, in bin order
-        const uint64_t bal = ballot64(take);
-        const uint32_t below = (uint32_t)__popcll(bal & lanemask_lt());
-        if ((tid & 63) == 0) sm.wcnt[0][tid >> 6] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        uint32_t off = 0;
-        for (int w = 0; w < (tid >> 6); ++w) off += sm.wcnt[0][w];
-        uint32_t tot = 0;
-        for (int w = 0; w < NT / 64; ++w) tot += sm.wcnt[0][w];
-        if (take) sm.keys[0][n_in + nfill + off + below] = (uint32_t)rj;  // key = c - load = residual
-        nfill += tot;
-        __syncthreads();
+      const int m = p.m_res;
+      int32_t rv[K];
+      uint32_t pos[K];
+      uint32_t takes = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = wbase + 64 * k + lane;
+        rv[k] = j < m ? res[j] : C;
       }
+      uint32_t run = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = wbase + 64 * k + lane;
+        int32_t rj = rv[k];
+        if (j < m && (rj < 0 || rj > C)) { sm.flags[0] = 1; rj = C; }
+        rv[k] = rj;
+        const bool take = j < m && rj < C;
+        const uint64_t bal = ballot64(take);
+        pos[k] = run + (uint32_t)__popcll(bal & lanemask_lt());
+        run += (uint32_t)__popcll(bal);
+        takes |= (uint32_t)take << k;
+      }
+      if (lane == 0) sm.wcnt[0][wave] = run;
+      __syncthreads();
+      uint32_t off = 0, tot = 0;
+      for (int w = 0; w < NT / 64; ++w) {
+        const uint32_t c = sm.wcnt[0][w];
+        off += w < wave ? c : 0u;
+        tot += c;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if ((takes >> k) & 1u) sm.keys[0][n_in + off + pos[k]] = (uint32_t)rv[k];  // key = c - load = residual
+      nfill = tot;
     }
     r = n_in + nfill;
     __syncthreads();
@@ -362,11 +428,22 @@ __device__ void prep_finish(const LaunchDesc &d, int64_t inst) {
   d.refuted[inst] = refuted;
 }
 
+// Clears the chunk accumulators, the tile counters and the task counter of
+// the sweep that follows (run by the small-instance prep grid).
+__device__ void clear_sweep_state(const LaunchDesc &d) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < d.acc_len; i += stride) d.acc[i] = 0;
+  for (int64_t i = t0; i < d.cnt_len; i += stride) d.tile_cnt[i] = 0;
+  if (t0 == 0) *d.counter = 0ull;
+}
+
 template <int NT, int CAP, int LARGE>
 __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   PrepSmem<NT, CAP> &sm = *reinterpret_cast<PrepSmem<NT, CAP> *>(smem_raw);
   const LaunchDesc d = *as_const(dp);
+  if (!LARGE) clear_sweep_state(d);
   for (int64_t inst = blockIdx.x; inst < d.count; inst += gridDim.x) {
     if (as_const(d.plan)[inst].large != LARGE) continue;
     prep_instance<NT, CAP>(d, inst, sm);
@@ -690,16 +767,6 @@ __device__ __forceinline__ int64_t fin_bound(int bound, const TileArgs &t, int64
   }
 }
 
-// First index of the decreasing array s[0..r) whose value is <= x.
-__device__ __forceinline__ int32_t first_le(const BP_GLOBAL int32_t *s, int32_t r, int64_t x) {
-  int32_t lo = 0, hi = r;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if ((int64_t)s[mid] > x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
 // L2 (Sec. 3.1) evaluated at the parameters where it can change: the range's
 // first parameter and w + 1, c - w + 1 for every size.  Candidate index
 // c = 0 is lo; c = 1 + 2i is w_i + 1; c = 2 + 2i is c - w_i + 1.
@@ -707,15 +774,21 @@ __device__ __forceinline__ int32_t first_le(const BP_GLOBAL int32_t *s, int32_t 
 //   n1 = #{w > c - lambda}, n2 = nbig - n1, sum W2 = pre[nbig] - pre[n1],
 //   W3 = {lambda <= w <= c/2} = sorted[nbig, j3) with j3 = #{w >= lambda},
 //   L2(lambda) = nbig + max(0, ceil((sum W3 - (c n2 - sum W2)) / c)).
+// The counts #{w > x} over the decreasing sizes are found by binary lifting
+// with a fixed number of steps, all 2 LPL searches of a lane in lockstep, so
+// that their loads are in flight together.
 template <int LPL>
 __device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL], bool ok[LPL]) {
   const int64_t C = t.C;
   const int32_t nbig = t.nb;  // includes the items of size c
+  const int32_t r = t.r;
+  int64_t x1[LPL], x3[LPL];
+  int32_t p1[LPL], p3[LPL];
   for (int j = 0; j < LPL; ++j) {
     const int64_t cidx = t.lam0 + lane_id() + 64 * j;
     int64_t lam = -1;
     if (cidx == 0) lam = t.lo;
-    else if (cidx <= 2 * (int64_t)t.r) {
+    else if (cidx <= 2 * (int64_t)r) {
       const int64_t i = (cidx - 1) >> 1;
       const int64_t w = t.sorted[i];
       lam = ((cidx - 1) & 1) ? C - w + 1 : w + 1;
@@ -723,8 +796,22 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL
     ok[j] = lam >= t.lo && lam <= t.hi;
     if (!ok[j]) lam = t.lo;
     lam_out[j] = lam;
-    const int32_t n1 = first_le(t.sorted, t.r, C - lam);
-    const int32_t j3 = first_le(t.sorted, t.r, lam - 1);
+    x1[j] = C - lam;  // n1 = #{w > c - lambda}
+    x3[j] = lam - 1;  // j3 = #{w > lambda - 1}
+    p1[j] = 0;
+    p3[j] = 0;
+  }
+  for (int32_t step = r > 0 ? (int32_t)(1u << (31 - __clz(r))) : 0; step > 0; step >>= 1) {
+    for (int j = 0; j < LPL; ++j) {
+      const int32_t q1 = p1[j] + step, q3 = p3[j] + step;
+      const int64_t v1 = t.sorted[min(q1, r) - 1];
+      const int64_t v3 = t.sorted[min(q3, r) - 1];
+      if (q1 <= r && v1 > x1[j]) p1[j] = q1;
+      if (q3 <= r && v3 > x3[j]) p3[j] = q3;
+    }
+  }
+  for (int j = 0; j < LPL; ++j) {
+    const int32_t n1 = p1[j], j3 = p3[j];
     const int64_t n2 = nbig - n1;
     const int64_t s2 = t.pre[nbig] - t.pre[n1];
     const int64_t s3 = j3 > nbig ? t.pre[j3] - t.pre[nbig] : 0;
@@ -745,7 +832,7 @@ __device__ __forceinline__ void flush_tile(const LaunchDesc &d, int64_t inst, in
     atomicMax(&d.keys[inst * kNB + bound], (unsigned long long)wmax);
     if (early) {
       const int64_t v = (int64_t)(wmax >> 32) + (bound == kL2 ? 0 : t.nf);
-      if (v > t.k) d.refuted[inst] = 1;
+      if (v > t.k) __hip_atomic_store(&d.refuted[inst], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -759,15 +846,6 @@ __device__ __forceinline__ int64_t find_entry(const BP_CONST Entry *e, int64_t n
   return lo;
 }
 
-// Clears the chunk accumulators, the tile counters and the task counter.
-__global__ __launch_bounds__(256) void k_zero(const LaunchDesc *__restrict__ dp) {
-  const LaunchDesc d = *as_const(dp);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (int64_t i = t0; i < d.acc_len; i += stride) d.acc[i] = 0;
-  for (int64_t i = t0; i < d.cnt_len; i += stride) d.tile_cnt[i] = 0;
-  if (t0 == 0) *d.counter = 0ull;
-}
 
 template <int LPL>
 __device__ void run_task(const LaunchDesc &d, uint64_t task) {
@@ -804,7 +882,9 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   t.i1 = t.nf + (int32_t)(span * (chunk + 1) / nch);
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
-    if (early && __builtin_amdgcn_readfirstlane(*(volatile int32_t *)&d.refuted[inst])) return;
+    if (early && __builtin_amdgcn_readfirstlane(
+                     __hip_atomic_load(&d.refuted[inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      return;
     t.lam0 = e.lam0 + tl * (64 * LPL);
     int64_t lam[LPL], lbp[LPL];
     bool ok[LPL];
@@ -828,18 +908,28 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
     }
     for (int j = 0; j < LPL; ++j) ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
     if (nch > 1) {
-      // add this chunk's parts; the wave that completes the tile finalises it
+      // Add this chunk's parts; the wave that completes the tile finalises
+      // it.  The parts and the tile counter are only ever touched by
+      // device-scope atomic read-modify-writes, which the device performs at
+      // its coherence point, past the per-XCD L2 caches.  Waiting for this
+      // wave's adds to be acknowledged before it bumps the counter therefore
+      // orders them for the wave that reads the final count, and no cache
+      // write-back or invalidation (a device-scope fence) is needed.
       long long *acc = d.acc + e.acc_base + (tl * (64 * LPL));
       for (int j = 0; j < LPL; ++j)
-        if (ok[j]) atomicAdd((unsigned long long *)&acc[lane_id() + 64 * j], (unsigned long long)part[j]);
-      __threadfence();
+        if (ok[j])
+          __hip_atomic_fetch_add((unsigned long long *)&acc[lane_id() + 64 * j], (unsigned long long)part[j],
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       uint32_t prev = 0;
-      if (lane_id() == 0) prev = atomicAdd(&d.tile_cnt[e.cnt_base + tl], 1u);
+      if (lane_id() == 0)
+        prev = __hip_atomic_fetch_add(&d.tile_cnt[e.cnt_base + tl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)prev);
       if (prev != (uint32_t)(nch - 1)) continue;
-      __threadfence();
       for (int j = 0; j < LPL; ++j)
-        part[j] = ok[j] ? (int64_t)atomicAdd((unsigned long long *)&acc[lane_id() + 64 * j], 0ull) : 0;
+        part[j] = ok[j] ? (int64_t)__hip_atomic_fetch_add((unsigned long long *)&acc[lane_id() + 64 * j], 0ull,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : 0;
     }
     for (int j = 0; j < LPL; ++j) lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
     flush_tile<LPL>(d, inst, bound, t, lam, lbp, ok, early);
@@ -1003,8 +1093,6 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_smal
   hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
                      prep_smem_large(), s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   return hipGetLastError();
@@ -1020,8 +1108,6 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_pre
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
                      prep_smem_large(), s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;

@@ -397,3 +397,21 @@ def test_stage_timing_averages_every_timed_call(ctx):
         assert ctx.stage_times(with_runs=True)[1] == 1
     finally:
         ctx.set_timing(False)
+
+
+@pytest.mark.parametrize("shape", [(4, 32, 64, 64), (1, 32, 64, 64), (2, 24, 64, 128)])
+def test_heavily_split_tiles_repeatably_exact(ctx, shape):
+    # tiles cut into many item chunks run by different waves, combined through
+    # device-scope atomics: the same exact result on every repetition
+    rng = np.random.default_rng(4242)
+    C = 20_000
+    items = rng.integers(C // 10, C // 2 + 1, size=3000).tolist() + [C - int(x) for x in rng.integers(C // 2, C, 600)]
+    want = O.bounds(C, len(items) // 2, items)
+    old = ctx.get_tuning()
+    try:
+        ctx.set_tuning(*shape)
+        say("split", shape)
+        for rep in range(8):
+            same(ctx.lower_bounds(C, len(items) // 2, items), want, ("split", shape, rep))
+    finally:
+        ctx.set_tuning(**old)
