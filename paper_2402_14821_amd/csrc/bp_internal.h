@@ -17,7 +17,7 @@ enum : int { kL1 = 0, kL2, kMT, kRAD2, kFS1, kCCM1, kVB2, kBJ1, kNB };
 constexpr int kWave = 64;
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
-constexpr int kLargeThreads = 512;      // prep block for one large instance
+constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
 
 // Input form of an instance.

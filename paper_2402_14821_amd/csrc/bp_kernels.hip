@@ -141,8 +141,7 @@ template <int NT, int CAP>
 struct PrepSmem {
   uint32_t keys[2][CAP];
   uint32_t hist[256];
-  uint32_t wcnt[NT / 64][256];
-  uint32_t woff[NT / 64][256];
+  uint32_t wcnt[NT / 64][256];  // per (wave, digit): counts, then offsets
   uint64_t wtot[NT / 64];
   int32_t flags[8];
 };
@@ -198,12 +197,12 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
       }
     }
     __syncthreads();
-    // offsets: digit-major, then wave
+    // offsets, digit-major then wave, written over the counts
     for (int dg = tid; dg < 256; dg += NT) {
       uint32_t run = 0;
       for (int w = 0; w < NW; ++w) {
         const uint32_t c = sm.wcnt[w][dg];
-        sm.woff[w][dg] = run;
+        sm.wcnt[w][dg] = run;
         run += c;
       }
       sm.hist[dg] = run;
@@ -224,7 +223,7 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
     for (int k = 0; k < K; ++k) {
       if (k < rows && wbase + 64 * k + lane < n) {
         const uint32_t d = (key[k] >> sh) & 255u;
-        b[sm.hist[d] + sm.woff[wave][d] + rank[k]] = key[k];
+        b[sm.hist[d] + sm.wcnt[wave][d] + rank[k]] = key[k];
       }
     }
     __syncthreads();
@@ -362,7 +361,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     // class boundaries on the decreasing sizes
     if (tid < 8) sm.flags[tid] = 0;
     __syncthreads();
-    int c_full = 0, c_big = 0, c_bm = 0, c_nz = 0;
+    uint32_t c_full = 0, c_big = 0, c_bm = 0, c_nz = 0;
     for (int i = tid; i < r; i += NT) {
       const uint32_t w = sz[i];
       c_full += w == uC;
@@ -370,10 +369,16 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
       c_bm += 2ull * w >= uC;
       c_nz += w > 0;
     }
-    if (c_full) atomicAdd(&sm.flags[1], c_full);
-    if (c_big) atomicAdd(&sm.flags[2], c_big);
-    if (c_bm) atomicAdd(&sm.flags[3], c_bm);
-    if (c_nz) atomicAdd(&sm.flags[4], c_nz);
+    c_full = wave_incl_scan_u32(c_full);
+    c_big = wave_incl_scan_u32(c_big);
+    c_bm = wave_incl_scan_u32(c_bm);
+    c_nz = wave_incl_scan_u32(c_nz);
+    if ((tid & 63) == 63) {
+      atomicAdd(&sm.flags[1], (int)c_full);
+      atomicAdd(&sm.flags[2], (int)c_big);
+      atomicAdd(&sm.flags[3], (int)c_bm);
+      atomicAdd(&sm.flags[4], (int)c_nz);
+    }
     __syncthreads();
     const int nf = sm.flags[1], nb = sm.flags[2], nm = sm.flags[3], nz = sm.flags[4];
     int32_t *sorted = d.sorted + p.ws_off;
