@@ -136,7 +136,8 @@ bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning);
  * records HIP events around each on the call's stream.  bp_ctx_stage_times
  * waits for every call made since timing was last switched on (set_timing
  * restarts the count) and returns the mean durations in milliseconds:
- * ms[0] reduction + sort + prefix (prep), ms[1] sweeps, ms[2] finalize;
+ * ms[0] reduction + sort + prefix (prep), ms[1] sweeps, ms[2] combine of
+ * split tiles + finalize;
  * *runs (optional) receives the number of calls averaged.  BP_ERR_STATE if
  * timing is off or no call was timed.  Every 64th timed call waits for the
  * oldest pending one, so long timed runs stay bounded in memory. */

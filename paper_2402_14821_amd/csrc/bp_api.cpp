@@ -167,11 +167,12 @@ bp_status Ctx::init(int dev) {
   HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
   for (auto &set : tev)
     for (hipEvent_t &e : set) HIP_TRY(hipEventCreate(&e));
-  bp_status st = counter_buf.reserve(256);
+  bp_status st = counter_buf.reserve(sizeof(unsigned long long) * kQueues * kQueueStride);
   if (st) return st;
   apply_tuning();
   grid_prep_small = num_cu * 2;
   grid_prep_large = std::max(1, num_cu / 4);
+  grid_comb = num_cu * 2;
   grid_fin = 64;
   const char *ng = getenv("BP_NO_GRAPH");
   use_graph = !(ng && ng[0] == '1');
@@ -186,7 +187,7 @@ void Ctx::destroy() {
   graph_exec = nullptr;
   graph = nullptr;
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
-                    &acc_buf, &cnt_buf, &out_buf, &red_buf})
+                    &acc_buf, &out_buf, &red_buf})
     b->release();
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (staged) (void)hipEventDestroy(staged);
@@ -215,7 +216,7 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc) {
   }
   if (graph_exec) return BP_OK;
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
+  hipError_t le = launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
                                   stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
@@ -329,15 +330,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       e.tpt = 1;
       task_cost[j] = tc / e.nchunks;
     }
-    if (e.nchunks > 1) {
-      e.acc_base = acc;
-      e.cnt_base = cnt;
-      acc += e.ntiles * tile;
-      cnt += e.ntiles;
-    }
   }
-  acc_len = acc;
-  cnt_len = cnt;
   std::vector<size_t> order(ent.size());
   for (size_t j = 0; j < order.size(); ++j) order[j] = j;
   // Longest task first, except that L2 tasks go first of all: they are cheap
@@ -348,16 +341,29 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
     if (la != lb) return la;
     return task_cost[a] > task_cost[b];
   });
-  entry_vec.resize(std::max<size_t>(ent.size(), 1));
+  std::vector<Entry> seq;
+  seq.reserve(ent.size() + 1);
+  for (size_t j : order) seq.push_back(ent[j]);
+  for (Entry &e : seq) {
+    e.split_base = cnt;
+    if (e.nchunks > 1) {
+      e.acc_base = acc;
+      acc += e.ntiles * e.nchunks * tile;
+      cnt += (e.ntiles + kSegTiles - 1) / kSegTiles;
+    }
+  }
+  acc_len = acc;
+  nsplit = cnt;
+  entry_vec.resize(std::max<size_t>(seq.size(), 1));
   memset(entry_vec.data(), 0, sizeof(Entry) * entry_vec.size());
   int64_t tb = 0;
-  for (size_t j = 0; j < order.size(); ++j) {
-    Entry e = ent[order[j]];
+  for (size_t j = 0; j < seq.size(); ++j) {
+    Entry e = seq[j];
     e.task_begin = tb;
     tb += ((e.ntiles + e.tpt - 1) / e.tpt) * e.nchunks;
     entry_vec[j] = e;
   }
-  nentries = (int64_t)ent.size();
+  nentries = (int64_t)seq.size();
   *ntasks_out = tb;
   return BP_OK;
 }
@@ -389,7 +395,6 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if ((st = keys_buf.reserve(sizeof(unsigned long long) * kNB * count))) return st;
   if ((st = ref_buf.reserve(sizeof(int32_t) * count))) return st;
   if ((st = acc_buf.reserve(sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
-  if ((st = cnt_buf.reserve(sizeof(uint32_t) * (size_t)std::max<int64_t>(cnt_len, 1)))) return st;
   char *h = (char *)stage_host.p;
   char *dv = (char *)stage_buf.p;
   LaunchDesc *d = (LaunchDesc *)h;
@@ -405,13 +410,12 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->refuted = (int32_t *)ref_buf.p;
   d->counter = (unsigned long long *)counter_buf.p;
   d->acc = (long long *)acc_buf.p;
-  d->tile_cnt = (uint32_t *)cnt_buf.p;
   d->out = out_dev;
   d->count = count;
   d->nentries = nentries;
   d->ntasks = ntasks;
   d->acc_len = acc_len;
-  d->cnt_len = cnt_len;
+  d->nsplit = nsplit;
   memcpy(h + off_plan, plan_vec.data(), sizeof(InstPlan) * (size_t)count);
   memcpy(h + off_ent, entry_vec.data(), sizeof(Entry) * entry_vec.size());
   if (host_in && host_in_len > 0) memcpy(h + off_in, host_in, sizeof(int32_t) * (size_t)host_in_len);
@@ -421,13 +425,13 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if (timing) {
     hipEvent_t *ev = nullptr;
     if ((st = timing_slot(&ev))) return st;
-    HIP_TRY(launch_pipeline_timed(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin,
+    HIP_TRY(launch_pipeline_timed(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
                                   s, ev));
   } else if (use_graph) {
     if ((st = ensure_graph(d_desc))) return st;
     HIP_TRY(hipGraphLaunch(graph_exec, s));
   } else {
-    HIP_TRY(launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_fin, s));
+    HIP_TRY(launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin, s));
   }
   return BP_OK;
 }

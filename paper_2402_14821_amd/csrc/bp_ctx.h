@@ -18,9 +18,9 @@ void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]);
 // kernels (bp_kernels.hip)
 hipError_t set_kernel_attrs();
 hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                           int grid_fin, hipStream_t s);
+                           int grid_comb, int grid_fin, hipStream_t s);
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_sweep, int grid_fin, hipStream_t s, hipEvent_t ev[4]);
+                                 int grid_sweep, int grid_comb, int grid_fin, hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
                          int64_t n, unsigned long long *loads, int32_t *out, int64_t *out_r, int32_t *out_residual,
                          int32_t *bad, hipStream_t s);
@@ -65,14 +65,14 @@ struct Ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
-  int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_fin = 0;
+  int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
   int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
-  int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, cnt_len = 0;
+  int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
   std::vector<InstPlan> plan_vec;
   std::vector<Entry> entry_vec;
 
-  DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, cnt_buf,
-      out_buf, red_buf;
+  DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, out_buf,
+      red_buf;
   HostBuf stage_host, in_host, out_host, red_host;
 
   bp_status init(int dev);

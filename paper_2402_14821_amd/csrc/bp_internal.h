@@ -15,6 +15,14 @@ namespace bpi {
 enum : int { kL1 = 0, kL2, kMT, kRAD2, kFS1, kCCM1, kVB2, kBJ1, kNB };
 
 constexpr int kWave = 64;
+// Task counters of the persistent sweep: kQueues of them, kQueueStride
+// 64-bit words (256 bytes) apart so that each sits in its own cache line and
+// memory channel.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;
+// Split tiles are combined in segments of kSegTiles consecutive tiles of one
+// entry, a block (one wave per tile) per segment.
+constexpr int kSegTiles = 8;
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
@@ -60,14 +68,16 @@ struct InstState {
 };
 
 // One (instance, bound) entry of the sweep schedule.  Its parameter range is
-// cut into tiles of 64 x (parameters per lane) parameters.  A task is either tpt consecutive tiles
-// over all items (nchunks = 1) or one of nchunks item chunks of one tile.
+// cut into tiles of 64 x (parameters per lane) parameters.  A task is either
+// tpt consecutive tiles over all items (nchunks = 1) or one of nchunks item
+// chunks of one tile ("split" tile), whose per-parameter partial sums go to a
+// slot of their own and are added up by the combine kernel.
 struct Entry {
-  int64_t task_begin;   // prefix of task counts over entries (LPT order)
+  int64_t task_begin;   // prefix of task counts over entries (schedule order)
   int64_t lam0;         // first parameter of the entry
   int64_t ntiles;
-  int64_t acc_base;     // nchunks > 1: this entry's per-parameter accumulators
-  int64_t cnt_base;     // nchunks > 1: this entry's per-tile chunk counters
+  int64_t acc_base;     // nchunks > 1: first partial-sum slot, laid out [tile][chunk][parameter]
+  int64_t split_base;   // combine segments of the entries before this one
   int32_t inst;
   int32_t bound;        // kL2 .. kBJ1
   int32_t tpt;          // tiles per task
@@ -86,15 +96,14 @@ struct LaunchDesc {
   uint32_t *av;             // per item: c - w for big items, w otherwise
   unsigned long long *keys; // [count][kNB] packed (value, parameter) maxima
   int32_t *refuted;         // [count] early-exit flags
-  unsigned long long *counter; // task counter of the persistent sweep
-  long long *acc;           // chunk accumulators (one per parameter of split tiles)
-  uint32_t *tile_cnt;       // finished chunks per split tile
+  unsigned long long *counter; // kQueues task counters of the persistent sweep, kQueueStride apart
+  long long *acc;           // partial sums of split tiles, one slot per (tile, chunk, parameter)
   bp_bounds *out;           // [count] results
   int64_t count;            // instances
   int64_t nentries;
   int64_t ntasks;
   int64_t acc_len;
-  int64_t cnt_len;
+  int64_t nsplit;           // combine segments (kSegTiles split tiles each) over all entries
 };
 
 }  // namespace bpi

@@ -433,14 +433,10 @@ __device__ void prep_finish(const LaunchDesc &d, int64_t inst) {
   d.refuted[inst] = refuted;
 }
 
-// Clears the chunk accumulators, the tile counters and the task counter of
-// the sweep that follows (run by the small-instance prep grid).
+// Clears the task counters of the sweep that follows (run by the
+// small-instance prep grid).
 __device__ void clear_sweep_state(const LaunchDesc &d) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (int64_t i = t0; i < d.acc_len; i += stride) d.acc[i] = 0;
-  for (int64_t i = t0; i < d.cnt_len; i += stride) d.tile_cnt[i] = 0;
-  if (t0 == 0) *d.counter = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < kQueues) d.counter[threadIdx.x * kQueueStride] = 0ull;
 }
 
 template <int NT, int CAP, int LARGE>
@@ -491,7 +487,17 @@ __device__ __forceinline__ int chunk_len(uint64_t maxinc) {
   return l > (1ull << 30) ? (1 << 30) : (int)l;
 }
 
-__device__ __forceinline__ int64_t ceil_div_i64(int64_t a, int64_t b) { return a / b + (a % b != 0); }
+// ceil(a / b) for 0 <= a < 2^53 and b >= 1 without a 64-bit integer division:
+// the correctly rounded fp64 quotient is within 2 of a / b, and the exact
+// remainder a - q b (no overflow: q b <= a + 2b, and q > 0 only when b <= a)
+// moves q to floor(a / b).  Every bound's numerator here is such a sum.
+__device__ __forceinline__ int64_t ceil_div_small(int64_t a, int64_t b) {
+  int64_t q = (int64_t)((double)a / (double)b);
+  int64_t r = a - q * b;
+  while (r < 0) { --q; r += b; }
+  while (r >= b) { ++q; r -= b; }
+  return q + (r != 0);
+}
 
 // Calls f(p[i]) for i in [i0, i1) in order.  Every lane uses the same item,
 // so items are read with scalar loads, 8 at a time, and the next block's
@@ -574,7 +580,7 @@ __device__ void part_mt(const TileArgs &t, const uint32_t lam[LPL], int64_t part
 
 __device__ __forceinline__ int64_t fin_mt(const TileArgs &t, int64_t lam, int64_t part) {
   const int64_t S = t.sumBig + (int64_t)(t.nm - t.nb) * (int64_t)(t.C / 2) + part;
-  return ceil_div_i64(S, (int64_t)t.C);
+  return ceil_div_small(S, (int64_t)t.C);
 }
 
 // f_RAD2 (c/4 < lambda <= c/3), from counts of threshold crossings:
@@ -614,7 +620,7 @@ __device__ void part_rad2(const TileArgs &t, const uint32_t lam[LPL], int64_t pa
 
 __device__ __forceinline__ int64_t fin_rad2(const TileArgs &t, int64_t lam, int64_t part) {
   const int64_t S = (int64_t)(t.nm - t.nf) * (int64_t)(t.C / 2) + part;
-  return ceil_div_i64(S, (int64_t)t.C);
+  return ceil_div_small(S, (int64_t)t.C);
 }
 
 // f_FS1 (1 <= lambda <= 100): with n = w (lambda + 1) and q = floor(n / c),
@@ -643,7 +649,7 @@ __device__ void part_fs1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
 }
 
 __device__ __forceinline__ int64_t fin_fs1(const TileArgs &t, int64_t lam, int64_t part) {
-  return ceil_div_i64(part, (int64_t)t.C * lam);
+  return ceil_div_small(part, (int64_t)t.C * lam);
 }
 
 // f_CCM1 (1 <= lambda <= c/2), K = floor(c / lambda):
@@ -673,9 +679,9 @@ __device__ void part_ccm1(const TileArgs &t, const uint32_t lam[LPL], int64_t pa
 }
 
 __device__ __forceinline__ int64_t fin_ccm1(const TileArgs &t, int64_t lam, int64_t part) {
-  const int64_t K = (int64_t)t.C / lam;
+  const int64_t K = (int64_t)((uint32_t)t.C / (uint32_t)lam);
   const int64_t S = 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
-  return ceil_div_i64(S, 2 * K);
+  return ceil_div_small(S, 2 * K);
 }
 
 // f_VB2 (2 <= lambda <= c), h(a) = ceil(a lambda / c) - 1 for a >= 1:
@@ -707,7 +713,7 @@ __device__ void part_vb2(const TileArgs &t, const uint32_t lam[LPL], int64_t par
 __device__ __forceinline__ int64_t fin_vb2(const TileArgs &t, int64_t lam, int64_t part) {
   const int64_t K = lam - 1;
   const int64_t S = 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
-  return ceil_div_i64(S, 2 * K);
+  return ceil_div_small(S, 2 * K);
 }
 
 // f_BJ1 (1 <= lambda <= c), p = c mod lambda, q = floor(w / lambda),
@@ -754,11 +760,12 @@ __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
 }
 
 __device__ __forceinline__ int64_t fin_bj1(const TileArgs &t, int64_t lam, int64_t part) {
-  const int64_t p = (int64_t)t.C % lam;
+  const uint32_t c32 = (uint32_t)t.C, l32 = (uint32_t)lam;
+  const int64_t p = (int64_t)(c32 % l32);
   const int64_t n = t.nz - t.nf;
-  const int64_t S = (part + t.sumNZ - n * p) / 2;
-  const int64_t fc = ((int64_t)t.C / lam) * (lam - p);
-  return ceil_div_i64(S, fc);
+  const int64_t S = (part + t.sumNZ - n * p) >> 1;  // the sum is even and >= 0
+  const int64_t fc = (int64_t)(c32 / l32) * (lam - p);
+  return ceil_div_small(S, fc);
 }
 
 __device__ __forceinline__ int64_t fin_bound(int bound, const TileArgs &t, int64_t lam, int64_t part) {
@@ -821,7 +828,31 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL
     const int64_t s2 = t.pre[nbig] - t.pre[n1];
     const int64_t s3 = j3 > nbig ? t.pre[j3] - t.pre[nbig] : 0;
     const int64_t x = s3 - (C * n2 - s2);
-    lbp[j] = nbig + (x > 0 ? ceil_div_i64(x, C) : 0);
+    lbp[j] = nbig + (x > 0 ? ceil_div_small(x, C) : 0);
+  }
+}
+
+// Largest packed key of a tile (0 if no lane holds a parameter of the range),
+// valid in every lane.
+template <int LPL>
+__device__ __forceinline__ uint64_t tile_max(const int64_t lam[LPL], const int64_t lbp[LPL], const bool ok[LPL]) {
+  uint64_t key = 0;
+  for (int j = 0; j < LPL; ++j)
+    if (ok[j]) key = umax64(key, pack_key(lbp[j], lam[j]));
+  return wave_max_u64(key);
+}
+
+// Folds a key into the instance's maximum for the bound and raises the
+// early-exit flag when the bound refutes the instance.  Keys only grow: a key
+// that does not beat the current one leaves it alone.
+__device__ __forceinline__ void publish_key(const LaunchDesc &d, int64_t inst, int bound, const TileArgs &t,
+                                            uint64_t key, bool early) {
+  if (!key) return;
+  unsigned long long *kp = &d.keys[inst * kNB + bound];
+  if (key > __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(kp, (unsigned long long)key);
+  if (early) {
+    const int64_t v = (int64_t)(key >> 32) + (bound == kL2 ? 0 : t.nf);
+    if (v > t.k) __hip_atomic_store(&d.refuted[inst], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -829,17 +860,8 @@ template <int LPL>
 __device__ __forceinline__ void flush_tile(const LaunchDesc &d, int64_t inst, int bound, const TileArgs &t,
                                            const int64_t lam[LPL], const int64_t lbp[LPL], const bool ok[LPL],
                                            bool early) {
-  uint64_t key = 0;
-  for (int j = 0; j < LPL; ++j)
-    if (ok[j]) key = umax64(key, pack_key(lbp[j], lam[j]));
-  const uint64_t wmax = wave_max_u64(key);
-  if (lane_id() == 0 && wmax) {
-    atomicMax(&d.keys[inst * kNB + bound], (unsigned long long)wmax);
-    if (early) {
-      const int64_t v = (int64_t)(wmax >> 32) + (bound == kL2 ? 0 : t.nf);
-      if (v > t.k) __hip_atomic_store(&d.refuted[inst], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  const uint64_t wmax = tile_max<LPL>(lam, lbp, ok);
+  if (lane_id() == 0) publish_key(d, inst, bound, t, wmax, early);
 }
 
 __device__ __forceinline__ int64_t find_entry(const BP_CONST Entry *e, int64_t n, uint64_t task) {
@@ -852,15 +874,14 @@ __device__ __forceinline__ int64_t find_entry(const BP_CONST Entry *e, int64_t n
 }
 
 
-template <int LPL>
-__device__ void run_task(const LaunchDesc &d, uint64_t task) {
-  const BP_CONST Entry &e = as_const(d.entries)[find_entry(as_const(d.entries), d.nentries, task)];
+// The tile arguments of one (instance, bound) entry; false when the
+// instance failed in prep.
+__device__ __forceinline__ bool entry_args(const LaunchDesc &d, const BP_CONST Entry &e, TileArgs &t, bool &early) {
   const int64_t inst = e.inst;
   const BP_CONST InstState &st = as_const(d.state)[inst];
-  if (st.status != BP_OK) return;
+  if (st.status != BP_OK) return false;
   const BP_CONST InstPlan &p = as_const(d.plan)[inst];
   const int bound = e.bound;
-  TileArgs t;
   t.wv = as_const((const uint32_t *)d.sorted + p.ws_off);
   t.av = as_const((const uint32_t *)d.av + p.ws_off);
   t.sorted = as_global(d.sorted + p.ws_off);
@@ -876,7 +897,23 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   t.nz = st.nz;
   t.sumBig = st.sumBig;
   t.sumNZ = st.sumNZ;
-  const bool early = (p.flags & kPlanEarlyExit) != 0;
+  early = (p.flags & kPlanEarlyExit) != 0;
+  return true;
+}
+
+__device__ __forceinline__ bool refuted_now(const LaunchDesc &d, int64_t inst) {
+  return __builtin_amdgcn_readfirstlane(
+             __hip_atomic_load(&d.refuted[inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0;
+}
+
+template <int LPL>
+__device__ void run_task(const LaunchDesc &d, uint64_t task) {
+  const BP_CONST Entry &e = as_const(d.entries)[find_entry(as_const(d.entries), d.nentries, task)];
+  const int64_t inst = e.inst;
+  const int bound = e.bound;
+  TileArgs t;
+  bool early;
+  if (!entry_args(d, e, t, early)) return;
   const int64_t local = (int64_t)task - e.task_begin;
   const int32_t nch = e.nchunks;
   const int64_t tile0 = (local / nch) * e.tpt;
@@ -887,9 +924,7 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   t.i1 = t.nf + (int32_t)(span * (chunk + 1) / nch);
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
-    if (early && __builtin_amdgcn_readfirstlane(
-                     __hip_atomic_load(&d.refuted[inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-      return;
+    if (early && refuted_now(d, inst)) return;
     t.lam0 = e.lam0 + tl * (64 * LPL);
     int64_t lam[LPL], lbp[LPL];
     bool ok[LPL];
@@ -911,49 +946,121 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       case kVB2: part_vb2<LPL>(t, l32, part); break;
       default: part_bj1<LPL>(t, l32, part); break;
     }
-    for (int j = 0; j < LPL; ++j) ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
     if (nch > 1) {
-      // Add this chunk's parts; the wave that completes the tile finalises
-      // it.  The parts and the tile counter are only ever touched by
-      // device-scope atomic read-modify-writes, which the device performs at
-      // its coherence point, past the per-XCD L2 caches.  Waiting for this
-      // wave's adds to be acknowledged before it bumps the counter therefore
-      // orders them for the wave that reads the final count, and no cache
-      // write-back or invalidation (a device-scope fence) is needed.
-      long long *acc = d.acc + e.acc_base + (tl * (64 * LPL));
-      for (int j = 0; j < LPL; ++j)
-        if (ok[j])
-          __hip_atomic_fetch_add((unsigned long long *)&acc[lane_id() + 64 * j], (unsigned long long)part[j],
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      uint32_t prev = 0;
-      if (lane_id() == 0)
-        prev = __hip_atomic_fetch_add(&d.tile_cnt[e.cnt_base + tl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)prev);
-      if (prev != (uint32_t)(nch - 1)) continue;
-      for (int j = 0; j < LPL; ++j)
-        part[j] = ok[j] ? (int64_t)__hip_atomic_fetch_add((unsigned long long *)&acc[lane_id() + 64 * j], 0ull,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                        : 0;
+      // A chunk of a split tile: store its partial sums in its own slot (no
+      // other wave touches it) and move on; the combine kernel adds the
+      // chunks of the tile once the sweep is over.
+      long long *slot = d.acc + e.acc_base + (tl * nch + chunk) * (64 * LPL);
+      for (int j = 0; j < LPL; ++j) slot[lane_id() + 64 * j] = (long long)part[j];
+      continue;
     }
-    for (int j = 0; j < LPL; ++j) lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
+    for (int j = 0; j < LPL; ++j) {
+      ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
+      lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
+    }
     flush_tile<LPL>(d, inst, bound, t, lam, lbp, ok, early);
   }
 }
 
-// Persistent sweep: wave b starts with task b, then takes tasks from one
-// atomic counter (offset by the grid size) until none is left.
+// Split tiles, in segments of kSegTiles consecutive tiles of one entry: a
+// block per segment, a wave per tile.  A wave adds the chunks' partial sums
+// of its tile (in chunk order; integer sums, so the order does not change
+// them) and finalises the tile; the block takes the maximum of its waves and
+// publishes it once, so the tiles of one bound do not queue on its key.
+// Tiles whose chunks did not all run -- the instance failed in prep, was
+// refuted early, or the tile lies past the effective range -- are skipped by
+// the same tests the sweep applied.
+template <int LPL>
+__global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__restrict__ dp) {
+  __shared__ unsigned long long wkey[kSegTiles];
+  const LaunchDesc d = *as_const(dp);
+  const int wave = threadIdx.x >> 6;
+  for (int64_t sg = blockIdx.x; sg < d.nsplit; sg += gridDim.x) {
+    // the entry holding segment sg: the last one with split_base <= sg (an
+    // entry without split tiles shares its split_base with the next entry
+    // that has some, so the search always lands on a split entry)
+    const BP_CONST Entry *es = as_const(d.entries);
+    int64_t lo = 0, hi = d.nentries - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (es[mid].split_base <= sg) lo = mid; else hi = mid - 1;
+    }
+    const BP_CONST Entry &e = es[lo];
+    TileArgs t;
+    bool early;
+    if (!entry_args(d, e, t, early)) continue;  // the same for the whole block
+    const int64_t tl = (sg - e.split_base) * kSegTiles + wave;
+    t.lam0 = e.lam0 + tl * (64 * LPL);
+    uint64_t key = 0;
+    if (tl < e.ntiles && t.lam0 <= t.hi && !(early && refuted_now(d, e.inst))) {
+      const int32_t nch = e.nchunks;
+      const long long *slots = d.acc + e.acc_base + tl * nch * (64 * LPL);
+      int64_t lam[LPL], lbp[LPL], part[LPL];
+      bool ok[LPL];
+      uint32_t l32[LPL];
+      tile_lams<LPL>(t, lam, l32);
+      for (int j = 0; j < LPL; ++j) part[j] = 0;
+      // four chunks' loads in flight at a time
+      int32_t c = 0;
+      for (; c + 4 <= nch; c += 4) {
+        long long v[4][LPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          for (int j = 0; j < LPL; ++j) v[u][j] = slots[(c + u) * (64 * LPL) + lane_id() + 64 * j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          for (int j = 0; j < LPL; ++j) part[j] += v[u][j];
+      }
+      for (; c < nch; ++c)
+        for (int j = 0; j < LPL; ++j) part[j] += slots[c * (64 * LPL) + lane_id() + 64 * j];
+      for (int j = 0; j < LPL; ++j) {
+        ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
+        lbp[j] = ok[j] ? fin_bound(e.bound, t, lam[j], part[j]) : 0;
+      }
+      key = tile_max<LPL>(lam, lbp, ok);
+    }
+    if (lane_id() == 0) wkey[wave] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t m = 0;
+      for (int w = 0; w < kSegTiles; ++w) m = umax64(m, wkey[w]);
+      publish_key(d, e.inst, e.bound, t, m, early);
+    }
+    __syncthreads();
+  }
+}
+
+// Persistent sweep.  Wave b runs task b first; the tasks past the grid are
+// dealt round-robin to kQueues queues (task grid + q + kQueues c is claim c
+// of queue q), each with its own counter.  A wave claims from the queue of
+// its own XCD first (blocks are dispatched to the XCDs round-robin) and from
+// the others once that one is exhausted, so no single counter serialises
+// every claim of the launch.  Every wave leaves when all queues are empty.
 template <int LPL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep(const LaunchDesc *__restrict__ dp) {
   const LaunchDesc d = *as_const(dp);
+  const uint64_t ntasks = (uint64_t)d.ntasks;
+  const uint64_t grid = gridDim.x;
+  const int home = (int)(blockIdx.x % kQueues);
+  uint32_t empty = 0;  // queues this wave found exhausted
   uint64_t task = blockIdx.x;
-  while (task < (uint64_t)d.ntasks) {
+  while (task < ntasks) {
     run_task<LPL>(d, task);
-    unsigned long long nxt = 0;
-    if (lane_id() == 0) nxt = atomicAdd(d.counter, 1ull);
-    nxt = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nxt) |
-          ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(nxt >> 32)) << 32);
-    task = (uint64_t)gridDim.x + nxt;
+    task = ntasks;
+    for (int k = 0; k < kQueues; ++k) {
+      const int q = (home + k) % kQueues;
+      if ((empty >> q) & 1u) continue;
+      unsigned long long c = 0;
+      if (lane_id() == 0) c = atomicAdd(&d.counter[q * kQueueStride], 1ull);
+      c = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)c) |
+          ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(c >> 32)) << 32);
+      const uint64_t t = grid + (uint64_t)q + (uint64_t)kQueues * c;
+      if (t < ntasks) {
+        task = t;
+        break;
+      }
+      empty |= 1u << q;
+    }
   }
 }
 
@@ -1089,8 +1196,17 @@ static hipError_t launch_sweep(const LaunchDesc *d_desc, int lpl, int grid_sweep
   return hipGetLastError();
 }
 
+static hipError_t launch_combine(const LaunchDesc *d_desc, int lpl, int grid_comb, hipStream_t s) {
+  switch (lpl) {
+    case 1: hipLaunchKernelGGL(k_combine<1>, dim3(grid_comb), dim3(64 * kSegTiles), 0, s, d_desc); break;
+    case 4: hipLaunchKernelGGL(k_combine<4>, dim3(grid_comb), dim3(64 * kSegTiles), 0, s, d_desc); break;
+    default: hipLaunchKernelGGL(k_combine<2>, dim3(grid_comb), dim3(64 * kSegTiles), 0, s, d_desc); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                           int grid_fin, hipStream_t s) {
+                           int grid_comb, int grid_fin, hipStream_t s) {
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
                      prep_smem_small(), s, d_desc);
   hipError_t e = hipGetLastError();
@@ -1099,13 +1215,14 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_smal
                      prep_smem_large(), s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
+  if ((e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   return hipGetLastError();
 }
 
 // The same launches with events around the stages (diagnostic timing).
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_sweep, int grid_fin, hipStream_t s, hipEvent_t ev[4]) {
+                                 int grid_sweep, int grid_comb, int grid_fin, hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipEventRecord(ev[0], s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
@@ -1117,6 +1234,7 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_pre
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+  if ((e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipEventRecord(ev[3], s);
