@@ -73,6 +73,18 @@ typedef struct bp_sweep {
  * accumulates in 64 bits and needs no cut. */
 #define BP_SWEEP_PAPER_VB2_CLAMP 1u
 
+/* flags of bp_sweep: compute the MT and BJ1 sums over most of their
+ * parameters from threshold sums of the sorted sizes instead of one
+ * evaluation per (item, parameter).  With U(t) = sum_w max(0, w - t) over
+ * the sizes 0 < w < c and K = floor(c / lambda), the BJ1 sum of Sec. 3.1 is
+ * exactly sum_{m=1..K} U(c - m lambda) - sum_{j=1..K} U(j lambda); the MT sum
+ * is a sum of the sizes on either side of lambda (small sizes) or of
+ * c - lambda (big sizes).  The results are the same integers as without the
+ * flag; only the work per parameter changes (about 2K threshold sums
+ * instead of r evaluations; parameters with large K stay dense).  bp_bounds
+ * .evals still counts r * (sum of range sizes). */
+#define BP_SWEEP_SEGMENTS 2u
+
 /* Result of one check.  value[b] is the bound, argmax_lambda[b] the smallest
  * parameter attaining it (-1 for L1 and for an empty range).  lb is the
  * maximum over the collection, lb_arg the first bound attaining it, verdict
@@ -177,6 +189,9 @@ bp_status bp_lower_bounds_dev(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *
  * some value > m).  verdict and lb may be NULL; bounds (optional) receives
  * the full record. */
 #define BP_NO_EARLY_EXIT 1u
+/* flags of bp_feasible, bp_feasible_dev and bp_request: the sums as with
+ * BP_SWEEP_SEGMENTS (same results, less work). */
+#define BP_SEGMENTS 2u
 bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *unpacked,
                       int64_t n, uint32_t flags, int32_t *verdict, int64_t *lb, bp_bounds *bounds);
 
@@ -229,7 +244,7 @@ typedef struct bp_request {
   const int32_t *residual; /* m entries */
   const int32_t *unpacked; /* n entries */
   uint64_t tag;            /* caller's value, returned in the result */
-  uint32_t flags;          /* BP_NO_EARLY_EXIT */
+  uint32_t flags;          /* BP_NO_EARLY_EXIT | BP_SEGMENTS */
   uint32_t reserved;
 } bp_request;
 

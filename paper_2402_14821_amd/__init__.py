@@ -25,7 +25,9 @@ BP_L1, BP_L2, BP_MT, BP_RAD2, BP_FS1, BP_CCM1, BP_VB2, BP_BJ1 = range(8)
 BP_NB = 8
 BOUND_NAMES = ("L1", "L2", "MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1")
 BP_SWEEP_PAPER_VB2_CLAMP = 1
+BP_SWEEP_SEGMENTS = 2
 BP_NO_EARLY_EXIT = 1
+BP_SEGMENTS = 2
 BP_MAX_ITEMS = 1 << 22
 BP_MAX_BATCH = 1 << 20
 

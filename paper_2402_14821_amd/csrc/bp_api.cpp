@@ -146,7 +146,8 @@ static bp_status check_sweep(int32_t C, const bp_sweep *sw, int64_t lo[kNB], int
       return fail(BP_ERR_RANGE, "sweep range of bound %d [%lld, %lld] outside [%lld, %lld] for C=%d", b,
                   (long long)lo[b], (long long)hi[b], (long long)dlo[b], (long long)dhi[b], C);
   }
-  if (sw && (sw->flags & ~BP_SWEEP_PAPER_VB2_CLAMP)) return fail(BP_ERR_ARG, "unknown bp_sweep flags 0x%x", sw->flags);
+  if (sw && (sw->flags & ~(BP_SWEEP_PAPER_VB2_CLAMP | BP_SWEEP_SEGMENTS)))
+    return fail(BP_ERR_ARG, "unknown bp_sweep flags 0x%x", sw->flags);
   return BP_OK;
 }
 
@@ -176,6 +177,10 @@ bp_status Ctx::init(int dev) {
   grid_fin = 64;
   const char *ng = getenv("BP_NO_GRAPH");
   use_graph = !(ng && ng[0] == '1');
+  // BP_SEGMENT_KCUT=K: segment tiles of BJ1 wherever floor(c / lambda) <= K
+  // (0 .. 64) instead of where the cost model puts the cut; same results.
+  const char *kc = getenv("BP_SEGMENT_KCUT");
+  if (kc && kc[0]) seg_kcut = std::min(std::max(atoi(kc), 0), (int)kSegMaxK);
   return BP_OK;
 }
 
@@ -187,7 +192,7 @@ void Ctx::destroy() {
   graph_exec = nullptr;
   graph = nullptr;
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
-                    &acc_buf, &out_buf, &red_buf})
+                    &acc_buf, &out_buf, &red_buf, &bidx_buf})
     b->release();
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (staged) (void)hipEventDestroy(staged);
@@ -248,7 +253,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   const int64_t count = (int64_t)pin.size();
   std::vector<InstPlan> &pl = plan_vec;
   pl.assign((size_t)count, InstPlan{});
-  int64_t ws = 0, pre = 0;
+  int64_t ws = 0, pre = 0, bidx = 0;
   std::vector<Entry> ent;
   std::vector<double> tile_cost_v;
   std::vector<int64_t> rcap_v;
@@ -277,36 +282,91 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
     p.pre_off = pre;
     ws += std::max<int64_t>(rcap, 1);
     pre += rcap + 1;
+    // Threshold table of the segment sums: buckets of width 2^bshift over
+    // [0, C + 1], about four sizes per bucket when the sizes spread evenly.
+    int64_t bw = 1;
+    if (q.segments) {
+      int32_t sh = 0;
+      while (((int64_t)q.C >> sh) > std::max<int64_t>(rcap / 4, 1)) ++sh;
+      p.flags |= kPlanSegments;
+      p.bshift = sh;
+      p.nbk = (int32_t)((((int64_t)q.C + 1) >> sh) + 2);
+      p.bidx_off = bidx;
+      bidx += p.nbk;
+      bw = 1ll << sh;
+    }
     for (int b = 0; b < kNB; ++b) {
       p.lo[b] = q.lo[b];
       p.hi[b] = q.hi[b];
     }
+    auto push = [&](Entry e, double tc) {
+      total += tc * (double)e.ntiles;
+      ent.push_back(e);
+      tile_cost_v.push_back(tc);
+      rcap_v.push_back(rcap);
+    };
+    const double dens = (double)std::max<int64_t>(rcap, 1) / (double)q.C;  // sizes per unit of capacity
     for (int b = kL2; b < kNB; ++b) {
       if (q.lo[b] > q.hi[b]) continue;
       Entry e;
       memset(&e, 0, sizeof e);
       e.inst = (int32_t)i;
       e.bound = b;
-      double tc;
+      e.mode = kModeDense;
       if (b == kL2) {
         const int64_t cand = 2 * rcap + 1;
         e.lam0 = 0;
         e.ntiles = (cand + tile - 1) / tile;
-        tc = (double)tile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0);
-      } else {
-        const int64_t nl = q.hi[b] - q.lo[b] + 1;
-        e.lam0 = q.lo[b];
-        e.ntiles = (nl + tile - 1) / tile;
-        tc = (double)tile * ((double)rcap * unit_cost(b) + 60.0);
+        push(e, (double)tile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0));
+        continue;
       }
-      total += tc * (double)e.ntiles;
-      ent.push_back(e);
-      tile_cost_v.push_back(tc);
-      rcap_v.push_back(rcap);
+      const double dense_tc = (double)tile * ((double)rcap * unit_cost(b) + 60.0);
+      if (q.segments && b == kMT) {
+        // two windows per tile (small sizes around lambda, big ones around
+        // c - lambda), each about (tile + bucket) sizes long
+        e.mode = kModeSegments;
+        e.lam0 = q.lo[b];
+        e.ntiles = (q.hi[b] - q.lo[b] + tile) / tile;
+        push(e, (double)tile * (2.0 * ((double)(tile + bw) * dens * 2.0 + 30.0)) + 400.0);
+        continue;
+      }
+      if (q.segments && b == kBJ1) {
+        // A tile whose smallest parameter is lambda has K = floor(c / lambda)
+        // and 2K windows of about (tile j + bucket) sizes; it is cheaper than
+        // r dense evaluations while K <= kcut.
+        int64_t kcut = 0;
+        for (int64_t K = 1; K <= kSegMaxK; ++K) {
+          const double seg = 2.0 * (((double)tile * K * K / 2.0 + (double)bw * K) * dens + 30.0 * K);
+          if (seg > (double)rcap * unit_cost(b)) break;
+          kcut = K;
+        }
+        if (seg_kcut >= 0) kcut = seg_kcut;
+        const int64_t lstar = kcut > 0 ? (int64_t)q.C / (kcut + 1) + 1 : q.hi[b] + 1;  // K(lambda) <= kcut from here
+        const int64_t ndense = std::max<int64_t>(0, (std::min(lstar, q.hi[b] + 1) - q.lo[b] + tile - 1) / tile);
+        if (ndense > 0) {
+          e.lam0 = q.lo[b];
+          e.ntiles = ndense;
+          push(e, dense_tc);
+        }
+        const int64_t s0 = q.lo[b] + ndense * tile;
+        if (s0 <= q.hi[b]) {
+          e.mode = kModeSegments;
+          e.lam0 = s0;
+          e.ntiles = (q.hi[b] - s0 + tile) / tile;
+          const double kmid = std::max(1.0, (double)q.C / (0.5 * (double)(s0 + q.hi[b])));
+          push(e, (double)tile * (60.0 * kmid + ((double)tile * kmid * kmid + 2.0 * (double)bw * kmid) * dens) + 400.0);
+        }
+        continue;
+      }
+      const int64_t nl = q.hi[b] - q.lo[b] + 1;
+      e.lam0 = q.lo[b];
+      e.ntiles = (nl + tile - 1) / tile;
+      push(e, dense_tc);
     }
   }
   ws_items = ws;
   pre_items = pre;
+  bidx_items = bidx;
   // Task size: about tasks_per_wave tasks per resident wave over the whole
   // launch.  A tile cheaper than that is grouped with its neighbours; a dearer
   // one is split into item chunks of at least min_chunk items.
@@ -317,7 +377,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   for (size_t j = 0; j < ent.size(); ++j) {
     Entry &e = ent[j];
     const double tc = tile_cost_v[j];
-    if (tc <= target || e.bound == kL2) {
+    if (tc <= target || e.bound == kL2 || e.mode == kModeSegments) {
       double tpt = std::floor(target / tc);
       tpt = std::min(std::max(tpt, 1.0), std::min((double)e.ntiles, 1e9));
       e.tpt = (int32_t)tpt;
@@ -395,6 +455,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if ((st = keys_buf.reserve(sizeof(unsigned long long) * kNB * count))) return st;
   if ((st = ref_buf.reserve(sizeof(int32_t) * count))) return st;
   if ((st = acc_buf.reserve(sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
+  if ((st = bidx_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bidx_items, 1)))) return st;
   char *h = (char *)stage_host.p;
   char *dv = (char *)stage_buf.p;
   LaunchDesc *d = (LaunchDesc *)h;
@@ -410,6 +471,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->refuted = (int32_t *)ref_buf.p;
   d->counter = (unsigned long long *)counter_buf.p;
   d->acc = (long long *)acc_buf.p;
+  d->bidx = (int32_t *)bidx_buf.p;
   d->out = out_dev;
   d->count = count;
   d->nentries = nentries;
@@ -454,7 +516,7 @@ const char *bp_last_error(void) { return bpi::g_err.c_str(); }
 bp_status bp_default_sweep(int32_t C, int64_t r, int32_t max_w, uint32_t flags, bp_sweep *out) {
   if (!out) return fail(BP_ERR_ARG, "out is NULL");
   if (C < 1) return fail(BP_ERR_ARG, "C = %d < 1", C);
-  if (flags & ~BP_SWEEP_PAPER_VB2_CLAMP) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BP_SWEEP_PAPER_VB2_CLAMP | BP_SWEEP_SEGMENTS)) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
   if (r < 0 || max_w < 0) return fail(BP_ERR_ARG, "negative r or max_w");
   memset(out, 0, sizeof *out);
   default_ranges(C, out->lo, out->hi);
@@ -709,7 +771,7 @@ bp_status run_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<con
 }
 
 bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,
-                       bool early, PlanIn *q) {
+                       bool early, PlanIn *q, bool segments) {
   if (C < 1) return fail(BP_ERR_ARG, "C = %d < 1", C);
   if (k < 0) return fail(BP_ERR_ARG, "k = %lld < 0", (long long)k);
   if (n_in < 0 || m_res < 0) return fail(BP_ERR_ARG, "negative count");
@@ -722,6 +784,7 @@ bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_
   q->form = form;
   q->early_exit = early;
   q->clamp = sw && (sw->flags & BP_SWEEP_PAPER_VB2_CLAMP);
+  q->segments = segments || (sw && (sw->flags & BP_SWEEP_SEGMENTS));
   return check_sweep(C, sw, q->lo, q->hi);
 }
 
@@ -769,9 +832,11 @@ bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
   if ((m > 0 && !residual) || (n > 0 && !unpacked)) return fail(BP_ERR_ARG, "NULL input array");
-  if (flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BP_NO_EARLY_EXIT | BP_SEGMENTS)) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
   std::vector<PlanIn> pin(1);
-  if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0]))) return st;
+  if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0],
+                         (flags & BP_SEGMENTS) != 0)))
+    return st;
   if ((st = host_validate_items(C, unpacked, n))) return st;
   if ((st = host_validate_items(C, residual, m))) return st;
   bp_bounds o;
@@ -788,9 +853,11 @@ bp_status bp_feasible_dev(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *d_re
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
   if (!d_out || (m > 0 && !d_residual) || (n > 0 && !d_unpacked)) return fail(BP_ERR_ARG, "NULL argument");
-  if (flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BP_NO_EARLY_EXIT | BP_SEGMENTS)) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
   std::vector<PlanIn> pin(1);
-  if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0]))) return st;
+  if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0],
+                         (flags & BP_SEGMENTS) != 0)))
+    return st;
   // both arrays are addressed from the unpacked base: residual offset in elements
   const ptrdiff_t diff = (m > 0 && n > 0) ? (d_residual - d_unpacked) : 0;
   const int32_t *base = n > 0 ? d_unpacked : d_residual;
@@ -864,11 +931,12 @@ bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, 
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
   if ((st = check_batch(batch))) return st;
-  if (flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(BP_NO_EARLY_EXIT | BP_SEGMENTS)) return fail(BP_ERR_ARG, "unknown flags 0x%x", flags);
   if (batch->count == 0) return BP_OK;
   if (!batch->items) return fail(BP_ERR_ARG, "NULL items");
   std::vector<PlanIn> pin;
   if ((st = batch_plan_in(batch, nullptr, !(flags & BP_NO_EARLY_EXIT), pin))) return st;
+  for (PlanIn &q : pin) q.segments = (flags & BP_SEGMENTS) != 0;
   std::vector<const int32_t *> a(batch->count), b(batch->count, nullptr);
   for (int32_t i = 0; i < batch->count; ++i) {
     a[i] = batch->items + batch->off[i];

@@ -44,7 +44,7 @@ struct PlanIn {
   int64_t in_off, res_off, n_in, k;
   int64_t lo[kNB], hi[kNB];
   int32_t m_res, C, form;
-  bool early_exit, clamp;
+  bool early_exit, clamp, segments;
 };
 
 struct Ctx {
@@ -55,6 +55,7 @@ struct Ctx {
   hipEvent_t staged = nullptr;  // staging buffers consumed by the device
   hipEvent_t done = nullptr;
   bool use_graph = true;
+  int seg_kcut = -1;  // BJ1 segment tiles for K <= seg_kcut; -1: chosen by the cost model
   bool timing = false;
   // Stage timing: one set of 4 events per timed run, reused round-robin; a
   // set is folded into the sums (waiting for it) before it is reused.
@@ -67,12 +68,12 @@ struct Ctx {
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
   int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
-  int64_t ws_items = 0, pre_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
+  int64_t ws_items = 0, pre_items = 0, bidx_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
   std::vector<InstPlan> plan_vec;
   std::vector<Entry> entry_vec;
 
   DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, out_buf,
-      red_buf;
+      red_buf, bidx_buf;
   HostBuf stage_host, in_host, out_host, red_host;
 
   bp_status init(int dev);
@@ -89,7 +90,7 @@ struct Ctx {
 };
 
 bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,
-                       bool early, PlanIn *q);
+                       bool early, PlanIn *q, bool segments = false);
 bp_status host_validate_items(int32_t C, const int32_t *items, int64_t r);
 bp_status launch_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<const int32_t *> &src_a,
                             const std::vector<const int32_t *> &src_b);

@@ -23,6 +23,8 @@ constexpr int kQueueStride = 32;
 // Split tiles are combined in segments of kSegTiles consecutive tiles of one
 // entry, a block (one wave per tile) per segment.
 constexpr int kSegTiles = 8;
+// Largest K = floor(c / lambda) a segment tile of BJ1 handles (2K windows).
+constexpr int kSegMaxK = 64;
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
@@ -45,11 +47,19 @@ struct InstPlan {
   int32_t C;
   int32_t form;
   int32_t r_cap;     // n_in + m_res: upper bound of the reduced count
-  uint32_t flags;    // kPlanClampVB2 | kPlanEarlyExit
+  uint32_t flags;    // kPlanClampVB2 | kPlanEarlyExit | kPlanSegments
   int32_t large;     // 1: prepared by the large-instance block
+  int32_t bshift;    // kPlanSegments: bucket width 2^bshift of the threshold table
+  int32_t nbk;       // kPlanSegments: entries of the threshold table
+  int64_t bidx_off;  // kPlanSegments: offset of the threshold table
 };
 constexpr uint32_t kPlanClampVB2 = 1u;
 constexpr uint32_t kPlanEarlyExit = 2u;
+constexpr uint32_t kPlanSegments = 4u;
+
+// How an entry's tiles compute their sums: one evaluation per (item,
+// parameter), or threshold sums over windows of the sorted sizes.
+enum : int32_t { kModeDense = 0, kModeSegments = 1 };
 
 // Per-instance state, written by the prep kernel.
 struct InstState {
@@ -82,6 +92,8 @@ struct Entry {
   int32_t bound;        // kL2 .. kBJ1
   int32_t tpt;          // tiles per task
   int32_t nchunks;      // item chunks per tile
+  int32_t mode;         // kModeDense or kModeSegments (never split into chunks)
+  int32_t pad;
 };
 
 struct LaunchDesc {
@@ -98,6 +110,7 @@ struct LaunchDesc {
   int32_t *refuted;         // [count] early-exit flags
   unsigned long long *counter; // kQueues task counters of the persistent sweep, kQueueStride apart
   long long *acc;           // partial sums of split tiles, one slot per (tile, chunk, parameter)
+  int32_t *bidx;            // threshold tables: bidx[b] = #{sorted sizes >= b 2^bshift}
   bp_bounds *out;           // [count] results
   int64_t count;            // instances
   int64_t nentries;

@@ -358,6 +358,21 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     uint32_t *sz = sm.keys[res_buf ^ 1];
     for (int i = tid; i < r; i += NT) sz[i] = uC - keys[i];
     __syncthreads();
+    if (p.flags & kPlanSegments) {
+      // threshold table of the segment sums: bidx[b] = #{sizes >= b 2^bshift},
+      // a binary search over the decreasing sizes in LDS per entry
+      int32_t *bidx = d.bidx + p.bidx_off;
+      const int sh = p.bshift;
+      for (int b = tid; b < p.nbk; b += NT) {
+        const uint64_t v = (uint64_t)b << sh;
+        int lo = 0, hi = (int)r;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((uint64_t)sz[mid] >= v) lo = mid + 1; else hi = mid;
+        }
+        bidx[b] = lo;
+      }
+    }
     // class boundaries on the decreasing sizes
     if (tid < 8) sm.flags[tid] = 0;
     __syncthreads();
@@ -477,6 +492,9 @@ struct TileArgs {
   int32_t C, r, nf, nb, nm, nz;
   int32_t i0, i1;        // streamed item range of this chunk, inside [nf, nz)
   int64_t sumBig, sumNZ;
+  const BP_CONST int32_t *bidx;  // threshold table (segment entries)
+  const BP_CONST int64_t *prec;  // prefix sums again, for scalar loads
+  int32_t bsh;                   // bucket width 2^bsh of the table
 };
 
 // Largest number of items whose per-item increments, each at most maxinc,
@@ -768,6 +786,118 @@ __device__ __forceinline__ int64_t fin_bj1(const TileArgs &t, int64_t lam, int64
   return ceil_div_small(S, fc);
 }
 
+// ---------------------------------------------------------------------------
+// Segment sums.  The table bidx[b] = #{sizes >= b B}, B = 2^bsh, over the
+// decreasing sizes bounds where a threshold falls: every size before
+// pos_ge(v) is >= v, every size from pos_lt(v) on is < v.  A tile's
+// parameters are consecutive, so for each threshold family the thresholds
+// of its lanes lie in one window [tlo, thi], and only the sizes between
+// pos_ge(thi + 1) and pos_lt(tlo + 1) need a per-lane test; the sizes
+// before count in full, those after not at all.
+
+__device__ __forceinline__ int32_t seg_pos_ge(const TileArgs &t, int64_t v) {
+  return t.bidx[(v + (1ll << t.bsh) - 1) >> t.bsh];
+}
+
+__device__ __forceinline__ int32_t seg_pos_lt(const TileArgs &t, int64_t v) { return t.bidx[v >> t.bsh]; }
+
+__device__ __forceinline__ int32_t clamp32(int32_t x, int32_t lo, int32_t hi) { return min(max(x, lo), hi); }
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// U(t) = sum over sizes [i0, i1) of max(0, w - t), for each lane threshold
+// th[j] in [tlo, thi].  Sizes before p0 exceed every threshold and add
+// w - t; in [p0, p1) max(0, w - t) = ((w - t) + |w - t|) / 2, with |w - t|
+// summed per lane (v_sad_u32); sizes from p1 on add 0.  So
+// 2 U = (H0 - N0 t) + (H1 - N1 t) + sum_[p0,p1) |w - t| with H, N the sum
+// and count of [i0, p0) and [i0, p1).
+template <int LPL>
+__device__ void seg_u(const TileArgs &t, int32_t i0, int32_t i1, int64_t tlo, int64_t thi, const uint32_t th[LPL],
+                      int64_t u[LPL]) {
+  const int32_t p0 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_ge(t, thi + 1), i0, i1));
+  const int32_t p1 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_lt(t, tlo + 1), p0, i1));
+  const int64_t base = t.prec[i0];
+  const int64_t h = (t.prec[p0] - base) + (t.prec[p1] - base);
+  const int64_t n = (int64_t)(p0 - i0) + (int64_t)(p1 - i0);
+  uint64_t sad[LPL] = {};
+  stream_chunked<LPL>(t.wv, p0, p1, chunk_len((uint64_t)t.C), sad, [&](uint32_t w, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] = sad_u32(w, th[j], s[j]);
+  });
+  for (int j = 0; j < LPL; ++j) u[j] = (h - n * (int64_t)th[j] + (int64_t)sad[j]) >> 1;
+}
+
+// f_BJ1 by segments.  Over the sizes 0 < w < c, with K = floor(c / lambda)
+// and p = c mod lambda, grouping the sizes by q = floor(w / lambda) turns
+// sum_w f_BJ1(w, lambda) into the telescoping form
+//   S = sum_{m=1..K} U(c - m lambda) - sum_{j=1..K} U(j lambda),
+// 2K threshold sums.  Lanes whose K is below the tile's largest mask the
+// extra terms.  Returns the same part as part_bj1 (part = 2S - W + n p).
+template <int LPL>
+__device__ void part_bj1_seg(const TileArgs &t, const int64_t lam_out[LPL], int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t l0 = uniform64(max(t.lo, t.lam0));
+  const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
+  uint32_t lam[LPL];
+  int32_t K[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    lam[j] = (uint32_t)min(max(lam_out[j], l0), l1);
+    K[j] = (int32_t)((uint32_t)C / lam[j]);
+  }
+  const int32_t kmax = (int32_t)(C / l0);
+  int64_t acc[LPL] = {};
+  for (int32_t q = 1; q <= kmax; ++q) {
+    uint32_t th[LPL];
+    int64_t u[LPL];
+    {
+      const int64_t tlo = (int64_t)q * l0, thi = min(C, (int64_t)q * l1);
+      for (int j = 0; j < LPL; ++j) th[j] = (uint32_t)min(max((int64_t)q * lam[j], tlo), thi);
+      seg_u<LPL>(t, t.nf, t.nz, tlo, thi, th, u);
+      for (int j = 0; j < LPL; ++j) acc[j] -= q <= K[j] ? u[j] : 0;
+    }
+    {
+      const int64_t tlo = max((int64_t)0, C - (int64_t)q * l1), thi = C - (int64_t)q * l0;
+      for (int j = 0; j < LPL; ++j) th[j] = (uint32_t)min(max(C - (int64_t)q * lam[j], tlo), thi);
+      seg_u<LPL>(t, t.nf, t.nz, tlo, thi, th, u);
+      for (int j = 0; j < LPL; ++j) acc[j] += q <= K[j] ? u[j] : 0;
+    }
+  }
+  const int64_t n = t.nz - t.nf;
+  for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j] - t.sumNZ + n * (int64_t)((uint32_t)C % lam[j]);
+}
+
+// f_MT by segments: the small sizes with w >= lambda and the big ones with
+// c - w < lambda (w >= c - lambda + 1) are prefixes of their classes; each
+// class has one window per tile.  Returns the same part as part_mt.
+template <int LPL>
+__device__ void part_mt_seg(const TileArgs &t, const int64_t lam_out[LPL], int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t l0 = uniform64(max(t.lo, t.lam0));
+  const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
+  uint32_t lam[LPL], lm1[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    lam[j] = (uint32_t)min(max(lam_out[j], l0), l1);
+    lm1[j] = lam[j] - 1u;  // wraps to -1 for lambda = 0: every size counts
+  }
+  const int32_t ps0 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_ge(t, l1), t.nm, t.nz));
+  const int32_t ps1 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_lt(t, l0), ps0, t.nz));
+  const int32_t pb0 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_ge(t, C - l0 + 1), t.nf, t.nb));
+  const int32_t pb1 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_lt(t, C - l1 + 1), pb0, t.nb));
+  uint64_t acc[LPL] = {};
+  const int L = chunk_len((uint64_t)C / 2 + 1);
+  stream_chunked<LPL>(t.av, pb0, pb1, L, acc, [&](uint32_t a, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] += (uint32_t)((int32_t)(a - lam[j]) >> 31) & a;
+  });
+  stream_chunked<LPL>(t.wv, ps0, ps1, L, acc, [&](uint32_t w, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] += (uint32_t)((int32_t)(lm1[j] - w) >> 31) & w;
+  });
+  const int64_t base = (int64_t)(pb0 - t.nf) * C - (t.prec[pb0] - t.prec[t.nf]) + (t.prec[ps0] - t.prec[t.nm]);
+  for (int j = 0; j < LPL; ++j) part[j] = base + (int64_t)acc[j];
+}
+
 __device__ __forceinline__ int64_t fin_bound(int bound, const TileArgs &t, int64_t lam, int64_t part) {
   switch (bound) {
     case kMT: return fin_mt(t, lam, part);
@@ -897,6 +1027,9 @@ __device__ __forceinline__ bool entry_args(const LaunchDesc &d, const BP_CONST E
   t.nz = st.nz;
   t.sumBig = st.sumBig;
   t.sumNZ = st.sumNZ;
+  t.bidx = as_const(d.bidx + p.bidx_off);
+  t.prec = as_const(d.pre + p.pre_off);
+  t.bsh = p.bshift;
   early = (p.flags & kPlanEarlyExit) != 0;
   return true;
 }
@@ -938,7 +1071,10 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
     uint32_t l32[LPL];
     tile_lams<LPL>(t, lam, l32);
     int64_t part[LPL];
-    switch (bound) {
+    if (e.mode == kModeSegments) {
+      if (bound == kMT) part_mt_seg<LPL>(t, lam, part);
+      else part_bj1_seg<LPL>(t, lam, part);
+    } else switch (bound) {
       case kMT: part_mt<LPL>(t, l32, part); break;
       case kRAD2: part_rad2<LPL>(t, l32, part); break;
       case kFS1: part_fs1<LPL>(t, l32, part); break;

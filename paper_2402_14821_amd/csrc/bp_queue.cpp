@@ -117,7 +117,8 @@ struct Queue {
     std::vector<const int32_t *> a(take.size()), b(take.size());
     for (size_t i = 0; i < take.size(); ++i) {
       const Req &q = take[i];
-      bp_status st = make_plan_in(q.C, q.m, q.n, q.m, kFormResidual, nullptr, !(q.flags & BP_NO_EARLY_EXIT), &pin[i]);
+      bp_status st = make_plan_in(q.C, q.m, q.n, q.m, kFormResidual, nullptr, !(q.flags & BP_NO_EARLY_EXIT), &pin[i],
+                                  (q.flags & BP_SEGMENTS) != 0);
       if (st) return st;
       a[i] = q.unpacked.data();
       b[i] = q.residual.data();
@@ -248,7 +249,7 @@ bp_status bp_queue_submit(bp_queue *qh, const bp_request *req, int32_t blocking,
   if (!req || !ticket) return fail(BP_ERR_ARG, "NULL argument");
   if (req->C < 1 || req->m < 0 || req->n < 0) return fail(BP_ERR_ARG, "bad request sizes");
   if ((req->m > 0 && !req->residual) || (req->n > 0 && !req->unpacked)) return fail(BP_ERR_ARG, "NULL request array");
-  if (req->flags & ~BP_NO_EARLY_EXIT) return fail(BP_ERR_ARG, "unknown flags");
+  if (req->flags & ~(BP_NO_EARLY_EXIT | BP_SEGMENTS)) return fail(BP_ERR_ARG, "unknown flags");
   if (req->n + req->m > kLargeCap) return fail(BP_ERR_LIMIT, "request of %lld items", (long long)(req->n + req->m));
   if ((st = host_validate_items(req->C, req->unpacked, req->n))) return st;
   if ((st = host_validate_items(req->C, req->residual, req->m))) return st;
