@@ -330,18 +330,21 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         push(e, (double)tile * (2.0 * ((double)(tile + bw) * dens * 2.0 + 30.0)) + 400.0);
         continue;
       }
-      if (q.segments && b == kBJ1) {
+      if (q.segments && (b == kBJ1 || b == kCCM1)) {
         // A tile whose smallest parameter is lambda has K = floor(c / lambda)
-        // and 2K windows of about (tile j + bucket) sizes; it is cheaper than
-        // r dense evaluations while K <= kcut.
+        // (BJ1) or floor(floor(c/2) / lambda) (CCM1) and 2K windows of about
+        // (tile j + bucket) sizes, at about per_size slots per size and
+        // parameter; it is cheaper than r dense evaluations while K <= kcut.
+        const double per_size = b == kBJ1 ? 1.0 : 1.5;
+        const int64_t knum = b == kBJ1 ? (int64_t)q.C : (int64_t)q.C / 2;
         int64_t kcut = 0;
         for (int64_t K = 1; K <= kSegMaxK; ++K) {
-          const double seg = 2.0 * (((double)tile * K * K / 2.0 + (double)bw * K) * dens + 30.0 * K);
+          const double seg = 2.0 * (((double)tile * K * K / 2.0 + (double)bw * K) * dens * per_size + 30.0 * K);
           if (seg > (double)rcap * unit_cost(b)) break;
           kcut = K;
         }
         if (seg_kcut >= 0) kcut = seg_kcut;
-        const int64_t lstar = kcut > 0 ? (int64_t)q.C / (kcut + 1) + 1 : q.hi[b] + 1;  // K(lambda) <= kcut from here
+        const int64_t lstar = kcut > 0 ? knum / (kcut + 1) + 1 : q.hi[b] + 1;  // K(lambda) <= kcut from here
         const int64_t ndense = std::max<int64_t>(0, (std::min(lstar, q.hi[b] + 1) - q.lo[b] + tile - 1) / tile);
         if (ndense > 0) {
           e.lam0 = q.lo[b];
@@ -353,8 +356,9 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
           e.mode = kModeSegments;
           e.lam0 = s0;
           e.ntiles = (q.hi[b] - s0 + tile) / tile;
-          const double kmid = std::max(1.0, (double)q.C / (0.5 * (double)(s0 + q.hi[b])));
-          push(e, (double)tile * (60.0 * kmid + ((double)tile * kmid * kmid + 2.0 * (double)bw * kmid) * dens) + 400.0);
+          const double kmid = std::max(1.0, (double)knum / (0.5 * (double)(s0 + q.hi[b])));
+          push(e, (double)tile * (60.0 * kmid + ((double)tile * kmid * kmid + 2.0 * (double)bw * kmid) * dens * per_size) +
+                      400.0);
         }
         continue;
       }

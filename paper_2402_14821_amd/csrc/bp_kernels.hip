@@ -869,6 +869,62 @@ __device__ void part_bj1_seg(const TileArgs &t, const int64_t lam_out[LPL], int6
   for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j] - t.sumNZ + n * (int64_t)((uint32_t)C % lam[j]);
 }
 
+// #{w in [i0, i1) : w >= th[j]} for thresholds in [tlo, thi], 1 <= tlo:
+// sizes before p0 are >= thi, sizes from p1 on are < tlo; in between one
+// sign bit per size and parameter.
+template <int LPL>
+__device__ void seg_count(const TileArgs &t, int32_t i0, int32_t i1, int64_t tlo, int64_t thi, const uint32_t th[LPL],
+                          int64_t cnt[LPL]) {
+  const int32_t p0 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_ge(t, thi), i0, i1));
+  const int32_t p1 = __builtin_amdgcn_readfirstlane(clamp32(seg_pos_lt(t, tlo), p0, i1));
+  uint32_t tm1[LPL], n[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    tm1[j] = th[j] - 1u;
+    n[j] = 0;
+  }
+  stream_u32(t.wv, p0, p1, [&](uint32_t w) {
+    for (int j = 0; j < LPL; ++j) n[j] += (tm1[j] - w) >> 31;
+  });
+  for (int j = 0; j < LPL; ++j) cnt[j] = (int64_t)(p0 - i0) + (int64_t)n[j];
+}
+
+// f_CCM1 by segments: sum_small floor(w / lambda) = sum_{q >= 1} #{small
+// w >= q lambda} and sum_big floor((c - w) / lambda) = sum_{q >= 1} #{big
+// w <= c - q lambda}.  Thresholds past the reach of a class give exact
+// zeros (small) or full counts (big), so they are clamped to the class
+// edge and no lane is masked.  Returns the same part as part_ccm1.
+template <int LPL>
+__device__ void part_ccm1_seg(const TileArgs &t, const int64_t lam_out[LPL], int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t l0 = uniform64(max(t.lo, t.lam0));
+  const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
+  uint32_t lam[LPL];
+  for (int j = 0; j < LPL; ++j) lam[j] = (uint32_t)min(max(lam_out[j], l0), l1);
+  const int64_t half = C / 2;
+  const int64_t scap = (C - 1) / 2 + 1;  // every small size is below it
+  const int64_t bfloor = half + 1;       // every big size reaches it
+  const int64_t nbig = t.nb - t.nf;
+  const int32_t qmax = (int32_t)(half / l0);
+  int64_t acc[LPL] = {};
+  for (int32_t q = 1; q <= qmax; ++q) {
+    uint32_t th[LPL];
+    int64_t c[LPL];
+    {
+      const int64_t tlo = min((int64_t)q * l0, scap), thi = min((int64_t)q * l1, scap);
+      for (int j = 0; j < LPL; ++j) th[j] = (uint32_t)min((int64_t)q * lam[j], scap);
+      seg_count<LPL>(t, t.nm, t.nz, tlo, thi, th, c);
+      for (int j = 0; j < LPL; ++j) acc[j] += c[j];
+    }
+    {
+      const int64_t tlo = max(C - (int64_t)q * l1 + 1, bfloor), thi = max(C - (int64_t)q * l0 + 1, bfloor);
+      for (int j = 0; j < LPL; ++j) th[j] = (uint32_t)max(C - (int64_t)q * lam[j] + 1, bfloor);
+      seg_count<LPL>(t, t.nf, t.nb, tlo, thi, th, c);
+      for (int j = 0; j < LPL; ++j) acc[j] -= nbig - c[j];
+    }
+  }
+  for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j];
+}
+
 // f_MT by segments: the small sizes with w >= lambda and the big ones with
 // c - w < lambda (w >= c - lambda + 1) are prefixes of their classes; each
 // class has one window per tile.  Returns the same part as part_mt.
@@ -1073,6 +1129,7 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
     int64_t part[LPL];
     if (e.mode == kModeSegments) {
       if (bound == kMT) part_mt_seg<LPL>(t, lam, part);
+      else if (bound == kCCM1) part_ccm1_seg<LPL>(t, lam, part);
       else part_bj1_seg<LPL>(t, lam, part);
     } else switch (bound) {
       case kMT: part_mt<LPL>(t, l32, part); break;
