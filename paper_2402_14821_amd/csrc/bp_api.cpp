@@ -128,6 +128,22 @@ static int ilog2ceil(int64_t x) {
   return l;
 }
 
+// Divisors of c in ascending order, by trial division up to sqrt(c) (cached
+// per context: a batch or a served stream has few distinct capacities).
+static const std::vector<int32_t> &divisors_of(Ctx *c, int32_t C) {
+  auto it = c->div_cache.find(C);
+  if (it != c->div_cache.end()) return it->second;
+  if (c->div_cache.size() > 4096) c->div_cache.clear();
+  std::vector<int32_t> lo, hi;
+  for (int64_t i = 1; i * i <= (int64_t)C; ++i) {
+    if (C % i) continue;
+    lo.push_back((int32_t)i);
+    if (i * i != (int64_t)C) hi.push_back((int32_t)(C / i));
+  }
+  lo.insert(lo.end(), hi.rbegin(), hi.rend());
+  return c->div_cache.emplace(C, std::move(lo)).first->second;
+}
+
 // Checks a caller range against the paper's range of that bound.
 static bp_status check_sweep(int32_t C, const bp_sweep *sw, int64_t lo[kNB], int64_t hi[kNB]) {
   int64_t dlo[kNB], dhi[kNB];
@@ -192,7 +208,7 @@ void Ctx::destroy() {
   graph_exec = nullptr;
   graph = nullptr;
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
-                    &acc_buf, &out_buf, &red_buf, &bidx_buf})
+                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf})
     b->release();
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (staged) (void)hipEventDestroy(staged);
@@ -253,7 +269,8 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   const int64_t count = (int64_t)pin.size();
   std::vector<InstPlan> &pl = plan_vec;
   pl.assign((size_t)count, InstPlan{});
-  int64_t ws = 0, pre = 0, bidx = 0;
+  int64_t ws = 0, pre = 0, bidx = 0, dcnt = 0;
+  div_vec.clear();
   std::vector<Entry> ent;
   std::vector<double> tile_cost_v;
   std::vector<int64_t> rcap_v;
@@ -362,6 +379,41 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         }
         continue;
       }
+      if (q.segments && b == kVB2 && !q.clamp && rcap >= kMirrorMinItems && q.C >= 5) {
+        // Mirrored VB2: a dense sum at lambda <= (c - 1)/2 also gives the sum
+        // at c - lambda.  N1 = the range's own low parameters, N2 = the
+        // mirrors of its high ones; the dense half is their hull.
+        const int64_t C = q.C, lo = q.lo[b], hi = q.hi[b];
+        const int64_t low_end = (C - 1) / 2, high_start = C - low_end;
+        const int64_t a1 = std::max<int64_t>(lo, 1), b1 = std::min(hi, low_end);
+        const int64_t a2 = C - std::min(hi, C - 1), b2 = C - std::max(lo, high_start);
+        const bool has1 = a1 <= b1, has2 = a2 <= b2;
+        const int64_t lm = std::min(has1 ? a1 : a2, has2 ? a2 : a1), mm = std::max(has1 ? b1 : b2, has2 ? b2 : b1);
+        const int64_t need = (has1 ? b1 - a1 + 1 : 0) + (has2 ? b2 - a2 + 1 : 0);
+        const std::vector<int32_t> &dv = divisors_of(this, q.C);
+        if (has1 && has2 && (double)(mm - lm + 1) < 0.75 * (double)need && (int)dv.size() <= kMaxDivs) {
+          p.div_off = (int64_t)div_vec.size();
+          p.ndiv = (int32_t)dv.size();
+          p.dc_off = dcnt;
+          div_vec.insert(div_vec.end(), dv.begin(), dv.end());
+          dcnt += 2 * (int64_t)dv.size();
+          e.mode = kModeMirror;
+          e.lam0 = lm;
+          e.aux = (int32_t)mm;
+          e.ntiles = (mm - lm + tile) / tile;
+          push(e, dense_tc);
+          // parameters the two halves miss: c/2 (even c) and c
+          e.mode = kModeDense;
+          e.aux = 0;
+          for (int64_t x : {C % 2 == 0 ? C / 2 : (int64_t)-1, C}) {
+            if (x < lo || x > hi) continue;
+            e.lam0 = x;
+            e.ntiles = 1;
+            push(e, dense_tc);
+          }
+          continue;
+        }
+      }
       const int64_t nl = q.hi[b] - q.lo[b] + 1;
       e.lam0 = q.lo[b];
       e.ntiles = (nl + tile - 1) / tile;
@@ -371,6 +423,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   ws_items = ws;
   pre_items = pre;
   bidx_items = bidx;
+  dcnt_items = dcnt;
   // Task size: about tasks_per_wave tasks per resident wave over the whole
   // launch.  A tile cheaper than that is grouped with its neighbours; a dearer
   // one is split into item chunks of at least min_chunk items.
@@ -440,7 +493,8 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   bp_status st;
   const size_t off_plan = align256(sizeof(LaunchDesc));
   const size_t off_ent = off_plan + align256(sizeof(InstPlan) * (size_t)count);
-  const size_t off_in = off_ent + align256(sizeof(Entry) * entry_vec.size());
+  const size_t off_div = off_ent + align256(sizeof(Entry) * entry_vec.size());
+  const size_t off_in = off_div + align256(sizeof(int32_t) * std::max<size_t>(div_vec.size(), 1));
   const size_t total = off_in + (host_in ? align256(sizeof(int32_t) * (size_t)std::max<int64_t>(host_in_len, 1)) : 0);
   if ((st = stage_host.reserve(total))) return st;
   void *old_dev = stage_buf.p;
@@ -460,6 +514,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if ((st = ref_buf.reserve(sizeof(int32_t) * count))) return st;
   if ((st = acc_buf.reserve(sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
   if ((st = bidx_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bidx_items, 1)))) return st;
+  if ((st = dcnt_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(dcnt_items, 1)))) return st;
   char *h = (char *)stage_host.p;
   char *dv = (char *)stage_buf.p;
   LaunchDesc *d = (LaunchDesc *)h;
@@ -476,6 +531,8 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->counter = (unsigned long long *)counter_buf.p;
   d->acc = (long long *)acc_buf.p;
   d->bidx = (int32_t *)bidx_buf.p;
+  d->divs = (const int32_t *)(dv + off_div);
+  d->dcnt = (int32_t *)dcnt_buf.p;
   d->out = out_dev;
   d->count = count;
   d->nentries = nentries;
@@ -484,6 +541,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->nsplit = nsplit;
   memcpy(h + off_plan, plan_vec.data(), sizeof(InstPlan) * (size_t)count);
   memcpy(h + off_ent, entry_vec.data(), sizeof(Entry) * entry_vec.size());
+  if (!div_vec.empty()) memcpy(h + off_div, div_vec.data(), sizeof(int32_t) * div_vec.size());
   if (host_in && host_in_len > 0) memcpy(h + off_in, host_in, sizeof(int32_t) * (size_t)host_in_len);
   HIP_TRY(hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(staged, s));

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <unordered_map>
 #include <vector>
 
 #include "bp_internal.h"
@@ -68,12 +69,14 @@ struct Ctx {
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
   int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
-  int64_t ws_items = 0, pre_items = 0, bidx_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
+  int64_t ws_items = 0, pre_items = 0, bidx_items = 0, dcnt_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
+  std::vector<int32_t> div_vec;  // divisor lists of this launch (staged with the plan)
+  std::unordered_map<int32_t, std::vector<int32_t>> div_cache;  // divisors of c by c
   std::vector<InstPlan> plan_vec;
   std::vector<Entry> entry_vec;
 
   DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, out_buf,
-      red_buf, bidx_buf;
+      red_buf, bidx_buf, dcnt_buf;
   HostBuf stage_host, in_host, out_host, red_host;
 
   bp_status init(int dev);

@@ -52,6 +52,10 @@ struct InstPlan {
   int32_t bshift;    // kPlanSegments: bucket width 2^bshift of the threshold table
   int32_t nbk;       // kPlanSegments: entries of the threshold table
   int64_t bidx_off;  // kPlanSegments: offset of the threshold table
+  int64_t div_off;   // ndiv > 0: offset of the divisors of c (ascending) in the divisor list
+  int64_t dc_off;    // ndiv > 0: offset of the multiple counts [small x ndiv][big x ndiv]
+  int32_t ndiv;      // divisors of c listed for the mirrored VB2 tiles (0: none)
+  int32_t pad2;
 };
 constexpr uint32_t kPlanClampVB2 = 1u;
 constexpr uint32_t kPlanEarlyExit = 2u;
@@ -59,7 +63,11 @@ constexpr uint32_t kPlanSegments = 4u;
 
 // How an entry's tiles compute their sums: one evaluation per (item,
 // parameter), or threshold sums over windows of the sorted sizes.
-enum : int32_t { kModeDense = 0, kModeSegments = 1 };
+// kModeMirror (VB2): each lane's dense sum at lambda also gives the sum at
+// c - lambda.
+enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2 };
+constexpr int kMaxDivs = 256;         // most divisors of c a mirrored instance may have
+constexpr int kMirrorMinItems = 256;  // fewer items: the per-parameter gcd outweighs the saved half
 
 // Per-instance state, written by the prep kernel.
 struct InstState {
@@ -92,8 +100,8 @@ struct Entry {
   int32_t bound;        // kL2 .. kBJ1
   int32_t tpt;          // tiles per task
   int32_t nchunks;      // item chunks per tile
-  int32_t mode;         // kModeDense or kModeSegments (never split into chunks)
-  int32_t pad;
+  int32_t mode;         // kModeDense, kModeSegments or kModeMirror (the last two never split into chunks)
+  int32_t aux;          // kModeMirror: last parameter of the dense half
 };
 
 struct LaunchDesc {
@@ -111,6 +119,8 @@ struct LaunchDesc {
   unsigned long long *counter; // kQueues task counters of the persistent sweep, kQueueStride apart
   long long *acc;           // partial sums of split tiles, one slot per (tile, chunk, parameter)
   int32_t *bidx;            // threshold tables: bidx[b] = #{sorted sizes >= b 2^bshift}
+  const int32_t *divs;      // divisor lists of the capacities (mirrored VB2)
+  int32_t *dcnt;            // per divisor d: #{small sizes divisible by d}, then the same for big sizes
   bp_bounds *out;           // [count] results
   int64_t count;            // instances
   int64_t nentries;

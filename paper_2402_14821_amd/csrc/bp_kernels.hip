@@ -406,6 +406,32 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     int64_t *pre = d.pre + p.pre_off;
     block_prefix<NT, CAP>(sm, sz, (int)r, pre);
     __syncthreads();
+    if (p.ndiv > 0) {
+      // mirrored VB2: per divisor d of c, the small and the big sizes that d
+      // divides (the divisors staged in hist, the counts in wcnt[0..1])
+      const int nd = p.ndiv;
+      const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
+      for (int k = tid; k < 256; k += NT) {
+        sm.hist[k] = k < nd ? (uint32_t)dv[k] : 1u;
+        sm.wcnt[0][k] = 0;
+        sm.wcnt[1][k] = 0;
+      }
+      __syncthreads();
+      for (int i = tid; i < r; i += NT) {
+        const int cls = (i >= nf && i < nb) ? 1 : ((i >= nm && i < nz) ? 0 : -1);
+        if (cls < 0) continue;
+        const uint32_t w = sz[i];
+        for (int k = 0; k < nd; ++k)
+          if (w % sm.hist[k] == 0u) atomicAdd(&sm.wcnt[cls][k], 1u);
+      }
+      __syncthreads();
+      int32_t *dc = d.dcnt + p.dc_off;
+      for (int k = tid; k < nd; k += NT) {
+        dc[k] = (int32_t)sm.wcnt[0][k];
+        dc[nd + k] = (int32_t)sm.wcnt[1][k];
+      }
+      __syncthreads();
+    }
     if (tid == 0) {
       st->r = (int32_t)r;
       st->nf = nf;
@@ -495,6 +521,9 @@ struct TileArgs {
   const BP_CONST int32_t *bidx;  // threshold table (segment entries)
   const BP_CONST int64_t *prec;  // prefix sums again, for scalar loads
   int32_t bsh;                   // bucket width 2^bsh of the table
+  int32_t ndiv;                  // mirrored VB2: divisors of c
+  const BP_GLOBAL int32_t *divs; // ascending
+  const BP_GLOBAL int32_t *dcnt; // [small x ndiv][big x ndiv] multiple counts
 };
 
 // Largest number of items whose per-item increments, each at most maxinc,
@@ -1031,6 +1060,52 @@ __device__ __forceinline__ uint64_t tile_max(const int64_t lam[LPL], const int64
 // Folds a key into the instance's maximum for the bound and raises the
 // early-exit flag when the bound refutes the instance.  Keys only grow: a key
 // that does not beat the current one leaves it alone.
+__device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b) {
+  while (b) {
+    const uint32_t r = a % b;
+    a = b;
+    b = r;
+  }
+  return a;
+}
+
+// Mirrored VB2.  For a >= 1, h(a, c - lambda) = a - 1 - h(a, lambda) - [c | a
+// lambda], and c | a lambda iff d | a with d = c / gcd(c, lambda).  Over a
+// class with n sizes summing (as a) to A, the sum at c - lambda is
+// A - n - (sum at lambda) - #{d | a}; the counts per divisor of c come from
+// prep (for the big class a = c - w, and d | c - w iff d | w).  Returns the
+// packed maximum over the lanes' keys at lambda and at c - lambda, each kept
+// when inside the bound's range [t.lo, t.hi]; lam[j] <= mm marks a lane in
+// the dense half.
+template <int LPL>
+__device__ uint64_t vb2_mirror_key(const TileArgs &t, int64_t mm, const int64_t lam[LPL], const int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t nsm = t.nz - t.nm, nbg = t.nb - t.nf;
+  const int64_t sum_small = t.sumNZ - t.sumBig - (int64_t)(t.nm - t.nb) * (C / 2);
+  const int64_t base = (sum_small - nsm) - (nbg * C - t.sumBig - nbg);  // (A - n) small minus (A - n) big
+  int64_t l1[LPL], v1[LPL], l2[LPL], v2[LPL];
+  bool o1[LPL], o2[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    const bool in = lam[j] >= 1 && lam[j] <= mm;
+    const uint32_t lj = in ? (uint32_t)lam[j] : 1u;
+    const uint32_t dd = (uint32_t)C / gcd_u32((uint32_t)C, lj);
+    int lo = 0, hi = t.ndiv - 1;  // dd is a divisor of c: find it
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((uint32_t)t.divs[mid] < dd) lo = mid + 1; else hi = mid;
+    }
+    const int64_t dsm = t.dcnt[lo], dbg = t.dcnt[t.ndiv + lo];
+    const int64_t part2 = 2 * (base - dsm + dbg) - part[j];
+    l1[j] = lam[j];
+    l2[j] = C - lam[j];
+    o1[j] = in && l1[j] >= t.lo && l1[j] <= t.hi;
+    o2[j] = in && l2[j] >= t.lo && l2[j] <= t.hi;
+    v1[j] = o1[j] ? fin_vb2(t, l1[j], part[j]) : 0;
+    v2[j] = o2[j] ? fin_vb2(t, l2[j], part2) : 0;
+  }
+  return umax64(tile_max<LPL>(l1, v1, o1), tile_max<LPL>(l2, v2, o2));
+}
+
 __device__ __forceinline__ void publish_key(const LaunchDesc &d, int64_t inst, int bound, const TileArgs &t,
                                             uint64_t key, bool early) {
   if (!key) return;
@@ -1086,6 +1161,9 @@ __device__ __forceinline__ bool entry_args(const LaunchDesc &d, const BP_CONST E
   t.bidx = as_const(d.bidx + p.bidx_off);
   t.prec = as_const(d.pre + p.pre_off);
   t.bsh = p.bshift;
+  t.ndiv = p.ndiv;
+  t.divs = as_global(d.divs + p.div_off);
+  t.dcnt = as_global(d.dcnt + p.dc_off);
   early = (p.flags & kPlanEarlyExit) != 0;
   return true;
 }
@@ -1124,8 +1202,14 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       continue;
     }
     if (t.lam0 > t.hi) return;
+    // the dense half of a mirrored VB2 entry runs over [1, aux]
+    TileArgs tv = t;
+    if (e.mode == kModeMirror) {
+      tv.lo = 1;
+      tv.hi = e.aux;
+    }
     uint32_t l32[LPL];
-    tile_lams<LPL>(t, lam, l32);
+    tile_lams<LPL>(tv, lam, l32);
     int64_t part[LPL];
     if (e.mode == kModeSegments) {
       if (bound == kMT) part_mt_seg<LPL>(t, lam, part);
@@ -1136,7 +1220,7 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       case kRAD2: part_rad2<LPL>(t, l32, part); break;
       case kFS1: part_fs1<LPL>(t, l32, part); break;
       case kCCM1: part_ccm1<LPL>(t, l32, part); break;
-      case kVB2: part_vb2<LPL>(t, l32, part); break;
+      case kVB2: part_vb2<LPL>(tv, l32, part); break;
       default: part_bj1<LPL>(t, l32, part); break;
     }
     if (nch > 1) {
@@ -1145,6 +1229,11 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       // chunks of the tile once the sweep is over.
       long long *slot = d.acc + e.acc_base + (tl * nch + chunk) * (64 * LPL);
       for (int j = 0; j < LPL; ++j) slot[lane_id() + 64 * j] = (long long)part[j];
+      continue;
+    }
+    if (e.mode == kModeMirror) {
+      const uint64_t key = vb2_mirror_key<LPL>(t, e.aux, lam, part);
+      if (lane_id() == 0) publish_key(d, inst, bound, t, key, early);
       continue;
     }
     for (int j = 0; j < LPL; ++j) {
@@ -1191,7 +1280,12 @@ __global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__
       int64_t lam[LPL], lbp[LPL], part[LPL];
       bool ok[LPL];
       uint32_t l32[LPL];
-      tile_lams<LPL>(t, lam, l32);
+      TileArgs tv = t;
+      if (e.mode == kModeMirror) {
+        tv.lo = 1;
+        tv.hi = e.aux;
+      }
+      tile_lams<LPL>(tv, lam, l32);
       for (int j = 0; j < LPL; ++j) part[j] = 0;
       // four chunks' loads in flight at a time
       int32_t c = 0;
@@ -1206,11 +1300,15 @@ __global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__
       }
       for (; c < nch; ++c)
         for (int j = 0; j < LPL; ++j) part[j] += slots[c * (64 * LPL) + lane_id() + 64 * j];
-      for (int j = 0; j < LPL; ++j) {
-        ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
-        lbp[j] = ok[j] ? fin_bound(e.bound, t, lam[j], part[j]) : 0;
+      if (e.mode == kModeMirror) {
+        key = vb2_mirror_key<LPL>(t, e.aux, lam, part);
+      } else {
+        for (int j = 0; j < LPL; ++j) {
+          ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
+          lbp[j] = ok[j] ? fin_bound(e.bound, t, lam[j], part[j]) : 0;
+        }
+        key = tile_max<LPL>(lam, lbp, ok);
       }
-      key = tile_max<LPL>(lam, lbp, ok);
     }
     if (lane_id() == 0) wkey[wave] = key;
     __syncthreads();

@@ -239,3 +239,37 @@ def test_queue_requests_with_segments(ctx):
         want = ctx.feasible(r.C, r.residual, r.unpacked, flags=bp.BP_NO_EARLY_EXIT)
         say("segments queue tag", i)
         same(bp.bounds_to_dict(rr.bounds), want, ("queue", i))
+
+
+def test_mirrored_vb2(ctx):
+    # VB2 in segment form reuses each dense sum at lambda for c - lambda (needs
+    # >= 256 sizes); odd, even, prime and highly composite capacities, full and
+    # partial ranges, compared with the oracle field by field
+    rng = np.random.default_rng(1505)
+    for C in (1009, 1000, 1024, 4096, 5040, 9973):
+        for t in range(3):
+            r = int(rng.integers(256, 700))
+            items = rng.integers(0, C + 1, size=r)
+            items[: r // 10] = rng.choice([C, C // 2, (C + 1) // 2, 1, C - 1], size=r // 10)
+            items = items.astype(np.int32)
+            lo = [O.default_range(b, C)[0] for b in range(O.NB)]
+            hi = [O.default_range(b, C)[1] for b in range(O.NB)]
+            if t == 1:
+                lo[O.VB2], hi[O.VB2] = sorted(int(x) for x in rng.integers(2, C + 1, size=2))
+            elif t == 2:
+                lo[O.VB2], hi[O.VB2] = C // 2 - 40, C // 2 + 60
+            say("mirrored VB2", C, t, r, lo[O.VB2], hi[O.VB2])
+            got = ctx.lower_bounds(C, r // 3, items, seg_sweep(C, lo, hi))
+            same(got, O.bounds(C, r // 3, items, lo, hi), ("mirror", C, t))
+    # 720720 has 240 divisors; windows around c/2 and at the top
+    C = 720720
+    items = rng.integers(1, C, size=400).astype(np.int32)
+    items[:40] = [d for d in range(2, 100000) if C % d == 0][:40]
+    for vlo, vhi in ((C // 2 - 200, C // 2 + 200), (C - 300, C)):
+        lo = [O.default_range(b, C)[0] for b in range(O.NB)]
+        hi = [min(O.default_range(b, C)[1], lo[b] + 99) for b in range(O.NB)]
+        lo[O.L2], hi[O.L2] = O.default_range(O.L2, C)
+        lo[O.VB2], hi[O.VB2] = vlo, vhi
+        say("mirrored VB2 720720", vlo, vhi)
+        got = ctx.lower_bounds(C, 100, items, seg_sweep(C, lo, hi))
+        same(got, O.bounds(C, 100, items, lo, hi), ("mirror 720720", vlo))

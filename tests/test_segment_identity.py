@@ -73,3 +73,27 @@ def test_ccm1_threshold_counts():
             total = 2 * K * len(big) + K * mid + 2 * (hs - hb)
             direct = sum(O.f(O.CCM1, C, w, lam) for w in items if 0 < w < C)
             assert total == direct, (C, items, lam)
+
+
+def test_vb2_mirror_identity():
+    # with h(a, lambda) = ceil(a lambda / c) - 1 for a >= 1:
+    #   h(a, c - lambda) = a - 1 - h(a, lambda) - [d | a],  d = c / gcd(c, lambda)
+    # checked through the oracle's f_VB2 (small sizes: f = 2 h(w); big sizes:
+    # f = 2 (lambda - 1) - 2 h(c - w))
+    import math
+
+    rng = random.Random(10)
+    for _ in range(300):
+        C = rng.randint(5, 150)
+        items = [rng.randint(1, C - 1) for _ in range(rng.randint(1, 10))]
+        small = [w for w in items if 2 * w < C]
+        big = [w for w in items if 2 * w > C]
+        for lam in range(2, (C - 1) // 2 + 1):
+            d = C // math.gcd(C, lam)
+            hs = sum(O.f(O.VB2, C, w, lam) for w in small) // 2
+            hb = sum(2 * (lam - 1) - O.f(O.VB2, C, w, lam) for w in big) // 2
+            hs2 = sum(w - 1 for w in small) - hs - sum(1 for w in small if w % d == 0)
+            hb2 = sum(C - w - 1 for w in big) - hb - sum(1 for w in big if w % d == 0)
+            lam2 = C - lam
+            assert 2 * hs2 == sum(O.f(O.VB2, C, w, lam2) for w in small), (C, items, lam)
+            assert 2 * hb2 == sum(2 * (lam2 - 1) - O.f(O.VB2, C, w, lam2) for w in big), (C, items, lam)
