@@ -338,6 +338,14 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         continue;
       }
       const double dense_tc = (double)tile * ((double)rcap * unit_cost(b) + 60.0);
+      if (q.segments && b == kRAD2) {
+        // four windows per tile (128 or 256 thresholds wide)
+        e.mode = kModeSegments;
+        e.lam0 = q.lo[b];
+        e.ntiles = (q.hi[b] - q.lo[b] + tile) / tile;
+        push(e, (double)tile * (4.0 * ((double)(2 * tile + bw) * dens * 1.5 + 30.0)) + 400.0);
+        continue;
+      }
       if (q.segments && b == kMT) {
         // two windows per tile (small sizes around lambda, big ones around
         // c - lambda), each about (tile + bucket) sizes long

@@ -954,6 +954,30 @@ __device__ void part_ccm1_seg(const TileArgs &t, const int64_t lam_out[LPL], int
   for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j];
 }
 
+// f_RAD2 by segments: the four threshold counts of part_rad2 (small sizes
+// >= lambda and >= c - 2 lambda + 1, big sizes >= 2 lambda and
+// >= c - lambda + 1), one window each per tile.  Same part as part_rad2.
+template <int LPL>
+__device__ void part_rad2_seg(const TileArgs &t, const int64_t lam_out[LPL], int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t l0 = uniform64(max(t.lo, t.lam0));
+  const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
+  uint32_t lam[LPL], th[LPL];
+  for (int j = 0; j < LPL; ++j) lam[j] = (uint32_t)min(max(lam_out[j], l0), l1);
+  int64_t n1[LPL], n2[LPL], n3[LPL], n4[LPL];
+  for (int j = 0; j < LPL; ++j) th[j] = lam[j];
+  seg_count<LPL>(t, t.nm, t.nz, l0, l1, th, n1);
+  for (int j = 0; j < LPL; ++j) th[j] = (uint32_t)(C - 2 * (int64_t)lam[j] + 1);
+  seg_count<LPL>(t, t.nm, t.nz, C - 2 * l1 + 1, C - 2 * l0 + 1, th, n2);
+  for (int j = 0; j < LPL; ++j) th[j] = 2u * lam[j];
+  seg_count<LPL>(t, t.nf, t.nb, 2 * l0, 2 * l1, th, n3);
+  for (int j = 0; j < LPL; ++j) th[j] = (uint32_t)(C - (int64_t)lam[j] + 1);
+  seg_count<LPL>(t, t.nf, t.nb, C - l1 + 1, C - l0 + 1, th, n4);
+  const int64_t c3 = C / 3, c2 = C / 2;
+  for (int j = 0; j < LPL; ++j)
+    part[j] = c3 * n1[j] + (c2 - c3) * n2[j] + (C - c2 - c3) * n3[j] + c3 * n4[j];
+}
+
 // f_MT by segments: the small sizes with w >= lambda and the big ones with
 // c - w < lambda (w >= c - lambda + 1) are prefixes of their classes; each
 // class has one window per tile.  Returns the same part as part_mt.
@@ -1214,6 +1238,7 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
     if (e.mode == kModeSegments) {
       if (bound == kMT) part_mt_seg<LPL>(t, lam, part);
       else if (bound == kCCM1) part_ccm1_seg<LPL>(t, lam, part);
+      else if (bound == kRAD2) part_rad2_seg<LPL>(t, lam, part);
       else part_bj1_seg<LPL>(t, lam, part);
     } else switch (bound) {
       case kMT: part_mt<LPL>(t, l32, part); break;

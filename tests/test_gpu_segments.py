@@ -1,8 +1,9 @@
 """GPU parity of the segment sums (BP_SWEEP_SEGMENTS / BP_SEGMENTS).
 
-The segment form computes the MT and BJ1 sums from threshold sums over the
-sorted sizes instead of one evaluation per (item, parameter); the bounds are
-the same integers.  Every record is compared with the CPU oracle (the dense
+The segment form computes the MT, RAD2, CCM1 and BJ1 sums from threshold
+sums over the sorted sizes instead of one evaluation per (item, parameter),
+and half of the VB2 sums from the other half (mirror); the bounds are the
+same integers.  Every record is compared with the CPU oracle (the dense
 definition) field by field, and at full size with the dense GPU path.
 BP_SEGMENT_KCUT forces segment tiles of BJ1 wherever floor(c / lambda) <= K,
 so that many windows per tile are exercised on small instances too.
