@@ -35,6 +35,11 @@ PEAK_VALU = 256 * 64 * 2.4e9  # full-rate lane-instructions/s: 256 CUs x 4 SIMD 
 DFF_NAMES = ("MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1")
 
 
+def log(msg: str) -> None:
+    """Progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def percentile(xs, p):
     import numpy as np
     return float(np.percentile(np.asarray(xs), p)) if len(xs) else None
@@ -218,7 +223,7 @@ def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain
                 for c in sorted(set(int(x) for x in Cs))}}
 
 
-def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30):
+def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30, flags: int = 0):
     """Open-loop Poisson arrivals of DFS requests into a bp_queue; latency from the library's clock."""
     import ctypes
     import threading
@@ -233,7 +238,7 @@ def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: in
         unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
         keep.append((res, unp))
         structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
-                                     unp.ctypes.data_as(bp._P32), i, 0, 0))
+                                     unp.ctypes.data_as(bp._P32), i, flags, 0))
     q = bp.Queue(ctx, budget, 1 << 20)
     results = []
     done = threading.Event()
@@ -277,6 +282,7 @@ def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: in
             "p50_us": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_us": float(np.percentile(lat, 99)) if len(lat) else None,
             "batches": stats["batches"], "peak_bytes": stats["bytes_peak"], "max_submit_lateness_s": late,
+            "segments": bool(flags & bp.BP_SEGMENTS),
             "workload": "DFS requests: roots n~U[200,5000], sizes U[C/20,C/2], C=10000, children commit 1-3 "
                         "items by decreasing best fit; early exit on; HBM budget 8 GB"}
 
@@ -436,11 +442,16 @@ def main():
         "verdict": rec["verdict"], "lb": rec["lb"],
         "segments": segments,
     }
+    log(f"large instance done: {ms_per_step:.3f} ms/step")
     if not args.no_batched:
         line["batched"] = bench_batched(bp, W, ctx)
+        log("batched leg done")
     if not args.no_served:
-        line["served"] = [bench_served(bp, W, ctx, rate, args.served_seconds, seed)
-                          for rate, seed in ((20_000.0, 3), (200_000.0, 4))]
+        line["served"] = []
+        for flags in (0, bp.BP_SEGMENTS):
+            for rate, seed in ((20_000.0, 3), (200_000.0, 4)):
+                line["served"].append(bench_served(bp, W, ctx, rate, args.served_seconds, seed, flags=flags))
+                log(f"served leg at {rate:.0f}/s (flags {flags}) done")
     if not args.no_cpu_baseline:
         import oracle as O
         items = O.residual_reduce(C, residual, unpacked)
