@@ -406,14 +406,28 @@ def main():
     achieved = ops / (sweep_avg * 1e-3)
     traffic = load_traffic("k_sweep")
 
-    # plain single-check latency on the small partial packing (host in, host out)
+    # plain single-check latency on the small partial packing (host in, host
+    # out): one bp_feasible call through ctypes with its arguments marshalled
+    # beforehand, so the figure is the library call and not numpy conversions
+    import ctypes
+    lib = bp.load()
     lat = []
-    smalls = [W.small_partial_packing(seed=s) for s in range(64)]
+    smalls = []
+    for s in range(64):
+        Cs, ms_, rs, us = W.small_partial_packing(seed=s)
+        rs = np.ascontiguousarray(rs, dtype=np.int32)
+        us = np.ascontiguousarray(us, dtype=np.int32)
+        smalls.append((Cs, len(rs), rs.ctypes.data_as(bp._P32), us.ctypes.data_as(bp._P32), len(us), rs, us))
+    v32, lb64, rec_small = ctypes.c_int32(0), ctypes.c_int64(0), bp.bp_bounds()
+    pv, plb, prec = ctypes.byref(v32), ctypes.byref(lb64), ctypes.byref(rec_small)
+    fz = lib.bp_feasible
     for i in range(args.latency_checks):
-        Cs, ms_, rs, us = smalls[i % len(smalls)]
+        Cs, ms_, prs, pus, nus, _, _ = smalls[i % len(smalls)]
         t1 = time.perf_counter()
-        ctx.feasible(Cs, rs, us)
+        st = fz(ctx.handle, Cs, ms_, prs, pus, nus, 0, pv, plb, prec)
         lat.append((time.perf_counter() - t1) * 1e6)
+        if st != 0:
+            raise bp.BpError(st, lib.bp_last_error().decode())
 
     line = {
         "metric": "(item x param) bound evals/s + feasibility checks/s, batched vs plain; p99 us",
