@@ -96,12 +96,14 @@ def cpu_baseline(C, items, target_s: float):
                       f"a single-thread probe puts the whole instance at {full_core_s:.1f} core-s)"}
 
 
-def sweep_ops(O, C, r):
-    """Algorithmic VALU slots of the six sweeps of one instance (exact ranges)."""
+def sweep_ops(bp, C, r):
+    """Algorithmic VALU slots of the six sweeps of one instance (exact ranges,
+    as the library's own bp_default_sweep states them)."""
+    sw = bp.default_sweep(int(C))
     ops = 0.0
-    for name, d in zip(DFF_NAMES, O.DFFS):
-        lo, hi = O.default_range(d, C)
-        ops += OPS_PER_EVAL[name] * r * max(0, hi - lo + 1)
+    for j, name in enumerate(DFF_NAMES):
+        b = bp.BP_MT + j
+        ops += OPS_PER_EVAL[name] * r * max(0, sw.hi[b] - sw.lo[b] + 1)
     return ops
 
 
@@ -127,7 +129,8 @@ def load_traffic(kernel: str):
     return float(vals["hbm_bytes_per_launch"])
 
 
-def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, plain_max: int = 4096):
+def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, plain_max: int = 4096,
+                  segments: bool = True):
     """Uneven batch: one batched call vs one plain call per instance (host in, host out)."""
     import numpy as np
 
@@ -144,13 +147,12 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
     t_batch = min(ts)
     evals = int(out["evals"].sum())
     # the sweep kernel of the same batch, timed with HIP events on the context's stream
-    import oracle as O  # ranges only
     ctx.set_timing(True)
     for _ in range(reps):
         ctx.lower_bounds_batch(Cs, ks, items_list)
     (prep_ms, sweep_ms, fin_ms), runs = ctx.stage_times(with_runs=True)
     ctx.set_timing(False)
-    ops = sum(sweep_ops(O, int(c), int(r)) for c, r in zip(Cs, out["r"]))
+    ops = sum(sweep_ops(bp, int(c), int(r)) for c, r in zip(Cs, out["r"]))
     fails = int((out["verdict"] == 0).sum())
     assert np.array_equal(out["verdict"] == 0, b.expect_fail), "batched verdicts differ from the construction"
     # plain: one call per instance, each synchronous
@@ -179,10 +181,12 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
                            "batched_instances": int(len(sub)), "batched_checks_per_s": batched,
                            "batched_over_plain": batched / plain}
     plain_rate = n_plain / per.sum()
-    try:
-        seg = bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps)
-    except bp.BpError as e:
-        seg = {"error": str(e)}
+    seg = None
+    if segments:
+        try:
+            seg = bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps)
+        except bp.BpError as e:
+            seg = {"error": str(e)}
 
     return {"workload": f"{count} instances, n lognormal(median 400, sigma 1) clipped to [50, 5000], "
                         "C in {1e3, 1e4, 1e6}, sizes U[1, C], 40% built to fail; host in/out",
@@ -297,6 +301,8 @@ def main():
     ap.add_argument("--latency-checks", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-segments", action="store_true",
+                    help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
     ap.add_argument("--served-seconds", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (scale for the HBM byte counters) and exit")
@@ -395,14 +401,15 @@ def main():
                         "(BP_SEGMENTS); identical bounds; nominal evals = r x sum of range sizes, not "
                         "evaluations performed"}
 
-    try:
-        segments = bench_segments()
-    except bp.BpError as e:  # reported, never the headline
-        ctx.set_timing(False)
-        segments = {"error": str(e)}
+    segments = None
+    if not args.no_segments:
+        try:
+            segments = bench_segments()
+        except bp.BpError as e:  # reported, never the headline
+            ctx.set_timing(False)
+            segments = {"error": str(e)}
 
-    import oracle as O  # ranges only (the bench's oracle leg)
-    ops = sweep_ops(O, C, r)
+    ops = sweep_ops(bp, C, r)
     achieved = ops / (sweep_avg * 1e-3)
     traffic = load_traffic("k_sweep")
 
@@ -458,11 +465,11 @@ def main():
     }
     log(f"large instance done: {ms_per_step:.3f} ms/step")
     if not args.no_batched:
-        line["batched"] = bench_batched(bp, W, ctx)
+        line["batched"] = bench_batched(bp, W, ctx, segments=not args.no_segments)
         log("batched leg done")
     if not args.no_served:
         line["served"] = []
-        for flags in (0, bp.BP_SEGMENTS):
+        for flags in ((0,) if args.no_segments else (0, bp.BP_SEGMENTS)):
             for rate, seed in ((20_000.0, 3), (200_000.0, 4)):
                 line["served"].append(bench_served(bp, W, ctx, rate, args.served_seconds, seed, flags=flags))
                 log(f"served leg at {rate:.0f}/s (flags {flags}) done")
