@@ -27,8 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Full-rate VALU issue slots per (item, parameter) evaluation of each sweep,
-# counted in the inner loops of the sweep kernel as built for gfx950 with 4
-# parameters per lane (32-bit add, sub, logic and shifts issue at twice the
+# counted in the inner loops of the sweep kernel as built for gfx950 with 2
+# parameters per lane, the default shape (32-bit add, sub, logic and shifts issue at twice the
 # full rate and count 1/2; mul_hi, mad_u64_u32, add3, sad and fp64 count 1).
 OPS_PER_EVAL = {"MT": 2.0, "RAD2": 3.0, "FS1": 10.25, "CCM1": 2.0, "VB2": 2.5, "BJ1": 4.0}
 PEAK_VALU = 256 * 64 * 2.4e9  # full-rate lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz

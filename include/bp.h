@@ -293,7 +293,10 @@ bp_status bp_queue_destroy(bp_queue *q);
 
 /* Checks, on the host, the multiply-shift constants the kernels use against
  * plain integer division: every divisor d in [d_lo, d_hi] with numerators
- * n in [0, n_hi] (and the extreme numerators).  Returns the number of
+ * n in [0, n_hi] (and the extreme numerators).  mode 0: floor(n / d) for
+ * n < 2^31; mode 1: ceil(a lam / c) - 1 (f_VB2's quotient), d taken as c;
+ * mode 2: the divisibility test d | n.  d_lo >= 1, d_hi < 2^31, n_hi < 2^31,
+ * else BP_ERR_ARG (also for any other mode).  Returns the number of
  * mismatches found (0 = all exact) or a negative status. */
 int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32_t mode);
 

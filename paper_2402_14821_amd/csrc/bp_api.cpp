@@ -1146,6 +1146,26 @@ int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32
         }
       }
     }
+  } else if (mode == 2) {
+    // d | n by family (3): d in [d_lo, d_hi], n in [0, n_hi], around multiples of d and below 2^31
+    for (uint64_t d = d_lo; d <= d_hi; ++d) {
+      const uint64_t M = divides_const((uint32_t)d);
+      auto one = [&](uint64_t n) {
+        if (n >= 0x80000000ull) return;
+        if (divides_u32((uint32_t)n, M) != (n % d == 0)) ++bad;
+      };
+      for (uint64_t n = 0; n <= n_hi; ++n) one(n);
+      for (uint64_t k = 1; k <= 64; ++k) {
+        one(d * k - 1);
+        one(d * k);
+        one(d * k + 1);
+      }
+      const uint64_t q = 0x7fffffffull / d;
+      for (uint64_t t = 0; t <= 4; ++t) {
+        one(q * d + t - 2);
+        one(0x7fffffffull - t);
+      }
+    }
   } else {
     return BP_ERR_ARG;
   }

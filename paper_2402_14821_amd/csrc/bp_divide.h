@@ -22,6 +22,16 @@
 //     ceil(a lam / c) - 1.  floor(a R / 2^64) is the high word of
 //     a * R_hi + mulhi(a, R_lo) (no overflow: < 2^63 + 2^32).  Cost: one
 //     v_mul_hi_u32 and one v_mad_u64_u32.
+//
+// (3) Divisibility of n < 2^32 by d, 1 <= d < 2^31 (Lemire, Kaser, Kurz,
+//     "Faster remainder by direct computation", 2019).  With M = ceil(2^64 / d)
+//     = (2^64 + e) / d, 0 <= e < d, and n = q d + t (0 <= t < d), n M =
+//     q 2^64 + q e + t M, so n M mod 2^64 = q e + t M as long as that is below
+//     2^64.  If t = 0 it is q e < (2^32 / d) d = 2^32 <= M; if t >= 1 it is at
+//     least M and below 2^32 + (d - 1)(2^64 / d + 1) < 2^64 (d < 2^31).  Hence
+//     d | n iff n M mod 2^64 <= M - 1.  For d = 1, M wraps to 0 and the test
+//     reads n 0 <= 2^64 - 1, true.  Cost: a 64-bit product by a 32-bit value
+//     and a 64-bit compare.
 #pragma once
 
 #include <stdint.h>
@@ -81,5 +91,11 @@ __host__ __device__ inline uint32_t vb2_part(uint32_t a, uint32_t r_lo, uint32_t
   uint64_t s = (uint64_t)a * r_hi + t;
   return (uint32_t)(s >> 32);
 }
+
+// Constant of family (3) for divisor d in [1, 2^31): ceil(2^64 / d) mod 2^64.
+__host__ __device__ inline uint64_t divides_const(uint32_t d) { return ~0ull / d + 1ull; }
+
+// d | n from M = divides_const(d).
+__host__ __device__ inline bool divides_u32(uint32_t n, uint64_t M) { return (uint64_t)n * M <= M - 1ull; }
 
 }  // namespace bpi

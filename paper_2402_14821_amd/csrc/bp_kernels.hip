@@ -408,21 +408,38 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     __syncthreads();
     if (p.ndiv > 0) {
       // mirrored VB2: per divisor d of c, the small and the big sizes that d
-      // divides (the divisors staged in hist, the counts in wcnt[0..1])
+      // divides (the counts in wcnt[0..1])
+      // d | w is tested as (w * M_d mod 2^64) < M_d with M_d = ceil(2^64 / d)
+      // (Lemire, Kaser, Kurz 2019, "Faster remainder by direct computation";
+      // exact for every 32-bit w and d >= 1, M_1 wraps to 0), and each wave
+      // adds its hits with one LDS atomic per (class, divisor) instead of one
+      // per divisible size.  The sort's key buffer is free here and holds M_d.
       const int nd = p.ndiv;
       const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
+      uint64_t *dmul = reinterpret_cast<uint64_t *>(keys);
       for (int k = tid; k < 256; k += NT) {
-        sm.hist[k] = k < nd ? (uint32_t)dv[k] : 1u;
+        const uint32_t dk = k < nd ? (uint32_t)dv[k] : 1u;
+        dmul[k] = ~0ull / dk + 1ull;
         sm.wcnt[0][k] = 0;
         sm.wcnt[1][k] = 0;
       }
       __syncthreads();
-      for (int i = tid; i < r; i += NT) {
-        const int cls = (i >= nf && i < nb) ? 1 : ((i >= nm && i < nz) ? 0 : -1);
-        if (cls < 0) continue;
-        const uint32_t w = sz[i];
-        for (int k = 0; k < nd; ++k)
-          if (w % sm.hist[k] == 0u) atomicAdd(&sm.wcnt[cls][k], 1u);
+      for (int base = 0; base < r; base += NT) {
+        const int i = base + tid;
+        const bool in_r = i < r;
+        const bool big = in_r && i >= nf && i < nb;
+        const bool small = in_r && i >= nm && i < nz;
+        if (ballot64(big || small) == 0ull) continue;  // wave-uniform
+        const uint64_t w = in_r ? (uint64_t)sz[i] : 0ull;
+        for (int k = 0; k < nd; ++k) {
+          const uint64_t mk = dmul[k];
+          const bool hit = w * mk <= mk - 1ull;
+          const uint64_t bs = ballot64(small && hit), bb = ballot64(big && hit);
+          if ((tid & 63) == 0) {
+            if (bs) atomicAdd(&sm.wcnt[0][k], (uint32_t)__popcll(bs));
+            if (bb) atomicAdd(&sm.wcnt[1][k], (uint32_t)__popcll(bb));
+          }
+        }
       }
       __syncthreads();
       int32_t *dc = d.dcnt + p.dc_off;

@@ -99,6 +99,18 @@ def test_vb2_reciprocal_large_capacities():
         assert bp.selftest_division(c, c, 2048, 1) == 0, c
 
 
+def test_divisibility_test_exhaustive_small_divisors():
+    # d | n as n * ceil(2^64 / d) mod 2^64 <= ceil(2^64 / d) - 1, every d < 2^11 and n < 2^13 (plus multiples)
+    assert bp.selftest_division(1, 2048, 8192, 2) == 0
+
+
+def test_divisibility_test_edge_divisors():
+    # divisors of the capacities the segment sums meet, powers of two and the top of the int32 range
+    for lo, hi in [(2**15 - 3, 2**15 + 3), (2**20 - 1, 2**20 + 1), (2**30 - 2, 2**30 + 2), (2**31 - 4, 2**31 - 1),
+                   (3125, 3125), (50_000, 50_000), (99_999, 100_001), (999_999, 1_000_001)]:
+        assert bp.selftest_division(lo, hi, 4096, 2) == 0, (lo, hi)
+
+
 def test_selftest_rejects_bad_ranges():
     assert bp.selftest_division(0, 10, 10, 0) == bp.BP_ERR_ARG
     assert bp.selftest_division(10, 5, 10, 0) == bp.BP_ERR_ARG
