@@ -152,11 +152,12 @@ struct PrepSmem {
 // wave ranks its keys in that order: a key's peers (lanes with the same
 // digit) come from ballots over the digit's bits, its rank is the wave's
 // running count of the digit plus the peers below it.  One block-wide scan
-// over (digit, wave) counts then gives every key its place.  Keys are <= c,
-// so a pass looks only at the bits below `bits`.  Returns the buffer index
-// holding the result.
+// over (digit, wave) counts then gives every key its place.  The digits are
+// those of key - kmin, kmin the smallest key, so the passes cover only the
+// bits of kmax - kmin (all keys equal or n = 0: no pass).  Returns the buffer
+// index holding the result.
 template <int NT, int CAP>
-__device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
+__device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n) {
   constexpr int NW = NT / 64;
   constexpr int K = CAP / NT;
   static_assert(K * NT == CAP, "capacity must be a multiple of the block size");
@@ -166,6 +167,30 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
   const int wbase = wave * 64 * K;
   // number of key rows of this wave that hold any key (wave-uniform)
   const int rows = n > wbase ? min(K, (n - wbase + 63) >> 6) : 0;
+  // key range: per-wave minimum and maximum, then every thread combines them
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
+  for (int k = 0; k < rows; ++k) {
+    const int i = wbase + 64 * k + lane;
+    if (i < n) {
+      const uint32_t v = sm.keys[0][i];
+      kmin = min(kmin, v);
+      kmax = max(kmax, v);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, off));
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+  }
+  if (lane == 0) sm.wtot[wave] = ((uint64_t)kmax << 32) | (uint64_t)kmin;
+  __syncthreads();
+  kmin = 0xffffffffu;
+  kmax = 0u;
+  for (int w = 0; w < NW; ++w) {
+    const uint64_t mm = sm.wtot[w];
+    kmin = min(kmin, (uint32_t)mm);
+    kmax = max(kmax, (uint32_t)(mm >> 32));
+  }
+  const int bits = kmax > kmin ? 32 - __clz((int)(kmax - kmin)) : 0;
   int src = 0;
   for (int sh = 0; sh < bits; sh += 8) {
     const uint32_t *a = sm.keys[src];
@@ -180,13 +205,17 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
       if (k < rows) {
         const int i = wbase + 64 * k + lane;
         const bool valid = i < n;
-        key[k] = valid ? a[i] : 0xffffffffu;
-        const uint32_t d = (key[k] >> sh) & 255u;
+        key[k] = valid ? a[i] : kmin;
+        const uint32_t d = ((key[k] - kmin) >> sh) & 255u;
+        // peers: the valid lanes whose digit equals this lane's, one ballot
+        // per digit bit; a lane keeps the lanes that agree with it on the bit
+        // (~(m ^ s) is m where its bit is set, ~m where it is clear)
         uint64_t peers = ballot64(valid);
         for (int bit = 0; bit < dbits; ++bit) {
-          const bool set = (d >> bit) & 1u;
-          const uint64_t m = ballot64(valid && set);
-          peers &= set ? m : ~m;
+          const uint32_t s32 = (uint32_t)__builtin_amdgcn_sbfe((int)d, (unsigned)bit, 1u);  // 0 or all ones
+          const uint64_t m = ballot64(s32 != 0u);
+          const uint64_t s64 = ((uint64_t)s32 << 32) | (uint64_t)s32;
+          peers &= ~(m ^ s64);
         }
         const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
         // the wave's LDS accesses complete in program order: every lane reads
@@ -222,7 +251,7 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n, int bits) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (k < rows && wbase + 64 * k + lane < n) {
-        const uint32_t d = (key[k] >> sh) & 255u;
+        const uint32_t d = ((key[k] - kmin) >> sh) & 255u;
         b[sm.hist[d] + sm.wcnt[wave][d] + rank[k]] = key[k];
       }
     }
@@ -352,8 +381,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
       status = BP_ERR_RANGE;
       r = 0;
     }
-    const int bits = 32 - __clz((int)uC);  // keys are <= c
-    const int res_buf = lds_radix_sort<NT, CAP>(sm, (int)r, bits);
+    const int res_buf = lds_radix_sort<NT, CAP>(sm, (int)r);
     uint32_t *keys = sm.keys[res_buf];
     uint32_t *sz = sm.keys[res_buf ^ 1];
     for (int i = tid; i < r; i += NT) sz[i] = uC - keys[i];
@@ -409,9 +437,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     if (p.ndiv > 0) {
       // mirrored VB2: per divisor d of c, the small and the big sizes that d
       // divides (the counts in wcnt[0..1])
-      // d | w is tested as (w * M_d mod 2^64) < M_d with M_d = ceil(2^64 / d)
-      // (Lemire, Kaser, Kurz 2019, "Faster remainder by direct computation";
-      // exact for every 32-bit w and d >= 1, M_1 wraps to 0), and each wave
+      // d | w by the multiply-compare test of bp_divide.h (family 3), and each wave
       // adds its hits with one LDS atomic per (class, divisor) instead of one
       // per divisible size.  The sort's key buffer is free here and holds M_d.
       const int nd = p.ndiv;
@@ -419,7 +445,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
       uint64_t *dmul = reinterpret_cast<uint64_t *>(keys);
       for (int k = tid; k < 256; k += NT) {
         const uint32_t dk = k < nd ? (uint32_t)dv[k] : 1u;
-        dmul[k] = ~0ull / dk + 1ull;
+        dmul[k] = divides_const(dk);
         sm.wcnt[0][k] = 0;
         sm.wcnt[1][k] = 0;
       }
@@ -430,10 +456,10 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
         const bool big = in_r && i >= nf && i < nb;
         const bool small = in_r && i >= nm && i < nz;
         if (ballot64(big || small) == 0ull) continue;  // wave-uniform
-        const uint64_t w = in_r ? (uint64_t)sz[i] : 0ull;
+        const uint32_t w = in_r ? sz[i] : 0u;
         for (int k = 0; k < nd; ++k) {
           const uint64_t mk = dmul[k];
-          const bool hit = w * mk <= mk - 1ull;
+          const bool hit = divides_u32(w, mk);
           const uint64_t bs = ballot64(small && hit), bb = ballot64(big && hit);
           if ((tid & 63) == 0) {
             if (bs) atomicAdd(&sm.wcnt[0][k], (uint32_t)__popcll(bs));
