@@ -128,20 +128,58 @@ static int ilog2ceil(int64_t x) {
   return l;
 }
 
-// Divisors of c in ascending order, by trial division up to sqrt(c) (cached
-// per context: a batch or a served stream has few distinct capacities).
-static const std::vector<int32_t> &divisors_of(Ctx *c, int32_t C) {
+// Divisors of c in ascending order, by trial division up to sqrt(c), and
+// c's prime factorisation with each divisor's place in the lattice of
+// exponent vectors (cached per context: a batch or a served stream has few
+// distinct capacities).
+static const Ctx::DivInfo &divisors_of(Ctx *c, int32_t C) {
   auto it = c->div_cache.find(C);
   if (it != c->div_cache.end()) return it->second;
   if (c->div_cache.size() > 4096) c->div_cache.clear();
-  std::vector<int32_t> lo, hi;
+  Ctx::DivInfo info;
+  std::vector<int32_t> hi;
   for (int64_t i = 1; i * i <= (int64_t)C; ++i) {
     if (C % i) continue;
-    lo.push_back((int32_t)i);
+    info.divs.push_back((int32_t)i);
     if (i * i != (int64_t)C) hi.push_back((int32_t)(C / i));
   }
-  lo.insert(lo.end(), hi.rbegin(), hi.rend());
-  return c->div_cache.emplace(C, std::move(lo)).first->second;
+  info.divs.insert(info.divs.end(), hi.rbegin(), hi.rend());
+  std::vector<int64_t> pr;
+  std::vector<int32_t> ex;
+  int64_t x = C;
+  for (int64_t q = 2; q * q <= x; ++q) {
+    if (x % q) continue;
+    int32_t a = 0;
+    while (x % q == 0) {
+      x /= q;
+      ++a;
+    }
+    pr.push_back(q);
+    ex.push_back(a);
+  }
+  if (x > 1) {
+    pr.push_back(x);
+    ex.push_back(1);
+  }
+  for (int32_t d : info.divs) {
+    int64_t bin = 0, stride = 1, y = d;
+    for (size_t j = 0; j < pr.size(); ++j) {
+      int32_t e = 0;
+      while (y % pr[j] == 0) {
+        y /= pr[j];
+        ++e;
+      }
+      bin += e * stride;
+      stride *= ex[j] + 1;
+    }
+    info.lattice.push_back((int32_t)bin);
+  }
+  info.lattice.push_back((int32_t)pr.size());
+  for (size_t j = 0; j < pr.size(); ++j) {
+    info.lattice.push_back((int32_t)pr[j]);
+    info.lattice.push_back(ex[j]);
+  }
+  return c->div_cache.emplace(C, std::move(info)).first->second;
 }
 
 // Checks a caller range against the paper's range of that bound.
@@ -398,12 +436,15 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         const bool has1 = a1 <= b1, has2 = a2 <= b2;
         const int64_t lm = std::min(has1 ? a1 : a2, has2 ? a2 : a1), mm = std::max(has1 ? b1 : b2, has2 ? b2 : b1);
         const int64_t need = (has1 ? b1 - a1 + 1 : 0) + (has2 ? b2 - a2 + 1 : 0);
-        const std::vector<int32_t> &dv = divisors_of(this, q.C);
+        const Ctx::DivInfo &di = divisors_of(this, q.C);
+        const std::vector<int32_t> &dv = di.divs;
         if (has1 && has2 && (double)(mm - lm + 1) < 0.75 * (double)need && (int)dv.size() <= kMaxDivs) {
+          // the divisors, then the lattice block the prep's multiple counts use
           p.div_off = (int64_t)div_vec.size();
           p.ndiv = (int32_t)dv.size();
           p.dc_off = dcnt;
           div_vec.insert(div_vec.end(), dv.begin(), dv.end());
+          div_vec.insert(div_vec.end(), di.lattice.begin(), di.lattice.end());
           dcnt += 2 * (int64_t)dv.size();
           e.mode = kModeMirror;
           e.lam0 = lm;
@@ -438,11 +479,29 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   const int64_t min_chunk = tune.min_chunk;
   const double target = std::max(1.0, total / ((double)tune.tasks_per_wave * (double)grid_sweep));
   std::vector<double> task_cost(ent.size());
+  // A BJ1 or CCM1 segment tile walks its 2K windows one after another, each a
+  // short chain of dependent loads.  When the launch has fewer such tiles
+  // than resident waves (one large instance), that chain and not the issue
+  // rate sets the sweep's length, so their q range is split into chunks of
+  // at most kSegQPerChunk values, each a task of its own; a launch with more
+  // tiles keeps them whole (its waves hide the latency, and split tiles cost
+  // partial-sum slots).
+  int64_t seg_tiles = 0;
+  for (const Entry &e : ent)
+    if (e.mode == kModeSegments && (e.bound == kBJ1 || e.bound == kCCM1)) seg_tiles += e.ntiles;
+  const bool split_seg = seg_tiles < (int64_t)grid_sweep;
   int64_t acc = 0, cnt = 0;
   for (size_t j = 0; j < ent.size(); ++j) {
     Entry &e = ent[j];
     const double tc = tile_cost_v[j];
-    if (tc <= target || e.bound == kL2 || e.mode == kModeSegments) {
+    if (split_seg && e.mode == kModeSegments && (e.bound == kBJ1 || e.bound == kCCM1)) {
+      const int64_t C = pin[e.inst].C;
+      const int64_t knum = e.bound == kBJ1 ? C : C / 2;
+      const int64_t kfirst = knum / std::max<int64_t>(1, e.lam0);  // the entry's largest window count
+      e.nchunks = (int32_t)std::min<int64_t>(64, std::max<int64_t>(1, (kfirst + kSegQPerChunk - 1) / kSegQPerChunk));
+      e.tpt = 1;
+      task_cost[j] = tc / e.nchunks;
+    } else if (tc <= target || e.bound == kL2 || e.mode == kModeSegments) {
       double tpt = std::floor(target / tc);
       tpt = std::min(std::max(tpt, 1.0), std::min((double)e.ntiles, 1e9));
       e.tpt = (int32_t)tpt;

@@ -71,7 +71,13 @@ struct Ctx {
   int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
   int64_t ws_items = 0, pre_items = 0, bidx_items = 0, dcnt_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
   std::vector<int32_t> div_vec;  // divisor lists of this launch (staged with the plan)
-  std::unordered_map<int32_t, std::vector<int32_t>> div_cache;  // divisors of c by c
+  // divisors of c by c, and c's divisor lattice: per divisor its bin
+  // sum_j e_j stride_j (e_j its exponent of the j-th prime of c, stride_j =
+  // prod_{i<j} (a_i + 1)), then the prime count and (prime, exponent) pairs
+  struct DivInfo {
+    std::vector<int32_t> divs, lattice;
+  };
+  std::unordered_map<int32_t, DivInfo> div_cache;
   std::vector<InstPlan> plan_vec;
   std::vector<Entry> entry_vec;
 

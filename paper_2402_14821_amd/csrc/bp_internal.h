@@ -25,6 +25,7 @@ constexpr int kQueueStride = 32;
 constexpr int kSegTiles = 8;
 // Largest K = floor(c / lambda) a segment tile of BJ1 handles (2K windows).
 constexpr int kSegMaxK = 64;
+constexpr int kSegQPerChunk = 8;  // q values per chunk of a split BJ1/CCM1 segment tile
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
@@ -119,7 +120,7 @@ struct LaunchDesc {
   unsigned long long *counter; // kQueues task counters of the persistent sweep, kQueueStride apart
   long long *acc;           // partial sums of split tiles, one slot per (tile, chunk, parameter)
   int32_t *bidx;            // threshold tables: bidx[b] = #{sorted sizes >= b 2^bshift}
-  const int32_t *divs;      // divisor lists of the capacities (mirrored VB2)
+  const int32_t *divs;      // per mirrored instance: divisors of c (ascending), their lattice bins, prime count, (prime, exponent) pairs
   int32_t *dcnt;            // per divisor d: #{small sizes divisible by d}, then the same for big sizes
   bp_bounds *out;           // [count] results
   int64_t count;            // instances

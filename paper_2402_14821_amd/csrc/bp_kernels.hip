@@ -436,42 +436,72 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     __syncthreads();
     if (p.ndiv > 0) {
       // mirrored VB2: per divisor d of c, the small and the big sizes that d
-      // divides (the counts in wcnt[0..1])
-      // d | w by the multiply-compare test of bp_divide.h (family 3), and each wave
-      // adds its hits with one LDS atomic per (class, divisor) instead of one
-      // per divisible size.  The sort's key buffer is free here and holds M_d.
-      const int nd = p.ndiv;
+      // divides.  With c = prod p_j^a_j, d | w iff every exponent of d is at
+      // most min(v_pj(w), a_j).  Each size adds 1 to the lattice bin of its
+      // capped exponent vector (about two multiply-compare divisibility tests
+      // of bp_divide.h per prime, family 3); superset sums along each prime's
+      // axis then turn the bins into the count of multiples of every divisor.
+      // wcnt[0..1] hold the small and the big class; the sort's key buffer is
+      // free here and holds the test constants of p_j^e, e = 1..a_j.
+      const int nd = p.ndiv;  // = number of lattice bins
       const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
-      uint64_t *dmul = reinterpret_cast<uint64_t *>(keys);
+      const BP_GLOBAL int32_t *dbin = dv + nd;
+      const int np = dv[2 * nd];
+      const BP_GLOBAL int32_t *pa = dv + 2 * nd + 1;  // (p_j, a_j) pairs
+      uint64_t *pmul = reinterpret_cast<uint64_t *>(keys);
+      if (tid == 0) {
+        int o = 0;
+        for (int j = 0; j < np; ++j) {
+          uint32_t q = 1;
+          for (int e = 1; e <= pa[2 * j + 1]; ++e) {
+            q *= (uint32_t)pa[2 * j];  // p_j^e divides c < 2^31
+            pmul[o++] = divides_const(q);
+          }
+        }
+      }
       for (int k = tid; k < 256; k += NT) {
-        const uint32_t dk = k < nd ? (uint32_t)dv[k] : 1u;
-        dmul[k] = divides_const(dk);
         sm.wcnt[0][k] = 0;
         sm.wcnt[1][k] = 0;
       }
       __syncthreads();
-      for (int base = 0; base < r; base += NT) {
-        const int i = base + tid;
-        const bool in_r = i < r;
-        const bool big = in_r && i >= nf && i < nb;
-        const bool small = in_r && i >= nm && i < nz;
-        if (ballot64(big || small) == 0ull) continue;  // wave-uniform
-        const uint32_t w = in_r ? sz[i] : 0u;
-        for (int k = 0; k < nd; ++k) {
-          const uint64_t mk = dmul[k];
-          const bool hit = divides_u32(w, mk);
-          const uint64_t bs = ballot64(small && hit), bb = ballot64(big && hit);
-          if ((tid & 63) == 0) {
-            if (bs) atomicAdd(&sm.wcnt[0][k], (uint32_t)__popcll(bs));
-            if (bb) atomicAdd(&sm.wcnt[1][k], (uint32_t)__popcll(bb));
-          }
+      for (int i = tid; i < r; i += NT) {
+        const int cls = (i >= nf && i < nb) ? 1 : ((i >= nm && i < nz) ? 0 : -1);
+        if (cls < 0) continue;
+        const uint32_t w = sz[i];
+        int bin = 0, stride = 1, o = 0;
+        for (int j = 0; j < np; ++j) {
+          const int aj = pa[2 * j + 1];
+          int e = 0;
+          while (e < aj && divides_u32(w, pmul[o + e])) ++e;
+          bin += e * stride;
+          stride *= aj + 1;
+          o += aj;
         }
+        atomicAdd(&sm.wcnt[cls][bin], 1u);
       }
       __syncthreads();
+      {
+        int stride = 1;
+        for (int j = 0; j < np; ++j) {
+          const int aj = pa[2 * j + 1];
+          for (int e = aj - 1; e >= 0; --e) {
+            // bins whose j-th exponent is e take the sums of the bins one step up
+            for (int b = tid; b < nd; b += NT) {
+              if ((b / stride) % (aj + 1) == e) {
+                sm.wcnt[0][b] += sm.wcnt[0][b + stride];
+                sm.wcnt[1][b] += sm.wcnt[1][b + stride];
+              }
+            }
+            __syncthreads();
+          }
+          stride *= aj + 1;
+        }
+      }
       int32_t *dc = d.dcnt + p.dc_off;
       for (int k = tid; k < nd; k += NT) {
-        dc[k] = (int32_t)sm.wcnt[0][k];
-        dc[nd + k] = (int32_t)sm.wcnt[1][k];
+        const int bk = dbin[k];
+        dc[k] = (int32_t)sm.wcnt[0][bk];
+        dc[nd + k] = (int32_t)sm.wcnt[1][bk];
       }
       __syncthreads();
     }
@@ -545,8 +575,10 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
 // A tile's items may be split into chunks run by different waves.  Every
 // function's per-parameter sum is an instance constant plus a part that is a
 // plain sum over the streamed items, so a chunk computes that part exactly
-// (int64) over its items; parts of different chunks are added with 64-bit
-// atomics and the wave that finishes a tile's last chunk finalises it.
+// (int64) over its items and stores it in a slot of its own; after the sweep
+// the combine kernel adds a tile's slots and finalises the tile.  Split BJ1
+// and CCM1 segment tiles divide their q range instead of the items, the
+// instance constant going with chunk 0.
 // Streamed items are [nf, nz); functions with a class split stream
 // [nf, nb) (big) and [nm, nz) (small) and count the mid items.
 
@@ -565,6 +597,7 @@ struct TileArgs {
   const BP_CONST int64_t *prec;  // prefix sums again, for scalar loads
   int32_t bsh;                   // bucket width 2^bsh of the table
   int32_t ndiv;                  // mirrored VB2: divisors of c
+  int32_t qc, qn;                // BJ1/CCM1 segment tiles: this chunk of qn takes its share of the q range
   const BP_GLOBAL int32_t *divs; // ascending
   const BP_GLOBAL int32_t *dcnt; // [small x ndiv][big x ndiv] multiple counts
 };
@@ -920,8 +953,11 @@ __device__ void part_bj1_seg(const TileArgs &t, const int64_t lam_out[LPL], int6
     K[j] = (int32_t)((uint32_t)C / lam[j]);
   }
   const int32_t kmax = (int32_t)(C / l0);
+  // chunk qc of qn takes q in [1 + floor(kmax qc / qn), floor(kmax (qc + 1) / qn)]
+  const int32_t qa = 1 + (int32_t)((int64_t)kmax * t.qc / t.qn);
+  const int32_t qb = (int32_t)((int64_t)kmax * (t.qc + 1) / t.qn);
   int64_t acc[LPL] = {};
-  for (int32_t q = 1; q <= kmax; ++q) {
+  for (int32_t q = qa; q <= qb; ++q) {
     uint32_t th[LPL];
     int64_t u[LPL];
     {
@@ -937,8 +973,10 @@ __device__ void part_bj1_seg(const TileArgs &t, const int64_t lam_out[LPL], int6
       for (int j = 0; j < LPL; ++j) acc[j] += q <= K[j] ? u[j] : 0;
     }
   }
+  // the instance constant goes with chunk 0 only, so the chunks' parts add up
   const int64_t n = t.nz - t.nf;
-  for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j] - t.sumNZ + n * (int64_t)((uint32_t)C % lam[j]);
+  for (int j = 0; j < LPL; ++j)
+    part[j] = 2 * acc[j] - (t.qc == 0 ? t.sumNZ - n * (int64_t)((uint32_t)C % lam[j]) : 0);
 }
 
 // #{w in [i0, i1) : w >= th[j]} for thresholds in [tlo, thi], 1 <= tlo:
@@ -977,8 +1015,11 @@ __device__ void part_ccm1_seg(const TileArgs &t, const int64_t lam_out[LPL], int
   const int64_t bfloor = half + 1;       // every big size reaches it
   const int64_t nbig = t.nb - t.nf;
   const int32_t qmax = (int32_t)(half / l0);
+  // chunk qc of qn takes q in [1 + floor(qmax qc / qn), floor(qmax (qc + 1) / qn)]
+  const int32_t qa = 1 + (int32_t)((int64_t)qmax * t.qc / t.qn);
+  const int32_t qb = (int32_t)((int64_t)qmax * (t.qc + 1) / t.qn);
   int64_t acc[LPL] = {};
-  for (int32_t q = 1; q <= qmax; ++q) {
+  for (int32_t q = qa; q <= qb; ++q) {
     uint32_t th[LPL];
     int64_t c[LPL];
     {
@@ -1256,6 +1297,9 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   const int64_t span = (int64_t)t.nz - t.nf;
   t.i0 = t.nf + (int32_t)(span * chunk / nch);
   t.i1 = t.nf + (int32_t)(span * (chunk + 1) / nch);
+  // a split BJ1/CCM1 segment tile divides its q range instead
+  t.qc = chunk;
+  t.qn = nch;
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
     if (early && refuted_now(d, inst)) return;
