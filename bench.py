@@ -227,6 +227,36 @@ def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain
                 for c in sorted(set(int(x) for x in Cs))}}
 
 
+def per_bound_table(bp, W, ctx, reps: int = 5):
+    """Sweep stage time of each DFF bound alone on the single large residual
+    instance, dense and segment form (the other ranges empty), from the
+    library's stage events; both forms must give the same bounds."""
+    C, m, residual, unpacked = W.large_residual(seed=1)
+    items = ctx.residual_reduce(C, residual, unpacked)
+    full = bp.default_sweep(C)
+    rows = []
+    for name, bounds in [(n, {bp.BP_MT + j}) for j, n in enumerate(DFF_NAMES)] + [("ALL", set(range(bp.BP_MT, 8)))]:
+        row = {"bound": name}
+        vals = []
+        for form, flags in (("dense", 0), ("segments", bp.BP_SWEEP_SEGMENTS)):
+            lo = [full.lo[b] if b in bounds else 1 for b in range(8)]
+            hi = [full.hi[b] if b in bounds else 0 for b in range(8)]
+            sw = bp.make_sweep(lo, hi, flags)
+            rec = ctx.lower_bounds(C, m, items, sw)  # warm-up (plan, graph)
+            ctx.set_timing(True)
+            for _ in range(reps):
+                ctx.lower_bounds(C, m, items, sw)
+            (p_ms, s_ms, _), _ = ctx.stage_times(with_runs=True)
+            ctx.set_timing(False)
+            row[form] = {"prep_us": p_ms * 1e3, "sweep_us": s_ms * 1e3}
+            vals.append(list(rec["value"]))
+        row["same_bounds"] = vals[0] == vals[1]
+        rows.append(row)
+        log(f"per-bound {name} done")
+    return {"workload": "single large residual instance, each DFF bound's full range alone", "r": int(len(items)),
+            "reps": reps, "rows": rows}
+
+
 def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30, flags: int = 0):
     """Open-loop Poisson arrivals of DFS requests into a bp_queue; latency from the library's clock."""
     import ctypes
@@ -301,6 +331,8 @@ def main():
     ap.add_argument("--latency-checks", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--per-bound", action="store_true",
+                    help="only time each DFF sweep alone on the large instance, dense and segment form, and exit")
     ap.add_argument("--no-segments", action="store_true",
                     help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
     ap.add_argument("--served-seconds", type=float, default=0.25)
@@ -327,6 +359,11 @@ def main():
 
     import paper_2402_14821_amd as bp
     from paper_2402_14821_amd import workloads as W
+
+    if args.per_bound:
+        with bp.Context(0) as pctx:
+            print(json.dumps(per_bound_table(bp, W, pctx)), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     C, m, residual, unpacked = W.large_residual(seed=1)
