@@ -241,10 +241,7 @@ bp_status Ctx::init(int dev) {
 void Ctx::destroy() {
   if (device >= 0) (void)hipSetDevice(device);
   if (stream) (void)hipStreamSynchronize(stream);
-  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  graph_exec = nullptr;
-  graph = nullptr;
+  drop_graphs();
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
                     &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf})
     b->release();
@@ -263,20 +260,29 @@ void Ctx::destroy() {
 
 void Ctx::apply_tuning() { grid_sweep = num_cu * tune.waves_per_cu; }
 
-// Captures the pipeline once per shape (parameters per lane, sweep grid);
-// every call replays it.
-bp_status Ctx::ensure_graph(const LaunchDesc *d_desc) {
-  if (!use_graph) return BP_OK;
-  if (graph_exec && (graph_lpl != tune.lanes_params || graph_grid != grid_sweep)) {
-    (void)hipGraphExecDestroy(graph_exec);
-    (void)hipGraphDestroy(graph);
-    graph_exec = nullptr;
-    graph = nullptr;
+void Ctx::drop_graphs() {
+  for (int v = 0; v < 4; ++v) {
+    if (graph_exec[v]) (void)hipGraphExecDestroy(graph_exec[v]);
+    if (graph[v]) (void)hipGraphDestroy(graph[v]);
+    graph_exec[v] = nullptr;
+    graph[v] = nullptr;
   }
-  if (graph_exec) return BP_OK;
+}
+
+// Captures the pipeline variant v once per shape (parameters per lane, sweep
+// grid); every call with that variant replays it.
+bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, int v) {
+  if (!use_graph) return BP_OK;
+  if (graph_exec[v] && (graph_lpl[v] != tune.lanes_params || graph_grid[v] != grid_sweep)) {
+    (void)hipGraphExecDestroy(graph_exec[v]);
+    (void)hipGraphDestroy(graph[v]);
+    graph_exec[v] = nullptr;
+    graph[v] = nullptr;
+  }
+  if (graph_exec[v]) return BP_OK;
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
-                                  stream);
+                                  (v & 1) != 0, (v & 2) != 0, stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
   if (le != hipSuccess) {
@@ -290,10 +296,10 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc) {
     (void)hipGraphDestroy(g);
     return hip_fail(ie, "hipGraphInstantiate");
   }
-  graph = g;
-  graph_exec = ex;
-  graph_lpl = tune.lanes_params;
-  graph_grid = grid_sweep;
+  graph[v] = g;
+  graph_exec[v] = ex;
+  graph_lpl[v] = tune.lanes_params;
+  graph_grid[v] = grid_sweep;
   return BP_OK;
 }
 
@@ -508,7 +514,10 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       e.nchunks = 1;
       task_cost[j] = tc * tpt;
     } else {
-      const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / min_chunk);
+      // an entry of a few tiles (FS1's 100 parameters, the single mirrored VB2
+      // parameters) would otherwise be a few long chains: chunks down to 256 items
+      const int64_t minc = e.ntiles < 4 ? std::min<int64_t>(min_chunk, 256) : min_chunk;
+      const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / minc);
       const int64_t want = (int64_t)std::ceil(tc / target);
       e.nchunks = (int32_t)std::min<int64_t>(std::min<int64_t>(want, maxch), 64);
       e.tpt = 1;
@@ -566,13 +575,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if ((st = stage_host.reserve(total))) return st;
   void *old_dev = stage_buf.p;
   if ((st = stage_buf.reserve(total))) return st;
-  if (stage_buf.p != old_dev && graph_exec) {
-    // the graph holds the descriptor's address: capture again
-    (void)hipGraphExecDestroy(graph_exec);
-    (void)hipGraphDestroy(graph);
-    graph_exec = nullptr;
-    graph = nullptr;
-  }
+  if (stage_buf.p != old_dev) drop_graphs();  // the graphs hold the descriptor's address: capture again
   if ((st = state_buf.reserve(sizeof(InstState) * count))) return st;
   if ((st = sorted_buf.reserve(sizeof(int32_t) * ws_items))) return st;
   if ((st = rec_buf.reserve(sizeof(uint32_t) * ws_items))) return st;
@@ -613,16 +616,21 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   HIP_TRY(hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(staged, s));
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
+  bool with_large = false;
+  for (int64_t i = 0; i < count && !with_large; ++i) with_large = plan_vec[i].large != 0;
+  const bool with_combine = nsplit > 0;
+  const int v = (with_large ? 1 : 0) | (with_combine ? 2 : 0);
   if (timing) {
     hipEvent_t *ev = nullptr;
     if ((st = timing_slot(&ev))) return st;
     HIP_TRY(launch_pipeline_timed(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
-                                  s, ev));
+                                  with_large, with_combine, s, ev));
   } else if (use_graph) {
-    if ((st = ensure_graph(d_desc))) return st;
-    HIP_TRY(hipGraphLaunch(graph_exec, s));
+    if ((st = ensure_graph(d_desc, v))) return st;
+    HIP_TRY(hipGraphLaunch(graph_exec[v], s));
   } else {
-    HIP_TRY(launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin, s));
+    HIP_TRY(launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
+                            with_large, with_combine, s));
   }
   return BP_OK;
 }

@@ -19,9 +19,10 @@ void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]);
 // kernels (bp_kernels.hip)
 hipError_t set_kernel_attrs();
 hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                           int grid_comb, int grid_fin, hipStream_t s);
+                           int grid_comb, int grid_fin, bool with_large, bool with_combine, hipStream_t s);
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_sweep, int grid_comb, int grid_fin, hipStream_t s, hipEvent_t ev[4]);
+                                 int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
+                                 hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
                          int64_t n, unsigned long long *loads, int32_t *out, int64_t *out_r, int32_t *out_residual,
                          int32_t *bad, hipStream_t s);
@@ -64,11 +65,13 @@ struct Ctx {
   hipEvent_t tev[kTimingRing][4] = {};
   int64_t t_runs = 0, t_folded = 0;
   double t_sum[3] = {0, 0, 0};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  // captured pipelines, one per variant (bit 0: large-instance prep, bit 1: combine)
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
-  int graph_lpl = 0, graph_grid = 0;   // shape the captured graph was made with
+  int graph_lpl[4] = {0, 0, 0, 0}, graph_grid[4] = {0, 0, 0, 0};  // shape each graph was captured with
+  void drop_graphs();
   int64_t ws_items = 0, pre_items = 0, bidx_items = 0, dcnt_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
   std::vector<int32_t> div_vec;  // divisor lists of this launch (staged with the plan)
   // divisors of c by c, and c's divisor lattice: per divisor its bin
@@ -87,7 +90,7 @@ struct Ctx {
 
   bp_status init(int dev);
   void destroy();
-  bp_status ensure_graph(const LaunchDesc *d_desc);
+  bp_status ensure_graph(const LaunchDesc *d_desc, int v);
   bp_status plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out);
   bp_status run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len, const int32_t *in_dev,
                 bp_bounds *out_dev, hipStream_t s);

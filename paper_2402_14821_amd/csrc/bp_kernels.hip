@@ -1608,36 +1608,44 @@ static hipError_t launch_combine(const LaunchDesc *d_desc, int lpl, int grid_com
   return hipGetLastError();
 }
 
+// The large-instance prep runs only when the launch holds a large instance and
+// the combine only when it has split tiles (either would find no work); the
+// small-instance prep always runs, as it clears the sweep's task counters.
 hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                           int grid_comb, int grid_fin, hipStream_t s) {
+                           int grid_comb, int grid_fin, bool with_large, bool with_combine, hipStream_t s) {
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
                      prep_smem_small(), s, d_desc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
-                     prep_smem_large(), s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (with_large) {
+    hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
+                       prep_smem_large(), s, d_desc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
-  if ((e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
+  if (with_combine && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   return hipGetLastError();
 }
 
 // The same launches with events around the stages (diagnostic timing).
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_sweep, int grid_comb, int grid_fin, hipStream_t s, hipEvent_t ev[4]) {
+                                 int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
+                                 hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipEventRecord(ev[0], s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
                      prep_smem_small(), s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
-                     prep_smem_large(), s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (with_large) {
+    hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
+                       prep_smem_large(), s, d_desc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-  if ((e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
+  if (with_combine && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipEventRecord(ev[3], s);
