@@ -515,8 +515,11 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       task_cost[j] = tc * tpt;
     } else {
       // an entry of a few tiles (FS1's 100 parameters, the single mirrored VB2
-      // parameters) would otherwise be a few long chains: chunks down to 256 items
-      const int64_t minc = e.ntiles < 4 ? std::min<int64_t>(min_chunk, 256) : min_chunk;
+      // parameters) would otherwise be a few long chains: chunks down to 256
+      // items, but at most 16 of them (the combine adds a tile's chunks in
+      // rounds of four dependent loads)
+      const int64_t minc = e.ntiles < 4 ? std::min<int64_t>(min_chunk, std::max<int64_t>(256, (rcap_v[j] + 15) / 16))
+                                        : min_chunk;
       const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / minc);
       const int64_t want = (int64_t)std::ceil(tc / target);
       e.nchunks = (int32_t)std::min<int64_t>(std::min<int64_t>(want, maxch), 64);
