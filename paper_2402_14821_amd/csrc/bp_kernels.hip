@@ -265,7 +265,7 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n) {
 // the same wave-striped layout as the sort: each wave first sums its keys,
 // then scans them row by row from its offset.
 template <int NT, int CAP>
-__device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n, int64_t *pre) {
+__device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n, int64_t *pre, bool narrow) {
   constexpr int NW = NT / 64;
   constexpr int K = CAP / NT;
   const int tid = threadIdx.x;
@@ -284,13 +284,25 @@ __device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n
   uint64_t carry = 0;
   for (int w = 0; w < wave; ++w) carry += sm.wtot[w];
   if (tid == 0) pre[0] = 0;
-  for (int k = 0; k < rows; ++k) {
-    const int i = wbase + 64 * k + lane;
-    const uint64_t v = i < n ? sizes[i] : 0u;
-    const uint64_t incl = wave_incl_scan_u64(v) + carry;
-    if (i < n) pre[i + 1] = (int64_t)incl;
-    carry = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, 63) |
-            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(incl >> 32), 63) << 32);
+  if (narrow) {
+    // every size < 2^26, so a row of 64 sums below 2^32: 32-bit row scans,
+    // the 64-bit carry added after
+    for (int k = 0; k < rows; ++k) {
+      const int i = wbase + 64 * k + lane;
+      const uint32_t v = i < n ? sizes[i] : 0u;
+      const uint32_t incl32 = wave_incl_scan_u32(v);
+      if (i < n) pre[i + 1] = (int64_t)(carry + incl32);
+      carry += (uint32_t)__builtin_amdgcn_readlane((int)incl32, 63);
+    }
+  } else {
+    for (int k = 0; k < rows; ++k) {
+      const int i = wbase + 64 * k + lane;
+      const uint64_t v = i < n ? sizes[i] : 0u;
+      const uint64_t incl = wave_incl_scan_u64(v) + carry;
+      if (i < n) pre[i + 1] = (int64_t)incl;
+      carry = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, 63) |
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(incl >> 32), 63) << 32);
+    }
   }
   (void)NW;
 }
@@ -432,7 +444,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
       av[i] = (2ull * w > uC) ? uC - w : w;  // c - w for big items, w otherwise
     }
     int64_t *pre = d.pre + p.pre_off;
-    block_prefix<NT, CAP>(sm, sz, (int)r, pre);
+    block_prefix<NT, CAP>(sm, sz, (int)r, pre, uC < (1u << 26));
     __syncthreads();
     if (p.ndiv > 0) {
       // mirrored VB2: per divisor d of c, the small and the big sizes that d
