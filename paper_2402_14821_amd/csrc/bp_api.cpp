@@ -261,28 +261,50 @@ void Ctx::destroy() {
 void Ctx::apply_tuning() { grid_sweep = num_cu * tune.waves_per_cu; }
 
 void Ctx::drop_graphs() {
-  for (int v = 0; v < 4; ++v) {
-    if (graph_exec[v]) (void)hipGraphExecDestroy(graph_exec[v]);
-    if (graph[v]) (void)hipGraphDestroy(graph[v]);
-    graph_exec[v] = nullptr;
-    graph[v] = nullptr;
+  for (auto &kv : graphs) {
+    if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
+    if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
   }
+  graphs.clear();
 }
 
-// Captures the pipeline variant v once per shape (parameters per lane, sweep
-// grid); every call with that variant replays it.
-bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, int v) {
-  if (!use_graph) return BP_OK;
-  if (graph_exec[v] && (graph_lpl[v] != tune.lanes_params || graph_grid[v] != grid_sweep)) {
-    (void)hipGraphExecDestroy(graph_exec[v]);
-    (void)hipGraphDestroy(graph[v]);
-    graph_exec[v] = nullptr;
-    graph[v] = nullptr;
+static int pow2_at_least(int64_t x) {
+  int p = 1;
+  while (p < x && p < (1 << 30)) p <<= 1;
+  return p;
+}
+
+// Kernels and grids of a launch of `count` instances and `ntasks` sweep
+// tasks: each grid is the work it has, rounded up to a power of two (few
+// distinct graphs), and at most the machine-filling size.  The persistent
+// sweep serves its task queues with any grid; a small launch so avoids
+// dispatching thousands of waves that would find no task.
+Ctx::LaunchShape Ctx::shape_of(int64_t count, int64_t ntasks) const {
+  bool with_large = false;
+  for (int64_t i = 0; i < count && !with_large; ++i) with_large = plan_vec[i].large != 0;
+  LaunchShape sh;
+  sh.v = (with_large ? 1 : 0) | (nsplit > 0 ? 2 : 0);
+  sh.lpl = tune.lanes_params;
+  sh.prep_small = std::min(grid_prep_small, pow2_at_least(std::max<int64_t>(count, 1)));
+  sh.prep_large = std::min(grid_prep_large, pow2_at_least(std::max<int64_t>(count, 1)));
+  sh.sweep = std::min(grid_sweep, std::max(64, pow2_at_least(ntasks)));
+  sh.comb = std::min(grid_comb, pow2_at_least(std::max<int64_t>(nsplit, 1)));
+  sh.fin = std::min(grid_fin, pow2_at_least((count + 255) / 256));
+  return sh;
+}
+
+// Captures the pipeline of one launch shape once; every call with that shape
+// replays it (the cache is dropped when it grows past 32 shapes).
+bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hipGraphExec_t *out) {
+  auto it = graphs.find(sh);
+  if (it != graphs.end()) {
+    *out = it->second.ex;
+    return BP_OK;
   }
-  if (graph_exec[v]) return BP_OK;
+  if (graphs.size() >= 32) drop_graphs();
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
-                                  (v & 1) != 0, (v & 2) != 0, stream);
+  hipError_t le = launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, (sh.v & 1) != 0,
+                                  (sh.v & 2) != 0, stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
   if (le != hipSuccess) {
@@ -296,10 +318,8 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, int v) {
     (void)hipGraphDestroy(g);
     return hip_fail(ie, "hipGraphInstantiate");
   }
-  graph[v] = g;
-  graph_exec[v] = ex;
-  graph_lpl[v] = tune.lanes_params;
-  graph_grid[v] = grid_sweep;
+  graphs[sh] = GraphPair{g, ex};
+  *out = ex;
   return BP_OK;
 }
 
@@ -619,21 +639,20 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   HIP_TRY(hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(staged, s));
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
-  bool with_large = false;
-  for (int64_t i = 0; i < count && !with_large; ++i) with_large = plan_vec[i].large != 0;
-  const bool with_combine = nsplit > 0;
-  const int v = (with_large ? 1 : 0) | (with_combine ? 2 : 0);
+  const LaunchShape sh = shape_of(count, ntasks);
+  const bool with_large = (sh.v & 1) != 0, with_combine = (sh.v & 2) != 0;
   if (timing) {
     hipEvent_t *ev = nullptr;
     if ((st = timing_slot(&ev))) return st;
-    HIP_TRY(launch_pipeline_timed(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
-                                  with_large, with_combine, s, ev));
+    HIP_TRY(launch_pipeline_timed(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, with_large,
+                                  with_combine, s, ev));
   } else if (use_graph) {
-    if ((st = ensure_graph(d_desc, v))) return st;
-    HIP_TRY(hipGraphLaunch(graph_exec[v], s));
+    hipGraphExec_t ex = nullptr;
+    if ((st = ensure_graph(d_desc, sh, &ex))) return st;
+    HIP_TRY(hipGraphLaunch(ex, s));
   } else {
-    HIP_TRY(launch_pipeline(d_desc, tune.lanes_params, grid_prep_small, grid_prep_large, grid_sweep, grid_comb, grid_fin,
-                            with_large, with_combine, s));
+    HIP_TRY(launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, with_large,
+                            with_combine, s));
   }
   return BP_OK;
 }

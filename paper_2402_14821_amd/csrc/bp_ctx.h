@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <unordered_map>
 #include <vector>
 
@@ -65,13 +66,27 @@ struct Ctx {
   hipEvent_t tev[kTimingRing][4] = {};
   int64_t t_runs = 0, t_folded = 0;
   double t_sum[3] = {0, 0, 0};
-  // captured pipelines, one per variant (bit 0: large-instance prep, bit 1: combine)
-  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipGraphExec_t graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Grids and kernels of one launch: variant bit 0 = large-instance prep, bit
+  // 1 = combine; each grid at most the machine-filling size of its kernel.
+  struct LaunchShape {
+    int v, lpl, prep_small, prep_large, sweep, comb, fin;
+    bool operator<(const LaunchShape &o) const {
+      const int a[7] = {v, lpl, prep_small, prep_large, sweep, comb, fin};
+      const int b[7] = {o.v, o.lpl, o.prep_small, o.prep_large, o.sweep, o.comb, o.fin};
+      for (int i = 0; i < 7; ++i)
+        if (a[i] != b[i]) return a[i] < b[i];
+      return false;
+    }
+  };
+  struct GraphPair {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+  };
+  std::map<LaunchShape, GraphPair> graphs;  // captured pipelines by shape
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
-  int graph_lpl[4] = {0, 0, 0, 0}, graph_grid[4] = {0, 0, 0, 0};  // shape each graph was captured with
   void drop_graphs();
+  LaunchShape shape_of(int64_t count, int64_t ntasks) const;
   int64_t ws_items = 0, pre_items = 0, bidx_items = 0, dcnt_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
   std::vector<int32_t> div_vec;  // divisor lists of this launch (staged with the plan)
   // divisors of c by c, and c's divisor lattice: per divisor its bin
@@ -90,7 +105,7 @@ struct Ctx {
 
   bp_status init(int dev);
   void destroy();
-  bp_status ensure_graph(const LaunchDesc *d_desc, int v);
+  bp_status ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hipGraphExec_t *ex);
   bp_status plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out);
   bp_status run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len, const int32_t *in_dev,
                 bp_bounds *out_dev, hipStream_t s);
