@@ -53,7 +53,9 @@ def cpu_baseline(C, items, target_s: float):
     import oracle as O
 
     O._load()
-    threads = min(16, os.cpu_count() or 1)
+    host = host_cpu()
+    # every core this process may run on, up to the 16-core share one GPU's process gets on the box
+    threads = max(1, min(16, host["affinity"]))
     ranges = [(d, *O.default_range(d, C)) for d in O.DFFS]
     ranges = [(d, lo, hi) for d, lo, hi in ranges if lo <= hi]
 
@@ -91,9 +93,29 @@ def cpu_baseline(C, items, target_s: float):
         evals = sum(ex.map(run, jobs))
     dt = time.perf_counter() - t0
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "nproc": host["nproc"], "affinity": host["affinity"], "cpu_model": host["model"],
             "sample": f"every {stride}th parameter of each of the six sweeps of the same instance "
-                      f"({evals} (item, parameter) evaluations in {dt:.2f} s wall on {threads} threads; "
-                      f"a single-thread probe puts the whole instance at {full_core_s:.1f} core-s)"}
+                      f"({evals} (item, parameter) evaluations in {dt:.2f} s wall on {threads} threads of "
+                      f"{host['nproc']} logical CPUs, {host['affinity']} in this process's affinity, "
+                      f"{host['model']}; a single-thread probe puts the whole instance at {full_core_s:.1f} core-s)"}
+
+
+def host_cpu():
+    """Logical CPU count, the CPUs this process may use, and the CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return {"nproc": os.cpu_count() or 1, "affinity": aff, "model": model}
 
 
 def sweep_ops(bp, C, r):

@@ -24,7 +24,11 @@
  *     completed.
  *   - The library owns contexts, queues and their device workspaces and frees
  *     them on destroy.  No exception crosses this interface.
- *   - A context may be used by one host thread at a time.
+ *   - A context may be used by one host thread at a time.  The device work of
+ *     a context's calls runs in call order, whatever streams it is queued on:
+ *     each launch waits for the previous launch of the same context (the
+ *     context reuses one set of device workspaces), so a *_dev call followed
+ *     by any other call needs no synchronisation by the caller.
  *   - On error a negative bp_status is returned and bp_last_error() gives a
  *     message for the calling thread.  Output buffers are then unspecified.
  */
@@ -48,7 +52,12 @@ typedef int32_t bp_status;
 #define BP_ERR_STATE (-6)  /* destroyed handle, unknown ticket, queue shut down */
 #define BP_ERR_LIMIT (-7)  /* input larger than the library's limits */
 
-#define BP_MAX_ITEMS (1 << 22) /* largest reduced instance (items, virtual items included) */
+/* Largest instance a check takes: n + m (residual form) or r (items form)
+ * at most BP_MAX_ITEMS, because one workgroup sorts an instance in its LDS;
+ * larger ones are BP_ERR_LIMIT.  The standalone reductions take up to
+ * BP_MAX_REDUCE_ITEMS. */
+#define BP_MAX_ITEMS (1 << 14)
+#define BP_MAX_REDUCE_ITEMS (1 << 30)
 #define BP_MAX_BATCH (1 << 20) /* most instances in one batched call */
 
 /* The bound collection, in the order used for results and tie-breaks: L1 and

@@ -28,7 +28,8 @@ BP_SWEEP_PAPER_VB2_CLAMP = 1
 BP_SWEEP_SEGMENTS = 2
 BP_NO_EARLY_EXIT = 1
 BP_SEGMENTS = 2
-BP_MAX_ITEMS = 1 << 22
+BP_MAX_ITEMS = 1 << 14
+BP_MAX_REDUCE_ITEMS = 1 << 30
 BP_MAX_BATCH = 1 << 20
 
 _i32, _i64, _u32, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64

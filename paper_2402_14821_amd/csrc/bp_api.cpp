@@ -220,6 +220,7 @@ bp_status Ctx::init(int dev) {
   HIP_TRY(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&last_run, hipEventDisableTiming));
   for (auto &set : tev)
     for (hipEvent_t &e : set) HIP_TRY(hipEventCreate(&e));
   bp_status st = counter_buf.reserve(sizeof(unsigned long long) * kQueues * kQueueStride);
@@ -241,6 +242,7 @@ bp_status Ctx::init(int dev) {
 void Ctx::destroy() {
   if (device >= 0) (void)hipSetDevice(device);
   if (stream) (void)hipStreamSynchronize(stream);
+  if (last_run && any_run) (void)hipEventSynchronize(last_run);
   drop_graphs();
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
                     &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf})
@@ -248,6 +250,8 @@ void Ctx::destroy() {
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (staged) (void)hipEventDestroy(staged);
   if (done) (void)hipEventDestroy(done);
+  if (last_run) (void)hipEventDestroy(last_run);
+  last_run = nullptr;
   for (auto &set : tev)
     for (hipEvent_t &e : set) {
       if (e) (void)hipEventDestroy(e);
@@ -260,12 +264,29 @@ void Ctx::destroy() {
 
 void Ctx::apply_tuning() { grid_sweep = num_cu * tune.waves_per_cu; }
 
+// Callers make sure no launch of these graphs is still running
+// (wait_last_run: every launch goes through run(), which records last_run).
 void Ctx::drop_graphs() {
   for (auto &kv : graphs) {
     if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
     if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
   }
   graphs.clear();
+  graph_used.clear();
+}
+
+bp_status Ctx::wait_last_run() {
+  if (any_run) HIP_TRY(hipEventSynchronize(last_run));
+  return BP_OK;
+}
+
+// Grows a device workspace; the old allocation may still be read by the
+// previous launch, so that launch is waited for before it is freed.
+bp_status Ctx::reserve_dev(DevBuf &b, size_t bytes) {
+  if (bytes <= b.cap) return BP_OK;
+  bp_status st = wait_last_run();
+  if (st) return st;
+  return b.reserve(bytes);
 }
 
 static int pow2_at_least(int64_t x) {
@@ -294,14 +315,27 @@ Ctx::LaunchShape Ctx::shape_of(int64_t count, int64_t ntasks) const {
 }
 
 // Captures the pipeline of one launch shape once; every call with that shape
-// replays it (the cache is dropped when it grows past 32 shapes).
+// replays it.  At most 32 shapes are kept: past that the least recently used
+// graph is destroyed, once the launch before this one has finished.
 bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hipGraphExec_t *out) {
   auto it = graphs.find(sh);
   if (it != graphs.end()) {
+    graph_used[sh] = run_count;
     *out = it->second.ex;
     return BP_OK;
   }
-  if (graphs.size() >= 32) drop_graphs();
+  if (graphs.size() >= 32) {
+    bp_status st = wait_last_run();
+    if (st) return st;
+    auto lru = graph_used.begin();
+    for (auto u = graph_used.begin(); u != graph_used.end(); ++u)
+      if (u->second < lru->second) lru = u;
+    auto g = graphs.find(lru->first);
+    if (g->second.ex) (void)hipGraphExecDestroy(g->second.ex);
+    if (g->second.g) (void)hipGraphDestroy(g->second.g);
+    graphs.erase(g);
+    graph_used.erase(lru);
+  }
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, (sh.v & 1) != 0,
                                   (sh.v & 2) != 0, stream);
@@ -319,6 +353,7 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hip
     return hip_fail(ie, "hipGraphInstantiate");
   }
   graphs[sh] = GraphPair{g, ex};
+  graph_used[sh] = run_count;
   *out = ex;
   return BP_OK;
 }
@@ -585,10 +620,12 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
 }
 
 // Runs one planned launch.  host_in (optional): input arena to stage with the
-// tables; else in_dev is the device input arena.  out_dev: device result
-// array; s: stream to queue on.
+// tables (it holds the residuals too); else in_dev and in2_dev are the device
+// arenas of the sizes and of the residuals.  out_dev: device result array;
+// s: stream to queue on.  The launch is ordered after the previous one of
+// this context, whichever stream that went to.
 bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len,
-                   const int32_t *in_dev, bp_bounds *out_dev, hipStream_t s) {
+                   const int32_t *in_dev, const int32_t *in2_dev, bp_bounds *out_dev, hipStream_t s) {
   bp_status st;
   const size_t off_plan = align256(sizeof(LaunchDesc));
   const size_t off_ent = off_plan + align256(sizeof(InstPlan) * (size_t)count);
@@ -597,22 +634,23 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   const size_t total = off_in + (host_in ? align256(sizeof(int32_t) * (size_t)std::max<int64_t>(host_in_len, 1)) : 0);
   if ((st = stage_host.reserve(total))) return st;
   void *old_dev = stage_buf.p;
-  if ((st = stage_buf.reserve(total))) return st;
+  if ((st = reserve_dev(stage_buf, total))) return st;
   if (stage_buf.p != old_dev) drop_graphs();  // the graphs hold the descriptor's address: capture again
-  if ((st = state_buf.reserve(sizeof(InstState) * count))) return st;
-  if ((st = sorted_buf.reserve(sizeof(int32_t) * ws_items))) return st;
-  if ((st = rec_buf.reserve(sizeof(uint32_t) * ws_items))) return st;
-  if ((st = pre_buf.reserve(sizeof(int64_t) * pre_items))) return st;
-  if ((st = keys_buf.reserve(sizeof(unsigned long long) * kNB * count))) return st;
-  if ((st = ref_buf.reserve(sizeof(int32_t) * count))) return st;
-  if ((st = acc_buf.reserve(sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
-  if ((st = bidx_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bidx_items, 1)))) return st;
-  if ((st = dcnt_buf.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(dcnt_items, 1)))) return st;
+  if ((st = reserve_dev(state_buf, sizeof(InstState) * count))) return st;
+  if ((st = reserve_dev(sorted_buf, sizeof(int32_t) * ws_items))) return st;
+  if ((st = reserve_dev(rec_buf, sizeof(uint32_t) * ws_items))) return st;
+  if ((st = reserve_dev(pre_buf, sizeof(int64_t) * pre_items))) return st;
+  if ((st = reserve_dev(keys_buf, sizeof(unsigned long long) * kNB * count))) return st;
+  if ((st = reserve_dev(ref_buf, sizeof(int32_t) * count))) return st;
+  if ((st = reserve_dev(acc_buf, sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
+  if ((st = reserve_dev(bidx_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(bidx_items, 1)))) return st;
+  if ((st = reserve_dev(dcnt_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(dcnt_items, 1)))) return st;
   char *h = (char *)stage_host.p;
   char *dv = (char *)stage_buf.p;
   LaunchDesc *d = (LaunchDesc *)h;
   memset(d, 0, sizeof *d);
   d->in = host_in ? (const int32_t *)(dv + off_in) : in_dev;
+  d->in2 = host_in ? (const int32_t *)(dv + off_in) : in2_dev;
   d->plan = (const InstPlan *)(dv + off_plan);
   d->entries = (const Entry *)(dv + off_ent);
   d->state = (InstState *)state_buf.p;
@@ -636,6 +674,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   memcpy(h + off_ent, entry_vec.data(), sizeof(Entry) * entry_vec.size());
   if (!div_vec.empty()) memcpy(h + off_div, div_vec.data(), sizeof(int32_t) * div_vec.size());
   if (host_in && host_in_len > 0) memcpy(h + off_in, host_in, sizeof(int32_t) * (size_t)host_in_len);
+  if (any_run) HIP_TRY(hipStreamWaitEvent(s, last_run, 0));
   HIP_TRY(hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(staged, s));
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
@@ -654,6 +693,9 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
     HIP_TRY(launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, with_large,
                             with_combine, s));
   }
+  HIP_TRY(hipEventRecord(last_run, s));
+  any_run = true;
+  ++run_count;
   return BP_OK;
 }
 
@@ -818,7 +860,8 @@ static bp_status reduce_common(bp_ctx *ctx, int32_t C, int32_t m, const int32_t 
   if (C < 1 || m < 0 || n < 0 || !out_items || !out_r) return fail(BP_ERR_ARG, "bad reduction arguments");
   if ((n > 0 && !size) || (m > 0 && !bin_of && !residual) || (bin_of && n > 0 && !bin_of))
     return fail(BP_ERR_ARG, "NULL input array");
-  if (n + (int64_t)m > BP_MAX_ITEMS) return fail(BP_ERR_LIMIT, "n + m = %lld > %d", (long long)(n + m), BP_MAX_ITEMS);
+  if (n + (int64_t)m > BP_MAX_REDUCE_ITEMS)
+    return fail(BP_ERR_LIMIT, "n + m = %lld > %d", (long long)(n + m), BP_MAX_REDUCE_ITEMS);
   // host staging: [size n][bin_of n][residual m]
   const size_t in_bytes = sizeof(int32_t) * (size_t)(2 * n + m) + 64;
   if ((st = c->wait_staging())) return st;
@@ -829,7 +872,7 @@ static bp_status reduce_common(bp_ctx *ctx, int32_t C, int32_t m, const int32_t 
   if (!bin_of && m) memcpy(h + 2 * n, residual, sizeof(int32_t) * m);
   // device: inputs, loads (u64 m), out (n + m), out_residual (m), out_r, bad
   const size_t dev_bytes = in_bytes + sizeof(uint64_t) * (size_t)(m + 1) + sizeof(int32_t) * (size_t)(n + 2 * (int64_t)m) + 256;
-  if ((st = c->red_buf.reserve(dev_bytes))) return st;
+  if ((st = c->reserve_dev(c->red_buf, dev_bytes))) return st;
   char *base = (char *)c->red_buf.p;
   int32_t *d_size = (int32_t *)base;
   int32_t *d_bin = d_size + n;
@@ -898,13 +941,13 @@ bp_status launch_host_batch(Ctx *c, std::vector<PlanIn> &pin, const std::vector<
   if ((st = c->plan(pin, &ntasks))) return st;
   if ((st = c->in_host.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return st;
   if ((st = c->out_host.reserve(sizeof(bp_bounds) * count))) return st;
-  if ((st = c->out_buf.reserve(sizeof(bp_bounds) * count))) return st;
+  if ((st = c->reserve_dev(c->out_buf, sizeof(bp_bounds) * count))) return st;
   int32_t *h = (int32_t *)c->in_host.p;
   for (int64_t i = 0; i < count; ++i) {
     if (pin[i].n_in) memcpy(h + pin[i].in_off, src_a[i], sizeof(int32_t) * (size_t)pin[i].n_in);
     if (pin[i].m_res) memcpy(h + pin[i].res_off, src_b[i], sizeof(int32_t) * (size_t)pin[i].m_res);
   }
-  if ((st = c->run(count, ntasks, h, tot, nullptr, (bp_bounds *)c->out_buf.p, c->stream))) return st;
+  if ((st = c->run(count, ntasks, h, tot, nullptr, nullptr, (bp_bounds *)c->out_buf.p, c->stream))) return st;
   HIP_TRY(hipMemcpyAsync(c->out_host.p, c->out_buf.p, sizeof(bp_bounds) * count, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipEventRecord(c->done, c->stream));
   return BP_OK;
@@ -980,9 +1023,7 @@ bp_status bp_lower_bounds_dev(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *
   if ((st = c->wait_staging())) return st;
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
-  static const int32_t *dummy = nullptr;
-  (void)dummy;
-  return c->run(1, ntasks, nullptr, 0, d_items, d_out, (hipStream_t)stream);
+  return c->run(1, ntasks, nullptr, 0, d_items, d_items, d_out, (hipStream_t)stream);
 }
 
 bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual, const int32_t *unpacked, int64_t n,
@@ -1017,15 +1058,13 @@ bp_status bp_feasible_dev(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *d_re
   if ((st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0],
                          (flags & BP_SEGMENTS) != 0)))
     return st;
-  // both arrays are addressed from the unpacked base: residual offset in elements
-  const ptrdiff_t diff = (m > 0 && n > 0) ? (d_residual - d_unpacked) : 0;
-  const int32_t *base = n > 0 ? d_unpacked : d_residual;
+  // the sizes and the residuals come from two arenas, each at offset 0
   pin[0].in_off = 0;
-  pin[0].res_off = n > 0 ? diff : 0;
+  pin[0].res_off = 0;
   if ((st = c->wait_staging())) return st;
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
-  return c->run(1, ntasks, nullptr, 0, base, d_out, (hipStream_t)stream);
+  return c->run(1, ntasks, nullptr, 0, d_unpacked, d_residual, d_out, (hipStream_t)stream);
 }
 
 static bp_status check_batch(const bp_batch *b) {
@@ -1082,7 +1121,7 @@ bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const in
   if ((st = c->wait_staging())) return st;
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
-  return c->run(batch->count, ntasks, nullptr, 0, d_items, d_out, (hipStream_t)stream);
+  return c->run(batch->count, ntasks, nullptr, 0, d_items, d_items, d_out, (hipStream_t)stream);
 }
 
 bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb) {

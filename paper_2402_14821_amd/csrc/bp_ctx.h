@@ -57,6 +57,13 @@ struct Ctx {
   hipStream_t stream = nullptr;
   hipEvent_t staged = nullptr;  // staging buffers consumed by the device
   hipEvent_t done = nullptr;
+  // End of the last launch queued by run(), on whatever stream it went to.
+  // The next run() makes its stream wait for it before rewriting the
+  // descriptor, the tables and the workspaces the launch still reads, and
+  // the host waits for it before a workspace is reallocated or a captured
+  // graph destroyed.
+  hipEvent_t last_run = nullptr;
+  bool any_run = false;
   bool use_graph = true;
   int seg_kcut = -1;  // BJ1 segment tiles for K <= seg_kcut; -1: chosen by the cost model
   bool timing = false;
@@ -83,6 +90,8 @@ struct Ctx {
     hipGraphExec_t ex = nullptr;
   };
   std::map<LaunchShape, GraphPair> graphs;  // captured pipelines by shape
+  std::map<LaunchShape, uint64_t> graph_used;  // last use (run counter) of each cached graph
+  uint64_t run_count = 0;
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
   void drop_graphs();
@@ -108,7 +117,9 @@ struct Ctx {
   bp_status ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hipGraphExec_t *ex);
   bp_status plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out);
   bp_status run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len, const int32_t *in_dev,
-                bp_bounds *out_dev, hipStream_t s);
+                const int32_t *in2_dev, bp_bounds *out_dev, hipStream_t s);
+  bp_status wait_last_run();
+  bp_status reserve_dev(DevBuf &b, size_t bytes);
   bp_status wait_staging();
   void apply_tuning();
   void timing_reset();

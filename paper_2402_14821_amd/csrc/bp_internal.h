@@ -30,6 +30,7 @@ constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
+static_assert(kLargeCap == BP_MAX_ITEMS, "the check's item limit is the large prep block's capacity");
 
 // Input form of an instance.
 enum : int32_t { kFormItems = 0, kFormResidual = 1 };
@@ -37,7 +38,7 @@ enum : int32_t { kFormItems = 0, kFormResidual = 1 };
 // Per-instance plan, written by the host, read-only on the device.
 struct InstPlan {
   int64_t in_off;    // items form: offset of items[]; residual form: offset of unpacked[]
-  int64_t res_off;   // residual form: offset of residual[] (int32) in the same input arena
+  int64_t res_off;   // residual form: offset of residual[] (int32) in the residual arena (LaunchDesc::in2)
   int64_t n_in;      // items form: r; residual form: number of unpacked items
   int64_t k;         // bins
   int64_t ws_off;    // offset of this instance's slice of the per-item workspaces
@@ -107,7 +108,8 @@ struct Entry {
 
 struct LaunchDesc {
   // inputs
-  const int32_t *in;        // input arena (items or unpacked + residuals)
+  const int32_t *in;        // input arena: items, or the unpacked sizes of residual-form instances
+  const int32_t *in2;       // residual arena: the residual capacities of residual-form instances
   const InstPlan *plan;
   const Entry *entries;
   // workspaces

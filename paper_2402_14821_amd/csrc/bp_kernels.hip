@@ -351,7 +351,7 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
     if (p.form == kFormResidual) {
       // one virtual item of size c - residual per bin with residual < c
       // (Fig. 3), appended in bin order: a stable compaction of the loaded bins
-      const BP_GLOBAL int32_t *res = as_global(d.in + p.res_off);
+      const BP_GLOBAL int32_t *res = as_global(d.in2 + p.res_off);
       const int m = p.m_res;
       int32_t rv[K];
       uint32_t pos[K];

@@ -29,3 +29,7 @@ def hand_bounds():
 
 def param_counts():
     return [tuple(int(x) for x in p) for p in lines("param_counts.txt")]
+
+
+def vb2_clamp():
+    return [tuple(int(x) for x in p) for p in lines("vb2_clamp.txt")]

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle_par
 import paper_2402_14821_amd as bp
 from paper_2402_14821_amd import workloads as W
 
@@ -84,6 +85,58 @@ def test_early_exit_verdicts_in_mix(ctx):
             assert r.lb == full["lb"]
         else:
             assert r.lb > len(reqs[i].residual)
+
+
+def _tight_twin(r):
+    """The same node with empty bins dropped until ceil(total / C) - 1 bins
+    remain (or only the loaded ones): a node the check must refute."""
+    total = int(np.sum(r.unpacked, dtype=np.int64)) + int(np.sum(r.C - r.residual.astype(np.int64)))
+    want_m = max(int((r.residual < r.C).sum()), -(-total // r.C) - 1)
+    keep = list(np.flatnonzero(r.residual < r.C))
+    empty = list(np.flatnonzero(r.residual == r.C))
+    keep += empty[: max(0, want_m - len(keep))]
+    return W.Request(r.t, r.C, r.residual[sorted(keep)].copy(), r.unpacked.copy(), r.node)
+
+
+def test_served_requests_match_oracle(ctx):
+    # 48 requests of the simulated search, 24 from each arrival-rate stream,
+    # and their tightened twins, served in one mix twice over: exhaustive
+    # (every field against the oracle) and with early exit (verdict against
+    # the oracle; a passing request's whole record, a failing one's lb above
+    # its bin count)
+    picks = []
+    for seed, rate in ((3, 20_000.0), (4, 200_000.0)):
+        reqs = W.dfs_requests(seed, rate=rate, duration=1.0, max_requests=600)
+        idx = np.linspace(0, len(reqs) - 1, 24).astype(int)
+        picks += [reqs[i] for i in idx]
+    picks += [_tight_twin(r) for r in picks]
+    items = [O.residual_reduce(r.C, r.residual, r.unpacked) for r in picks]
+    want = O.bounds_many([(r.C, len(r.residual), it) for r, it in zip(picks, items)],
+                         threads=oracle_par.pool_threads(), l2_dense=True)
+    say("served mix vs oracle,", len(picks), "requests x 2")
+    q = bp.Queue(ctx, 8 << 30, 4096)
+    tickets = {}
+    for i, r in enumerate(picks):
+        tickets[q.submit(r.C, r.residual, r.unpacked, tag=2 * i, flags=bp.BP_NO_EARLY_EXIT)] = (i, False)
+        tickets[q.submit(r.C, r.residual, r.unpacked, tag=2 * i + 1)] = (i, True)
+    res = drain(q, len(tickets))
+    q.close()
+    refuted_early = 0
+    for t, got in res.items():
+        i, early = tickets[t]
+        w, m = want[i], len(picks[i].residual)
+        assert got.status == 0 and got.bounds.r == len(items[i])
+        assert got.verdict == w["verdict"], (i, early)
+        if not early or w["verdict"] == 1:
+            assert list(got.bounds.value) == w["value"].tolist(), (i, early)
+            assert list(got.bounds.argmax_lambda) == w["argmax"].tolist(), (i, early)
+            assert (got.lb, got.bounds.lb_arg) == (w["lb"], w["lb_arg"]), (i, early)
+        else:
+            assert got.lb > m, (i, got.lb, m)
+            refuted_early += got.bounds.early_exit
+    verdicts = [w["verdict"] for w in want]
+    assert 0 < sum(verdicts) < len(verdicts)  # both kinds of nodes
+    assert refuted_early == len(verdicts) - sum(verdicts)
 
 
 def test_admission_limits(ctx):

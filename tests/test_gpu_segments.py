@@ -4,7 +4,8 @@ The segment form computes the MT, RAD2, CCM1 and BJ1 sums from threshold
 sums over the sorted sizes instead of one evaluation per (item, parameter),
 and half of the VB2 sums from the other half (mirror); the bounds are the
 same integers.  Every record is compared with the CPU oracle (the dense
-definition) field by field, and at full size with the dense GPU path.
+definition) field by field; at full size both with the oracle's dense record
+and per parameter, and with the dense GPU path.
 BP_SEGMENT_KCUT forces segment tiles of BJ1 wherever floor(c / lambda) <= K,
 so that many windows per tile are exercised on small instances too.
 """
@@ -17,6 +18,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle_par
 import paper_2402_14821_amd as bp
 from paper_2402_14821_amd import workloads as W
 
@@ -191,20 +193,44 @@ def test_partial_packings_flag(ctx):
         assert early["verdict"] == want["verdict"]
 
 
-def test_large_residual_instance_equals_dense(ctx, ctx64):
-    # full size: every field of the segment record equals the dense record,
-    # and the dense record is pinned to the oracle by the dense parity tests
-    C, m, res, unp = W.large_residual(1)
-    say("segments config-2 full size")
+def test_large_residual_instance_full(ctx, ctx64):
+    # full size: every field of the segment record against the oracle's dense
+    # record, and equal to the dense GPU record
+    C, m, res, unp, items, want = oracle_par.large_residual_record(1)
+    say("segments config-2 full size, dense oracle record")
     dense = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
     for c, name in ((ctx, "model"), (ctx64, "kcut64")):
         seg = c.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT | bp.BP_SEGMENTS)
+        same(seg, want, name)
         same(seg, dense, name)
-        assert seg["evals"] == dense["evals"] and seg["r"] == dense["r"]
-    items = O.residual_reduce(C, res, unp)
-    assert (dense["value"][O.MT], dense["argmax"][O.MT]) == O.piecewise_bound(O.MT, C, items)
-    a = int(dense["argmax"][O.BJ1])
-    assert O.dff_bound(O.BJ1, C, items, a, a)[0] == dense["value"][O.BJ1]
+        assert seg["evals"] == dense["evals"] and seg["r"] == dense["r"] == len(items)
+
+
+def test_large_residual_per_parameter_values(ctx, ctx64):
+    # copies of the large instance in one batch, each with single-parameter or
+    # short-window ranges and the segment flag: per-parameter values
+    C, m, res, unp, items, _ = oracle_par.large_residual_record(1)
+    rng = random.Random(78)
+    dlo, dhi = zip(*(O.default_range(b, C) for b in range(O.NB)))
+    sweeps = []
+    for t in range(256):
+        lo, hi = [1] * O.NB, [0] * O.NB
+        for b in range(O.L2, O.NB):
+            if t < 192:
+                lam = rng.randint(dlo[b], dhi[b])
+                lo[b], hi[b] = lam, lam
+            else:
+                a = rng.randint(dlo[b], dhi[b])
+                lo[b], hi[b] = a, min(dhi[b], a + rng.choice([5, 64, 127, 128, 129, 700]) - 1)
+        sweeps.append((lo, hi))
+    want = O.bounds_many([(C, m, items, lo, hi) for lo, hi in sweeps], threads=oracle_par.pool_threads(),
+                         l2_dense=True)
+    for c, name in ((ctx, "model"), (ctx64, "kcut64")):
+        say("segments config-2 per-parameter values", name)
+        out = c.lower_bounds_batch([C] * len(sweeps), [m] * len(sweeps), [items] * len(sweeps),
+                                   [bp.make_sweep(lo, hi, bp.BP_SWEEP_SEGMENTS) for lo, hi in sweeps])
+        for i in range(len(sweeps)):
+            same(bp.bounds_to_dict(out[i]), want[i], (name, i, sweeps[i]))
 
 
 def test_uneven_batch_equals_dense(ctx):

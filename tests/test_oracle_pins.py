@@ -13,7 +13,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from golden_io import dff_values, fig3, hand_bounds, param_counts
+from golden_io import dff_values, fig3, hand_bounds, param_counts, vb2_clamp
+import oracle_par
 
 NAME2ID = {n: i for i, n in enumerate(O.NAMES)}
 
@@ -307,3 +308,54 @@ def test_large_capacity_products_stay_exact():
         num = w * (lam + 1)
         want = w * lam if num % C == 0 else (num // C) * C
         assert O.f(O.FS1, C, w, lam) == want
+
+
+# --- the paper's VB2 cut (Sec. 4, "Implementation details") -------------------
+
+
+@pytest.mark.parametrize("row", vb2_clamp(), ids=lambda r: f"c{r[0]}-r{r[1]}-w{r[2]}")
+def test_vb2_clamp_hand_values(row):
+    C, r, maxw, want_hi = row
+    assert O.default_range(O.VB2, C, r, maxw, clamp_vb2=True) == (2, want_hi)
+    assert O.default_range(O.VB2, C, r, maxw, clamp_vb2=False) == (2, C)
+    # the cut touches only VB2
+    for b in range(O.NB):
+        if b != O.VB2:
+            assert O.default_range(b, C, r, maxw, clamp_vb2=True) == O.default_range(b, C)
+
+
+def test_vb2_clamp_keeps_32_bit_products():
+    # Where the cut binds, hi is the largest parameter with r * max w * hi <= 2^32 - 1
+    # (the paper's reason for it), checked by that inequality on both sides.
+    rng = random.Random(23)
+    for _ in range(2000):
+        C = rng.randint(1, 2**31 - 1)
+        r = rng.randint(0, 20000)
+        maxw = rng.randint(0, C)
+        lo, hi = O.default_range(O.VB2, C, r, maxw, clamp_vb2=True)
+        assert lo == 2 and hi <= C
+        d = r * maxw
+        if d == 0:
+            assert hi == C  # no items: nothing to cut
+        elif hi == C:
+            assert d * C <= 2**32 - 1  # the cut lies past c
+        else:
+            assert d * hi <= 2**32 - 1 < d * (hi + 1)
+
+
+# --- the thread-pool helper used for full-size records --------------------------
+
+
+def test_pooled_record_equals_single_pass():
+    # cutting every range into chunks (down to one parameter) keeps the maximum
+    # and the smallest maximiser of one pass over the range
+    rng = random.Random(29)
+    for t in range(60):
+        C, items = _rand_instance(rng, cmax=400, nmax=25)
+        k = rng.randint(0, len(items) + 1)
+        want = O.bounds(C, k, items, l2_dense=True)
+        for chunk in (1, 3, 17, None):
+            got = oracle_par.dense_record(C, k, items, threads=4, chunk=chunk)
+            for f in ("value", "argmax"):
+                assert np.array_equal(got[f], want[f]), (t, chunk, f, got[f], want[f])
+            assert (got["lb"], got["lb_arg"], got["verdict"]) == (want["lb"], want["lb_arg"], want["verdict"])
