@@ -243,6 +243,25 @@ bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, 
 bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, int32_t reps,
                             bp_tuning *best, double *best_ms);
 
+/* Allocation-free variant of bp_feasible_dev, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same check and record as
+ * bp_feasible_dev, without a context, on the calling thread's current HIP
+ * device; d_residual[m], d_unpacked[n] and d_out are device pointers owned
+ * by the caller, and the work is queued on stream.  The launch tables and
+ * every workspace live in one static device array of
+ * BP_NOALLOC_SCRATCH_BYTES per GPU, held by the process until it ends and
+ * shared by every call on that GPU, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other host threads) race
+ * and must be serialised by the caller.  The kernels clear what has to start
+ * at zero.  No hipMalloc, hipFree, pinned-host allocation, memory copy or
+ * graph is used.  flags: BP_NO_EARLY_EXIT only (the sweeps run dense;
+ * BP_SEGMENTS is BP_ERR_ARG).  n + m > BP_NOALLOC_MAX_ITEMS: BP_ERR_LIMIT. */
+#define BP_NOALLOC_MAX_ITEMS (1 << 14)
+#define BP_NOALLOC_SCRATCH_BYTES (32u << 20)
+bp_status bp_feasible_dev_noalloc(int32_t C, int32_t m, const int32_t *d_residual, const int32_t *d_unpacked,
+                                  int64_t n, uint32_t flags, bp_bounds *d_out, void *stream);
+
 /* ---- served checks (continuous batching) -------------------------------- */
 
 /* One request: a partial packing in residual form, as bp_feasible takes it. */

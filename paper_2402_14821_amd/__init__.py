@@ -30,6 +30,8 @@ BP_NO_EARLY_EXIT = 1
 BP_SEGMENTS = 2
 BP_MAX_ITEMS = 1 << 14
 BP_MAX_REDUCE_ITEMS = 1 << 30
+BP_NOALLOC_MAX_ITEMS = 1 << 14
+BP_NOALLOC_SCRATCH_BYTES = 32 << 20
 BP_MAX_BATCH = 1 << 20
 
 _i32, _i64, _u32, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
@@ -100,6 +102,7 @@ _SIGNATURES = {
     "bp_lower_bounds_dev": ([_VP, _i32, _i32, _VP, _i64, ctypes.POINTER(bp_sweep), _VP, _VP], _i32),
     "bp_feasible": ([_VP, _i32, _i32, _P32, _P32, _i64, _u32, _P32, _P64, ctypes.POINTER(bp_bounds)], _i32),
     "bp_feasible_dev": ([_VP, _i32, _i32, _VP, _VP, _i64, _u32, _VP, _VP], _i32),
+    "bp_feasible_dev_noalloc": ([_i32, _i32, _VP, _VP, _i64, _u32, _VP, _VP], _i32),
     "bp_ctx_set_timing": ([_VP, _i32], _i32),
     "bp_ctx_get_tuning": ([_VP, ctypes.POINTER(bp_tuning)], _i32),
     "bp_ctx_set_tuning": ([_VP, ctypes.POINTER(bp_tuning)], _i32),
@@ -197,6 +200,13 @@ def make_sweep(lo, hi, flags: int = 0) -> bp_sweep:
         sw.hi[b] = int(hi[b])
     sw.flags = flags
     return sw
+
+
+def feasible_dev_noalloc(C: int, m: int, d_residual_ptr: int, n: int, d_unpacked_ptr: int, d_out_ptr: int,
+                         stream_ptr: int, flags: int = 0):
+    """bp_feasible_dev_noalloc on the current HIP device (no context)."""
+    _check(load().bp_feasible_dev_noalloc(C, m, _VP(d_residual_ptr), _VP(d_unpacked_ptr), n, flags,
+                                          _VP(d_out_ptr), _VP(stream_ptr)))
 
 
 def selftest_division(d_lo: int, d_hi: int, n_hi: int, mode: int) -> int:

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -1065,6 +1066,87 @@ bp_status bp_feasible_dev(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *d_re
   int64_t ntasks = 0;
   if ((st = c->plan(pin, &ntasks))) return st;
   return c->run(1, ntasks, nullptr, 0, d_unpacked, d_residual, d_out, (hipStream_t)stream);
+}
+
+// ---- allocation-free check -------------------------------------------------
+
+bp_status bp_feasible_dev_noalloc(int32_t C, int32_t m, const int32_t *d_residual, const int32_t *d_unpacked,
+                                  int64_t n, uint32_t flags, bp_bounds *d_out, void *stream) {
+  if (!d_out || (m > 0 && !d_residual) || (n > 0 && !d_unpacked)) return fail(BP_ERR_ARG, "NULL argument");
+  if (flags & ~BP_NO_EARLY_EXIT)
+    return fail(BP_ERR_ARG, "flags 0x%x: the allocation-free check takes BP_NO_EARLY_EXIT only", flags);
+  if (n < 0 || m < 0) return fail(BP_ERR_ARG, "negative count");
+  if (n + (int64_t)m > BP_NOALLOC_MAX_ITEMS)
+    return fail(BP_ERR_LIMIT, "n + m = %lld exceeds BP_NOALLOC_MAX_ITEMS = %d", (long long)(n + m),
+                BP_NOALLOC_MAX_ITEMS);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned char *base = nullptr;
+  HIP_TRY(noalloc_scratch(dev, &base));
+  // Host-side planning tables only (no device memory): a planner per host
+  // thread, set up for the device's compute-unit count and the default shape.
+  thread_local Ctx planner;
+  thread_local int planner_dev = -1;
+  if (planner_dev != dev) {
+    int cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    planner.num_cu = cu;
+    planner.grid_prep_small = cu * 2;
+    planner.grid_prep_large = std::max(1, cu / 4);
+    planner.grid_comb = cu * 2;
+    planner.grid_fin = 64;
+    planner_dev = dev;
+  }
+  planner.tune = bp_tuning{2, 32, 32, 2048};
+  planner.apply_tuning();
+  std::vector<PlanIn> pin(1);
+  bp_status st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0], false);
+  if (st) return st;
+  pin[0].in_off = 0;
+  pin[0].res_off = 0;
+  int64_t ntasks = 0;
+  if ((st = planner.plan(pin, &ntasks))) return st;
+  if (planner.acc_len > kNaAccSlots) {
+    // more partial-sum slots than the array holds: tiles split only where a
+    // bound has fewer than four tiles
+    planner.tune.min_chunk = 65536;
+    if ((st = planner.plan(pin, &ntasks))) return st;
+    if (planner.acc_len > kNaAccSlots)
+      return fail(BP_ERR_LIMIT, "%lld partial-sum slots exceed the %lld of the static workspace",
+                  (long long)planner.acc_len, (long long)kNaAccSlots);
+  }
+  if (planner.nentries > kNoAllocMaxEntries)
+    return fail(BP_ERR_LIMIT, "%lld schedule entries > %d", (long long)planner.nentries, kNoAllocMaxEntries);
+  NoAllocTables t;
+  memset(&t, 0, sizeof t);
+  LaunchDesc &d = t.d;
+  d.in = d_unpacked;
+  d.in2 = d_residual;
+  d.plan = (const InstPlan *)(base + offsetof(NoAllocTables, p));
+  d.entries = (const Entry *)(base + offsetof(NoAllocTables, e));
+  d.state = (InstState *)(base + kNaState);
+  d.sorted = (int32_t *)(base + kNaSorted);
+  d.pre = (int64_t *)(base + kNaPre);
+  d.av = (uint32_t *)(base + kNaAv);
+  d.keys = (unsigned long long *)(base + kNaKeys);
+  d.refuted = (int32_t *)(base + kNaRefuted);
+  d.counter = (unsigned long long *)(base + kNaCounter);
+  d.acc = (long long *)(base + kNaAcc);
+  d.bidx = (int32_t *)(base + kNaCounter);  // no segment tables in this variant: never read
+  d.divs = (const int32_t *)(base + kNaCounter);
+  d.dcnt = (int32_t *)(base + kNaCounter);
+  d.out = d_out;
+  d.count = 1;
+  d.nentries = planner.nentries;
+  d.ntasks = ntasks;
+  d.acc_len = planner.acc_len;
+  d.nsplit = planner.nsplit;
+  t.p = planner.plan_vec[0];
+  for (int64_t j = 0; j < planner.nentries; ++j) t.e[j] = planner.entry_vec[(size_t)j];
+  const Ctx::LaunchShape sh = planner.shape_of(1, ntasks);
+  HIP_TRY(launch_noalloc(t, base, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, (sh.v & 1) != 0,
+                         (sh.v & 2) != 0, (hipStream_t)stream));
+  return BP_OK;
 }
 
 static bp_status check_batch(const bp_batch *b) {

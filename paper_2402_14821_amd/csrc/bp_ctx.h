@@ -24,6 +24,10 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_smal
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
                                  int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
                                  hipStream_t s, hipEvent_t ev[4]);
+hipError_t noalloc_scratch(int device, unsigned char **out);
+hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
+                          int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
+                          bool with_combine, hipStream_t s);
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
                          int64_t n, unsigned long long *loads, int32_t *out, int64_t *out_r, int32_t *out_residual,
                          int32_t *bad, hipStream_t s);

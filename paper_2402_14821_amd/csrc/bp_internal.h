@@ -132,4 +132,29 @@ struct LaunchDesc {
   int64_t nsplit;           // combine segments (kSegTiles split tiles each) over all entries
 };
 
+// Allocation-free check (bp_feasible_dev_noalloc): the tables and every
+// workspace of a one-instance launch inside one file-scope device array per
+// GPU, at the fixed offsets below.  The rest of the array holds the partial
+// sums of split tiles.
+constexpr size_t kNoAllocScratchBytes = size_t(BP_NOALLOC_SCRATCH_BYTES);
+constexpr int kNoAllocMaxEntries = 8;  // one instance, dense sweeps: L2 + six functions
+constexpr int kNoAllocMaxDevices = 64;
+struct NoAllocTables {
+  LaunchDesc d;
+  InstPlan p;
+  Entry e[kNoAllocMaxEntries];
+};
+constexpr size_t na_align(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kNaState = na_align(sizeof(NoAllocTables));
+constexpr size_t kNaKeys = kNaState + na_align(sizeof(InstState));
+constexpr size_t kNaRefuted = kNaKeys + na_align(sizeof(unsigned long long) * kNB);
+constexpr size_t kNaCounter = kNaRefuted + na_align(sizeof(int32_t));
+constexpr size_t kNaSorted = kNaCounter + na_align(sizeof(unsigned long long) * kQueues * kQueueStride);
+constexpr size_t kNaAv = kNaSorted + na_align(sizeof(int32_t) * size_t(BP_NOALLOC_MAX_ITEMS));
+constexpr size_t kNaPre = kNaAv + na_align(sizeof(uint32_t) * size_t(BP_NOALLOC_MAX_ITEMS));
+constexpr size_t kNaAcc = kNaPre + na_align(sizeof(int64_t) * (size_t(BP_NOALLOC_MAX_ITEMS) + 1));
+constexpr int64_t kNaAccSlots = int64_t((kNoAllocScratchBytes - kNaAcc) / sizeof(long long));
+static_assert(kNaAcc < kNoAllocScratchBytes / 2, "the partial-sum slots keep most of the array");
+static_assert(BP_NOALLOC_MAX_ITEMS <= kLargeCap, "the prep kernels bound the item count");
+
 }  // namespace bpi

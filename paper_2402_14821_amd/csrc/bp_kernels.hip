@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "bp_divide.h"
 #include "bp_internal.h"
 
@@ -1661,6 +1663,51 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_pre
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipEventRecord(ev[3], s);
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free check.  Its tables and workspaces are this file-scope
+// array; each GPU holds its own copy, whose address hipGetSymbolAddress
+// gives with that GPU current.  Host code uses that address, never the
+// array's name (a host-side stand-in).
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Set-up, once per device: the address of that device's array (the caller
+// has made `device` current).
+hipError_t noalloc_scratch(int device, unsigned char **out) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (unsigned char *)p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// Writes the launch tables (passed by value, so no copy from host memory is
+// needed) to the start of the array.
+__global__ __launch_bounds__(64) void k_noalloc_tables(NoAllocTables t, NoAllocTables *dst) {
+  if (threadIdx.x == 0) *dst = t;
+}
+
+// The tables' kernel, then the pipeline reading its descriptor from `base`
+// (the array's device address).
+hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
+                          int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
+                          bool with_combine, hipStream_t s) {
+  hipLaunchKernelGGL(k_noalloc_tables, dim3(1), dim3(64), 0, s, t, (NoAllocTables *)base);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_pipeline((const LaunchDesc *)base, lpl, grid_prep_small, grid_prep_large, grid_sweep, grid_comb,
+                         grid_fin, with_large, with_combine, s);
 }
 
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
