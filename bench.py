@@ -28,8 +28,20 @@ sys.path.insert(0, ROOT)
 
 # Full-rate VALU issue slots per (item, parameter) evaluation of each sweep,
 # counted in the inner loops of the sweep kernel as built for gfx950 with 2
-# parameters per lane, the default shape (32-bit add, sub, logic and shifts issue at twice the
-# full rate and count 1/2; mul_hi, mad_u64_u32, add3, sad and fp64 count 1).
+# parameters per lane, the default shape.  Weights from the measured issue
+# rates (profiles/valu_rates_gfx950.txt, `bench.py --valu-rates`): 32-bit
+# add, sub, and, xor and shifts issue at 1.69-1.88x the full rate and count
+# 1/2; v_mul_hi_u32, v_mad_u64_u32, v_add3_u32, v_sad_u32, compares, selects
+# and fp64 issue at 0.90-0.98x and count 1.  Per evaluation:
+#   MT   v_sub_u32, v_ashrrev_i32, v_and_b32 (1/2 each), 1/2 v_add3_u32      = 2.0
+#   RAD2 two families of v_sub_u32 + v_lshrrev_b32 (1/2 each), 1/2 v_add3_u32 x 2 = 3.0
+#   FS1  2 v_fma_f64, 2 v_mul_f64, 2 v_add_f64, 2 v_cndmask_b32, v_floor_f64,
+#        v_cmp_eq_f64, 1/2 conversion                                        = 10.25
+#   CCM1 v_mul_hi_u32, v_lshrrev_b32 (1/2), 1/2 v_add3_u32                  = 2.0
+#   VB2  v_mul_hi_u32, v_mad_u64_u32, 1/2 v_add3_u32                        = 2.5
+#   BJ1  v_mul_hi_u32, v_lshrrev_b32 (1/2), v_mad_u64_u32, v_sad_u32,
+#        1/2 v_add3_u32                                                      = 4.0
+# (v_add3_u32 adds two items' increments at once, hence 1/2 per evaluation.)
 OPS_PER_EVAL = {"MT": 2.0, "RAD2": 3.0, "FS1": 10.25, "CCM1": 2.0, "VB2": 2.5, "BJ1": 4.0}
 PEAK_VALU = 256 * 64 * 2.4e9  # full-rate lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 DFF_NAMES = ("MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1")
@@ -118,6 +130,37 @@ def host_cpu():
     return {"nproc": os.cpu_count() or 1, "affinity": aff, "model": model}
 
 
+def valu_rates(blocks_per_cu: int = 8, iters: int = 4000, reps: int = 3):
+    """Issue rate of each opcode of the sweep's inner loops, measured by the
+    microbenchmark library (hand-written gfx950 kernels, one opcode each on
+    eight independent chains per lane), as lane-operations/s and as a
+    fraction of the full rate PEAK_VALU."""
+    import ctypes
+
+    import paper_2402_14821_amd as bp
+
+    bp._preload_torch_hip_runtime()
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2402_14821_amd", "libbp_ubench.so"))
+    lib.bpu_num_ops.restype = ctypes.c_int
+    lib.bpu_op_name.restype = ctypes.c_char_p
+    lib.bpu_op_name.argtypes = [ctypes.c_int]
+    lib.bpu_valu_rate.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)] * 3
+    lib.bpu_valu_rate.restype = ctypes.c_int
+    rows = []
+    for op in range(lib.bpu_num_ops()):
+        rate, ms, per_lane = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        st = lib.bpu_valu_rate(0, op, blocks_per_cu, iters, reps, ctypes.byref(rate), ctypes.byref(ms),
+                               ctypes.byref(per_lane))
+        name = lib.bpu_op_name(op).decode()
+        if st != 0:
+            raise RuntimeError(f"microbenchmark of {name} failed with HIP error {st}")
+        rows.append({"op": name, "lane_ops_per_s": rate.value, "frac_of_full_rate": rate.value / PEAK_VALU,
+                     "ms": ms.value})
+        log(f"valu rate {name}: {rate.value / PEAK_VALU:.3f} of the full rate")
+    return {"full_rate_lane_ops_per_s": PEAK_VALU, "blocks_per_cu": blocks_per_cu, "waves_per_cu": 4 * blocks_per_cu,
+            "insts_per_lane": iters * 128, "reps": reps, "rates": rows}
+
+
 def sweep_ops(bp, C, r):
     """Algorithmic VALU slots of the six sweeps of one instance (exact ranges,
     as the library's own bp_default_sweep states them)."""
@@ -129,26 +172,48 @@ def sweep_ops(bp, C, r):
     return ops
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch of a kernel, from the counter summary in profiles/,
-    or None when the kernel source changed since the counters were taken."""
+def kernel_source_sha256() -> str:
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    src = os.path.join(ROOT, "paper_2402_14821_amd", "csrc", "bp_kernels.hip")
+    with open(src, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def load_profile(name: str):
+    """key: value pairs of a counter summary in profiles/, or None when it is
+    missing or the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and not line.startswith("#"):
+            if line.startswith("#") and "sha256" in line and ":" in line:
+                vals["kernel_source_sha256"] = line.rsplit(":", 1)[1].strip()
+            elif ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2402_14821_amd", "csrc", "bp_kernels.hip")
-    with open(src, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    if vals.get("kernel_source_sha256") != digest or "hbm_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    return vals
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch of a kernel, from the counter summary in profiles/,
+    or None when the kernel source changed since the counters were taken."""
+    vals = load_profile(f"{kernel}_traffic.txt")
+    if not vals or "hbm_bytes_per_launch" not in vals:
         return None
     return float(vals["hbm_bytes_per_launch"])
+
+
+def load_valu_insts(kernel: str):
+    """Wave-level VALU instructions per launch (SQ_INSTS_VALU), or None."""
+    vals = load_profile(f"{kernel}_large_residual_sq_counters.txt")
+    if not vals or "SQ_INSTS_VALU" not in vals:
+        return None
+    return float(vals["SQ_INSTS_VALU"])
 
 
 def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, plain_max: int = 4096,
@@ -358,6 +423,8 @@ def main():
     ap.add_argument("--no-segments", action="store_true",
                     help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
     ap.add_argument("--served-seconds", type=float, default=0.25)
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only measure the VALU issue rate of each inner-loop opcode and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (scale for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -368,6 +435,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.valu_rates:
+        print(json.dumps(valu_rates()), flush=True)
+        return
 
     if args.calibrate_copy:
         n = args.calibrate_copy << 20
@@ -471,6 +542,7 @@ def main():
     ops = sweep_ops(bp, C, r)
     achieved = ops / (sweep_avg * 1e-3)
     traffic = load_traffic("k_sweep")
+    valu_insts = load_valu_insts("k_sweep")
 
     # plain single-check latency on the small partial packing (host in, host
     # out): one bp_feasible call through ctypes with its arguments marshalled
@@ -516,7 +588,11 @@ def main():
         "stages_ms": {"prep": prep_avg, "sweep": sweep_avg, "finalize": fin_avg, "runs": runs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic, "kernel": "k_sweep",
-                     "ops_per_eval": OPS_PER_EVAL, "tuning": ctx.get_tuning()},
+                     "ops_per_eval": OPS_PER_EVAL, "weights": "profiles/valu_rates_gfx950.txt",
+                     "slots_per_launch": ops,
+                     # every VALU instruction the kernel issued (SQ_INSTS_VALU x 64 lanes) as one full slot
+                     "frac_issue": (valu_insts * 64 / (sweep_avg * 1e-3) / PEAK_VALU) if valu_insts else None,
+                     "tuning": ctx.get_tuning()},
         "plain_small_check_us": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "n": len(lat),
                                  "workload": "n=50 sizes U[20,100], m=20, C=150, 30% pre-packed; host in/out"},
         "verdict": rec["verdict"], "lb": rec["lb"],

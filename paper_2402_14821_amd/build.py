@@ -18,6 +18,9 @@ LIB = os.path.join(HERE, "libbp.so")
 ARCH = os.environ.get("BP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_queue.cpp"]
+# VALU issue-rate microbenchmark (bench.py --valu-rates), a library of its own
+UBENCH_SOURCES = ["bp_ubench.hip"]
+UBENCH_LIB = os.path.join(HERE, "libbp_ubench.so")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"--offload-arch={ARCH}", "-I", os.path.join(HERE, "..", "include")]
@@ -39,20 +42,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libbp.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source, link libbp.so and the microbenchmark library
+    libbp_ubench.so; returns the path of libbp.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [s for s in SOURCES + UBENCH_SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    _link([objs[s] for s in SOURCES], LIB)
+    _link([objs[s] for s in UBENCH_SOURCES], UBENCH_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {UBENCH_LIB}")
     return LIB
 
 
