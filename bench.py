@@ -344,25 +344,42 @@ def per_bound_table(bp, W, ctx, reps: int = 5):
             "reps": reps, "rows": rows}
 
 
-def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30, flags: int = 0):
-    """Open-loop Poisson arrivals of DFS requests into a bp_queue; latency from the library's clock."""
+def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30, flags: int = 0,
+                 max_slots: int = 8192):
+    """Open-loop Poisson arrivals of the simulated search's requests into a
+    bp_queue.  Roots go in as partial packings (checked exhaustively: the
+    search expands them), children as (parent ticket, commits) without their
+    instances; a request whose parent was rejected is dropped with its
+    subtree.  Latency from the library's clock; evaluations as performed."""
     import ctypes
     import threading
 
     import numpy as np
 
-    reqs = W.dfs_requests(seed, rate=rate, duration=duration)
+    t_gen = time.perf_counter()
+    reqs = W.dfs_requests(seed, rate=rate, duration=duration, instances="roots")
+    t_gen = time.perf_counter() - t_gen
     lib = bp.load()
+    m_of = {}
     structs, keep = [], []
     for i, r in enumerate(reqs):
-        res = np.ascontiguousarray(r.residual, dtype=np.int32)
-        unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
-        keep.append((res, unp))
-        structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
-                                     unp.ctypes.data_as(bp._P32), i, flags, 0))
-    q = bp.Queue(ctx, budget, 1 << 20)
+        if r.parent < 0:
+            res = np.ascontiguousarray(r.residual, dtype=np.int32)
+            unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
+            keep.append((res, unp))
+            m_of[i] = len(res)
+            structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
+                                         unp.ctypes.data_as(bp._P32), i, flags | bp.BP_NO_EARLY_EXIT, 0, 0, None,
+                                         0, 0))
+        else:
+            m_of[i] = m_of[r.parent]
+            cm = (bp.bp_commit * max(1, len(r.commits)))(*[bp.bp_commit(w, b) for w, b in r.commits])
+            keep.append(cm)
+            structs.append(bp.bp_request(r.C, m_of[i], 0, None, None, i, flags, 0, 0, cm, len(r.commits), 0))
+    q = bp.Queue(ctx, budget, max_slots)
     results = []
     done = threading.Event()
+    submitted = [0]
 
     def poller():
         arr = (bp.bp_result * 4096)()
@@ -370,17 +387,26 @@ def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: in
         while True:
             lib.bp_queue_poll(q.handle, ctypes.cast(arr, ctypes.c_void_p), 4096, ctypes.byref(got), 2000)
             for j in range(got.value):
-                results.append((arr[j].tag, arr[j].submit_us, arr[j].done_us, arr[j].status, arr[j].bounds.evals))
-            if done.is_set() and len(results) + rejected[0] >= len(structs):
+                a = arr[j]
+                results.append((a.tag, a.submit_us, a.done_us, a.status, a.bounds.evals, a.bounds.evals_done,
+                                a.from_parent, a.verdict))
+            if done.is_set() and len(results) >= submitted[0]:
                 return
 
-    rejected = [0]
     th = threading.Thread(target=poller, daemon=True)
     th.start()
     ticket = ctypes.c_uint64(0)
+    tickets = np.zeros(len(reqs), dtype=np.uint64)
+    rejected = dropped = 0
     t0 = time.perf_counter()
     late = 0.0
     for i, r in enumerate(reqs):
+        if r.parent >= 0:
+            pt = int(tickets[r.parent])
+            if pt == 0:  # the parent was rejected or dropped: the search cannot go on from it
+                dropped += 1
+                continue
+            structs[i].parent = pt
         while True:
             now = time.perf_counter() - t0
             if now >= r.t:
@@ -388,24 +414,36 @@ def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: in
         late = max(late, now - r.t)
         st = lib.bp_queue_submit(q.handle, ctypes.byref(structs[i]), 0, ctypes.byref(ticket))
         if st == bp.BP_ERR_AGAIN:
-            rejected[0] += 1
+            rejected += 1
         elif st != 0:
             raise bp.BpError(st, lib.bp_last_error().decode())
+        else:
+            tickets[i] = ticket.value
+            submitted[0] += 1
+    t_submit = time.perf_counter() - t0
     done.set()
     th.join(timeout=120)
     t_end = time.perf_counter() - t0
     stats = q.stats()
     q.close()
-    lat = np.array([d - s for _, s, d, st, _ in results if st == 0])
-    evals = sum(e for *_, st, e in results if st == 0)
-    return {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "completed": int(len(lat)),
-            "rejected": rejected[0], "checks_per_s": len(lat) / t_end, "evals_per_s": evals / t_end,
+    ok = [x for x in results if x[3] == 0]
+    lat = np.array([d - s for _, s, d, *_ in ok])
+    evals_nominal = sum(x[4] for x in ok)
+    evals_done = sum(x[5] for x in ok)
+    return {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "submitted": submitted[0],
+            "completed": int(len(ok)), "rejected": rejected, "dropped_with_rejected_parent": dropped,
+            "checks_per_s": len(ok) / t_end, "evals_per_s": evals_done / t_end,
+            "nominal_evals_per_s": evals_nominal / t_end,
             "p50_us": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_us": float(np.percentile(lat, 99)) if len(lat) else None,
-            "batches": stats["batches"], "peak_bytes": stats["bytes_peak"], "max_submit_lateness_s": late,
-            "segments": bool(flags & bp.BP_SEGMENTS),
-            "workload": "DFS requests: roots n~U[200,5000], sizes U[C/20,C/2], C=10000, children commit 1-3 "
-                        "items by decreasing best fit; early exit on; HBM budget 8 GB"}
+            "from_parent": int(stats["from_parent"]), "full_sweeps": int(stats["full_sweeps"]),
+            "node_evictions": int(stats["node_evictions"]), "batches": stats["batches"],
+            "peak_bytes": stats["bytes_peak"], "max_slots": max_slots, "max_submit_lateness_s": late,
+            "submit_s": t_submit, "generate_s": t_gen, "segments": bool(flags & bp.BP_SEGMENTS),
+            "fails": int(sum(1 for x in ok if x[7] == 0)),
+            "workload": "simulated search: roots n~U[200,5000], sizes U[C/20,C/2], C=10000, m = best-fit-decreasing "
+                        "bins; children commit 1-3 items by decreasing best fit, 30% backtracking, a new root every "
+                        "64 nodes; roots exhaustive, children from their parents' sums; HBM budget 8 GB"}
 
 
 def main():
@@ -422,7 +460,7 @@ def main():
                     help="only time each DFF sweep alone on the large instance, dense and segment form, and exit")
     ap.add_argument("--no-segments", action="store_true",
                     help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
-    ap.add_argument("--served-seconds", type=float, default=0.25)
+    ap.add_argument("--served-seconds", type=float, default=2.0)
     ap.add_argument("--valu-rates", action="store_true",
                     help="only measure the VALU issue rate of each inner-loop opcode and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

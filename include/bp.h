@@ -113,6 +113,9 @@ typedef struct bp_bounds {
   int64_t evals;
   int32_t status;
   int32_t early_exit; /* 1 when an early-exit call stopped once lb > k (values then partial) */
+  int64_t evals_done; /* (item, parameter) evaluations of the work that ran: evals, less what an
+                         early exit skipped; for a served request computed from another node's
+                         sums, (changed items) x (sum of range sizes) */
 } bp_bounds;
 
 /* Library version string (static storage). */
@@ -264,7 +267,23 @@ bp_status bp_feasible_dev_noalloc(int32_t C, int32_t m, const int32_t *d_residua
 
 /* ---- served checks (continuous batching) -------------------------------- */
 
-/* One request: a partial packing in residual form, as bp_feasible takes it. */
+/* One item committed to a bin by the search (Sec. 5: decreasing best fit
+ * assigns an unpacked item to a bin), relative to a parent node. */
+typedef struct bp_commit {
+  int32_t size; /* the item's size: one of the parent's unpacked items */
+  int32_t bin;  /* 0 .. m - 1; the bin's load plus size must not exceed C */
+} bp_commit;
+
+/* One request: a node of the search.  Either a partial packing in residual
+ * form, as bp_feasible takes it (parent = 0), or the node reached from an
+ * earlier request of the same queue (parent = its ticket) by committing
+ * ncommit items: the unpacked items lose those sizes and each commit's bin
+ * gains its size.  A child request is checked from the parent's per-
+ * parameter sums kept on the device when they are still there (the reduced
+ * instance changes by the committed items and by the changed bins' virtual
+ * items, Fig. 3), else from the parent's instance kept on the host; its
+ * residual and unpacked may then be NULL (n is ignored).  C and m of a child
+ * are its parent's. */
 typedef struct bp_request {
   int32_t C;
   int32_t m;
@@ -274,7 +293,12 @@ typedef struct bp_request {
   uint64_t tag;            /* caller's value, returned in the result */
   uint32_t flags;          /* BP_NO_EARLY_EXIT | BP_SEGMENTS */
   uint32_t reserved;
+  uint64_t parent;           /* 0, or the ticket of an earlier request of this queue */
+  const bp_commit *commits;  /* ncommit items (parent != 0) */
+  int32_t ncommit;           /* 0 .. BP_MAX_COMMIT */
+  int32_t reserved2;
 } bp_request;
+#define BP_MAX_COMMIT 1024
 
 typedef struct bp_result {
   uint64_t ticket;
@@ -286,25 +310,40 @@ typedef struct bp_result {
   double start_us;  /* host clock when the request's batch was launched */
   double done_us;   /* host clock when the result became visible */
   bp_bounds bounds;
+  int32_t from_parent; /* 1: computed from another node's per-parameter sums; 0: full sweeps */
+  int32_t reserved;
 } bp_result;
 
 typedef struct bp_queue_stats {
   uint64_t submitted, completed, rejected, batches, in_flight;
   uint64_t bytes_in_use, bytes_peak, budget;
   double busy_us;
+  uint64_t from_parent;  /* completed from another node's sums */
+  uint64_t full_sweeps;  /* completed by the full sweeps */
+  uint64_t nodes_kept;   /* node states on the device now */
+  uint64_t node_evictions;
+  uint64_t node_bytes;   /* device bytes of the node-state arena */
 } bp_queue_stats;
 
 /* A queue owns a serving thread that admits requests into free slots while
  * earlier batches run, launches them as batches on its own streams and
- * publishes results.  hbm_budget_bytes bounds the device memory held by
- * admitted requests; max_slots bounds the requests admitted at once. */
+ * publishes results.  hbm_budget_bytes is allocated at creation: three
+ * quarters hold the node states of finished requests (least recently used
+ * evicted first), one quarter bounds the device memory charged to admitted
+ * requests (inputs and workspaces); max_slots bounds the requests admitted
+ * at once.  A request that does not fit waits (blocking submit) or is
+ * rejected with BP_ERR_AGAIN. */
 typedef struct bp_queue bp_queue;
 bp_status bp_queue_create(bp_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots, bp_queue **out);
 
 /* Copy the request (the caller may free its arrays on return) and return a
  * ticket.  blocking = 0: BP_ERR_AGAIN when no slot or budget is free;
- * blocking = 1: wait for one.  A request larger than the whole budget is
- * BP_ERR_LIMIT. */
+ * blocking = 1: wait for one.  A request larger than the admission share of
+ * the budget is BP_ERR_LIMIT.  A child request whose parent the queue no
+ * longer knows (the queue keeps the most recent BP_QUEUE_HISTORY nodes) and
+ * that carries no instance is BP_ERR_STATE; a commit outside [0, m) or past
+ * its bin's capacity is BP_ERR_RANGE. */
+#define BP_QUEUE_HISTORY 65536
 bp_status bp_queue_submit(bp_queue *q, const bp_request *req, int32_t blocking, uint64_t *ticket);
 
 /* Up to max finished results; waits up to timeout_us (0 = do not wait) for

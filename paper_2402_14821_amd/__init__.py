@@ -33,6 +33,8 @@ BP_MAX_REDUCE_ITEMS = 1 << 30
 BP_NOALLOC_MAX_ITEMS = 1 << 14
 BP_NOALLOC_SCRATCH_BYTES = 32 << 20
 BP_MAX_BATCH = 1 << 20
+BP_MAX_COMMIT = 1024
+BP_QUEUE_HISTORY = 65536
 
 _i32, _i64, _u32, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 _P32, _P64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
@@ -45,22 +47,27 @@ class bp_sweep(ctypes.Structure):
 class bp_bounds(ctypes.Structure):
     _fields_ = [("value", _i64 * BP_NB), ("argmax_lambda", _i64 * BP_NB), ("lb", _i64), ("lb_arg", _i32),
                 ("verdict", _i32), ("k", _i64), ("r", _i64), ("evals", _i64), ("status", _i32),
-                ("early_exit", _i32)]
+                ("early_exit", _i32), ("evals_done", _i64)]
 
 
 class bp_batch(ctypes.Structure):
     _fields_ = [("count", _i32), ("reserved", _i32), ("off", _P64), ("items", _P32), ("C", _P32), ("k", _P32)]
 
 
+class bp_commit(ctypes.Structure):
+    _fields_ = [("size", _i32), ("bin", _i32)]
+
+
 class bp_request(ctypes.Structure):
     _fields_ = [("C", _i32), ("m", _i32), ("n", _i64), ("residual", _P32), ("unpacked", _P32), ("tag", _u64),
-                ("flags", _u32), ("reserved", _u32)]
+                ("flags", _u32), ("reserved", _u32), ("parent", _u64), ("commits", ctypes.POINTER(bp_commit)),
+                ("ncommit", _i32), ("reserved2", _i32)]
 
 
 class bp_result(ctypes.Structure):
     _fields_ = [("ticket", _u64), ("tag", _u64), ("status", _i32), ("verdict", _i32), ("lb", _i64),
                 ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double), ("done_us", ctypes.c_double),
-                ("bounds", bp_bounds)]
+                ("bounds", bp_bounds), ("from_parent", _i32), ("reserved", _i32)]
 
 
 class bp_tuning(ctypes.Structure):
@@ -70,12 +77,14 @@ class bp_tuning(ctypes.Structure):
 class bp_queue_stats(ctypes.Structure):
     _fields_ = [("submitted", _u64), ("completed", _u64), ("rejected", _u64), ("batches", _u64),
                 ("in_flight", _u64), ("bytes_in_use", _u64), ("bytes_peak", _u64), ("budget", _u64),
-                ("busy_us", ctypes.c_double)]
+                ("busy_us", ctypes.c_double), ("from_parent", _u64), ("full_sweeps", _u64), ("nodes_kept", _u64),
+                ("node_evictions", _u64), ("node_bytes", _u64)]
 
 
 BOUNDS_DTYPE = np.dtype([("value", np.int64, BP_NB), ("argmax_lambda", np.int64, BP_NB), ("lb", np.int64),
                          ("lb_arg", np.int32), ("verdict", np.int32), ("k", np.int64), ("r", np.int64),
-                         ("evals", np.int64), ("status", np.int32), ("early_exit", np.int32)])
+                         ("evals", np.int64), ("status", np.int32), ("early_exit", np.int32),
+                         ("evals_done", np.int64)])
 assert BOUNDS_DTYPE.itemsize == ctypes.sizeof(bp_bounds)
 
 
@@ -180,11 +189,12 @@ def bounds_to_dict(b) -> dict:
     if isinstance(b, bp_bounds):
         return {"value": np.array(b.value[:], dtype=np.int64), "argmax": np.array(b.argmax_lambda[:], dtype=np.int64),
                 "lb": int(b.lb), "lb_arg": int(b.lb_arg), "verdict": int(b.verdict), "k": int(b.k), "r": int(b.r),
-                "evals": int(b.evals), "status": int(b.status), "early_exit": int(b.early_exit)}
+                "evals": int(b.evals), "status": int(b.status), "early_exit": int(b.early_exit),
+                "evals_done": int(b.evals_done)}
     return {"value": np.array(b["value"], dtype=np.int64), "argmax": np.array(b["argmax_lambda"], dtype=np.int64),
             "lb": int(b["lb"]), "lb_arg": int(b["lb_arg"]), "verdict": int(b["verdict"]), "k": int(b["k"]),
             "r": int(b["r"]), "evals": int(b["evals"]), "status": int(b["status"]),
-            "early_exit": int(b["early_exit"])}
+            "early_exit": int(b["early_exit"]), "evals_done": int(b["evals_done"])}
 
 
 def default_sweep(C: int, r: int = 0, max_w: int = 0, flags: int = 0) -> bp_sweep:
@@ -377,7 +387,23 @@ class Queue:
 
     def submit(self, C: int, residual, unpacked, tag: int = 0, flags: int = 0, blocking: bool = True) -> int:
         res, unp = _i32arr(residual), _i32arr(unpacked)
-        req = bp_request(C, len(res), len(unp), _p32(res), _p32(unp), tag, flags, 0)
+        req = bp_request(C, len(res), len(unp), _p32(res), _p32(unp), tag, flags, 0, 0, None, 0, 0)
+        t = _u64(0)
+        _check(self._lib.bp_queue_submit(self.handle, ctypes.byref(req), int(blocking), ctypes.byref(t)))
+        return int(t.value)
+
+    def submit_child(self, C: int, m: int, parent: int, commits, tag: int = 0, flags: int = 0,
+                     blocking: bool = True, residual=None, unpacked=None) -> int:
+        """A node reached from request `parent` by committing (size, bin) pairs;
+        its instance may be given too (used only when the parent is gone)."""
+        arr = (bp_commit * max(len(commits), 1))(*[bp_commit(int(w), int(b)) for w, b in commits])
+        if residual is not None:
+            res, unp = _i32arr(residual), _i32arr(unpacked)
+            pr, pu, n = _p32(res), _p32(unp), len(unp)
+        else:
+            pr = pu = None
+            n = 0
+        req = bp_request(C, m, n, pr, pu, tag, flags, 0, parent, arr, len(commits), 0)
         t = _u64(0)
         _check(self._lib.bp_queue_submit(self.handle, ctypes.byref(req), int(blocking), ctypes.byref(t)))
         return int(t.value)
@@ -385,7 +411,7 @@ class Queue:
     def try_submit(self, C: int, residual, unpacked, tag: int = 0, flags: int = 0):
         """Non-blocking submit: ticket, or None when the queue is full (BP_ERR_AGAIN)."""
         res, unp = _i32arr(residual), _i32arr(unpacked)
-        req = bp_request(C, len(res), len(unp), _p32(res), _p32(unp), tag, flags, 0)
+        req = bp_request(C, len(res), len(unp), _p32(res), _p32(unp), tag, flags, 0, 0, None, 0, 0)
         t = _u64(0)
         st = self._lib.bp_queue_submit(self.handle, ctypes.byref(req), 0, ctypes.byref(t))
         if st == BP_ERR_AGAIN:

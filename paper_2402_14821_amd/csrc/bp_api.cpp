@@ -395,6 +395,15 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
     p.r_cap = (int32_t)rcap;
     p.large = rcap > kSmallCap ? 1 : 0;
     p.flags = (q.clamp ? kPlanClampVB2 : 0u) | (q.early_exit ? kPlanEarlyExit : 0u);
+    p.state_off = q.state_off;
+    if (q.state_off >= 0) {
+      // node states hold the paper's full ranges, computed by plain tiles
+      int64_t dlo[kNB], dhi[kNB];
+      default_ranges(q.C, dlo, dhi);
+      for (int b = kL2; b < kNB; ++b)
+        if (q.lo[b] != dlo[b] || q.hi[b] != dhi[b] || q.clamp)
+          return fail(BP_ERR_ARG, "instance %lld: a node state needs the paper's full ranges", (long long)i);
+    }
     p.ws_off = ws;
     p.pre_off = pre;
     ws += std::max<int64_t>(rcap, 1);
@@ -435,6 +444,12 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         e.lam0 = 0;
         e.ntiles = (cand + tile - 1) / tile;
         push(e, (double)tile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0));
+        if (q.state_off >= 0) {
+          // the L2 aggregates of the node state at every lambda in [0, c/2]
+          e.mode = kModeL2State;
+          e.ntiles = ((int64_t)q.C / 2 + tile) / tile;
+          push(e, (double)tile * (2.0 * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0));
+        }
         continue;
       }
       const double dense_tc = (double)tile * ((double)rcap * unit_cost(b) + 60.0);
@@ -665,6 +680,10 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->bidx = (int32_t *)bidx_buf.p;
   d->divs = (const int32_t *)(dv + off_div);
   d->dcnt = (int32_t *)dcnt_buf.p;
+  d->nodes = nodes;
+  for (int64_t i = 0; i < count; ++i)
+    if (plan_vec[(size_t)i].state_off >= 0 && !nodes)
+      return fail(BP_ERR_STATE, "instance %lld asks for a node state but the context has no node arena", (long long)i);
   d->out = out_dev;
   d->count = count;
   d->nentries = nentries;
@@ -980,6 +999,7 @@ bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_
   if (n_in < 0 || m_res < 0) return fail(BP_ERR_ARG, "negative count");
   if (n_in + m_res > BP_MAX_ITEMS) return fail(BP_ERR_LIMIT, "%lld items > %d", (long long)(n_in + m_res), BP_MAX_ITEMS);
   memset(q, 0, sizeof *q);
+  q->state_off = -1;
   q->C = C;
   q->k = k;
   q->n_in = n_in;

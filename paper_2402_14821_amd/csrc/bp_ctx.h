@@ -24,6 +24,8 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_smal
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
                                  int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
                                  hipStream_t s, hipEvent_t ev[4]);
+hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
+                             long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s);
 hipError_t noalloc_scratch(int device, unsigned char **out);
 hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
                           int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
@@ -52,6 +54,7 @@ struct PlanIn {
   int64_t lo[kNB], hi[kNB];
   int32_t m_res, C, form;
   bool early_exit, clamp, segments;
+  int64_t state_off;  // >= 0: write the node state there (served requests); -1: none
 };
 
 struct Ctx {
@@ -120,6 +123,7 @@ struct Ctx {
   void destroy();
   bp_status ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hipGraphExec_t *ex);
   bp_status plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out);
+  long long *nodes = nullptr;  // node-state arena for plans with state_off >= 0 (owned by a served queue)
   bp_status run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_t host_in_len, const int32_t *in_dev,
                 const int32_t *in2_dev, bp_bounds *out_dev, hipStream_t s);
   bp_status wait_last_run();

@@ -6,6 +6,8 @@
 // host rewrites the descriptor and the inputs, then replays the graph.
 #pragma once
 
+#include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/bp.h"
@@ -58,6 +60,7 @@ struct InstPlan {
   int64_t dc_off;    // ndiv > 0: offset of the multiple counts [small x ndiv][big x ndiv]
   int32_t ndiv;      // divisors of c listed for the mirrored VB2 tiles (0: none)
   int32_t pad2;
+  int64_t state_off; // >= 0: the instance's node state (see node_layout) at LaunchDesc::nodes + state_off
 };
 constexpr uint32_t kPlanClampVB2 = 1u;
 constexpr uint32_t kPlanEarlyExit = 2u;
@@ -67,7 +70,9 @@ constexpr uint32_t kPlanSegments = 4u;
 // parameter), or threshold sums over windows of the sorted sizes.
 // kModeMirror (VB2): each lane's dense sum at lambda also gives the sum at
 // c - lambda.
-enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2 };
+// kModeL2State: tiles over every lambda in [0, c/2] that store the L2
+// aggregates of the node state (no maximum).
+enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2, kModeL2State = 3 };
 constexpr int kMaxDivs = 256;         // most divisors of c a mirrored instance may have
 constexpr int kMirrorMinItems = 256;  // fewer items: the per-parameter gcd outweighs the saved half
 
@@ -85,6 +90,7 @@ struct InstState {
   int32_t maxw;
   int32_t status;    // BP_OK or an error found on the device
   int32_t pad;
+  unsigned long long evals_done;  // (item, parameter) evaluations of the tiles that ran
 };
 
 // One (instance, bound) entry of the sweep schedule.  Its parameter range is
@@ -124,6 +130,7 @@ struct LaunchDesc {
   int32_t *bidx;            // threshold tables: bidx[b] = #{sorted sizes >= b 2^bshift}
   const int32_t *divs;      // per mirrored instance: divisors of c (ascending), their lattice bins, prime count, (prime, exponent) pairs
   int32_t *dcnt;            // per divisor d: #{small sizes divisible by d}, then the same for big sizes
+  long long *nodes;         // node-state arena of served requests (InstPlan::state_off)
   bp_bounds *out;           // [count] results
   int64_t count;            // instances
   int64_t nentries;
@@ -131,6 +138,82 @@ struct LaunchDesc {
   int64_t acc_len;
   int64_t nsplit;           // combine segments (kSegTiles split tiles each) over all entries
 };
+
+// Node state of a served request (incremental serving): everything the
+// bounds of the collection need, as sums over the reduced items that are
+// additive in the items, so that a node one commit away from another has
+// its state from the other's plus the changed items' terms.  Per bound, in
+// the order L2, MT, RAD2, FS1, CCM1, VB2, BJ1, over the paper's ranges
+// (Sec. 3.1), int64:
+//   L2    lambda in [0, c/2]: n1(lambda) = #{w > c - lambda}, then
+//         T(lambda) = sum of the sizes in W2 and W3 (c/2 < w <= c - lambda,
+//         or lambda <= w <= c/2); L2(I, lambda) = nbig + max(0, ceil((T -
+//         c (nbig - n1)) / c)) with nbig = #{2w > c};
+//   DFF f S_f(lambda) = sum_w f(w, lambda) for lambda in its range.
+// node_len(C, b) is the number of elements of bound b, node_off(C, b) its
+// first element; node_layout fills off[b] = node_off(C, b), off[kNB] = the
+// length.  (No arrays in the functions the kernels call: a runtime-indexed
+// array would be placed in per-lane scratch memory.)
+__host__ __device__ inline int64_t node_len(int32_t C, int b) {
+  const int64_t c = C;
+  switch (b) {
+    case kL2: return 2 * (c / 2 + 1);
+    case kMT: return c / 2 + 1;
+    case kRAD2: return c / 3 > c / 4 ? c / 3 - c / 4 : 0;
+    case kFS1: return 100;
+    case kCCM1: return c / 2;
+    case kVB2: return c > 1 ? c - 1 : 0;
+    case kBJ1: return c;
+    default: return 0;
+  }
+}
+
+__host__ __device__ inline int64_t node_off(int32_t C, int bound) {
+  int64_t o = 0;
+  for (int b = kL2; b < bound; ++b) o += node_len(C, b);
+  return o;
+}
+
+__host__ __device__ inline void node_layout(int32_t C, int64_t off[kNB + 1]) {
+  off[0] = 0;
+  for (int b = 0; b < kNB; ++b) off[b + 1] = off[b] + node_len(C, b);
+}
+
+// A served request computed from another node's state (the base) and the
+// items by which its reduced instance differs from the base's.
+struct NodeTask {
+  int64_t base_off;    // node state of the base (LaunchDesc::nodes + base_off)
+  int64_t dst_off;     // where this request's node state goes (-1: not kept)
+  int64_t tile_begin;  // prefix of node_tiles() over the tasks of the launch
+  int64_t sumW;        // total size of the request's reduced items
+  int64_t r;           // their count
+  int64_t k;           // bins
+  int32_t C;
+  int32_t nbig;        // #{2w > c} among them
+  int32_t d_off;       // changed items: delta[d_off .. d_off + nd), v > 0 adds a size v - 1,
+  int32_t nd;          //   v < 0 removes a size -v - 1
+  int32_t out_idx;     // record index in the launch's output
+  int32_t pad;
+};
+
+// Parameters handled by one block of the served-child kernel, and the
+// per-bound tile counts: tb[b] is the first tile of bound b, tb[kNB] the
+// total (L2 tiles cover lambda in [0, c/2], both aggregates).
+constexpr int kNodeTile = 256;
+// Parameters of bound b in one node state (L2: lambda in [0, c/2]).
+__host__ __device__ inline int64_t node_params(int32_t C, int b) {
+  return b == kL2 ? node_len(C, b) / 2 : node_len(C, b);
+}
+
+__host__ __device__ inline int64_t node_tile_count(int32_t C, int b) {
+  return (node_params(C, b) + kNodeTile - 1) / kNodeTile;
+}
+
+__host__ __device__ inline int64_t node_tiles(int32_t C) {
+  int64_t n = 0;
+  for (int b = kL2; b < kNB; ++b) n += node_tile_count(C, b);
+  return n;
+}
 
 // Allocation-free check (bp_feasible_dev_noalloc): the tables and every
 // workspace of a one-instance launch inside one file-scope device array per

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "bp_divide.h"
@@ -553,6 +554,7 @@ __device__ void prep_finish(const LaunchDesc &d, int64_t inst) {
     if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
   }
   for (int b = 0; b < kNB; ++b) d.keys[inst * kNB + b] = 0ull;
+  st->evals_done = 0ull;
   int refuted = 0;
   if ((p.flags & kPlanEarlyExit) && st->status == BP_OK && r > 0) {
     const int64_t l1 = (st->sumW + p.C - 1) / p.C;
@@ -614,6 +616,7 @@ struct TileArgs {
   int32_t qc, qn;                // BJ1/CCM1 segment tiles: this chunk of qn takes its share of the q range
   const BP_GLOBAL int32_t *divs; // ascending
   const BP_GLOBAL int32_t *dcnt; // [small x ndiv][big x ndiv] multiple counts
+  long long *node;               // served request: this bound's block of the node state, indexed by lambda - lo
 };
 
 // Largest number of items whose per-item increments, each at most maxinc,
@@ -715,9 +718,9 @@ __device__ void part_mt(const TileArgs &t, const uint32_t lam[LPL], int64_t part
   for (int j = 0; j < LPL; ++j) part[j] = (int64_t)acc[j];
 }
 
-__device__ __forceinline__ int64_t fin_mt(const TileArgs &t, int64_t lam, int64_t part) {
-  const int64_t S = t.sumBig + (int64_t)(t.nm - t.nb) * (int64_t)(t.C / 2) + part;
-  return ceil_div_small(S, (int64_t)t.C);
+// S_MT(lambda) over the streamed items (sizes c excluded); f_MT(c) = c.
+__device__ __forceinline__ int64_t sum_mt(const TileArgs &t, int64_t lam, int64_t part) {
+  return t.sumBig + (int64_t)(t.nm - t.nb) * (int64_t)(t.C / 2) + part;
 }
 
 // f_RAD2 (c/4 < lambda <= c/3), from counts of threshold crossings:
@@ -755,9 +758,8 @@ __device__ void part_rad2(const TileArgs &t, const uint32_t lam[LPL], int64_t pa
     part[j] = c3 * n1[j] + (c2 - c3) * n2[j] + (C - c2 - c3) * n3[j] + c3 * n4[j];
 }
 
-__device__ __forceinline__ int64_t fin_rad2(const TileArgs &t, int64_t lam, int64_t part) {
-  const int64_t S = (int64_t)(t.nm - t.nf) * (int64_t)(t.C / 2) + part;
-  return ceil_div_small(S, (int64_t)t.C);
+__device__ __forceinline__ int64_t sum_rad2(const TileArgs &t, int64_t lam, int64_t part) {
+  return (int64_t)(t.nm - t.nf) * (int64_t)(t.C / 2) + part;
 }
 
 // f_FS1 (1 <= lambda <= 100): with n = w (lambda + 1) and q = floor(n / c),
@@ -785,9 +787,7 @@ __device__ void part_fs1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
   for (int j = 0; j < LPL; ++j) part[j] = (int64_t)Q[j] * (int64_t)t.C - (int64_t)D[j];
 }
 
-__device__ __forceinline__ int64_t fin_fs1(const TileArgs &t, int64_t lam, int64_t part) {
-  return ceil_div_small(part, (int64_t)t.C * lam);
-}
+__device__ __forceinline__ int64_t sum_fs1(const TileArgs &t, int64_t lam, int64_t part) { return part; }
 
 // f_CCM1 (1 <= lambda <= c/2), K = floor(c / lambda):
 //   big 2K - 2 floor((c - w)/lambda), mid K, small 2 floor(w / lambda).
@@ -815,10 +815,9 @@ __device__ void part_ccm1(const TileArgs &t, const uint32_t lam[LPL], int64_t pa
   for (int j = 0; j < LPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
 }
 
-__device__ __forceinline__ int64_t fin_ccm1(const TileArgs &t, int64_t lam, int64_t part) {
+__device__ __forceinline__ int64_t sum_ccm1(const TileArgs &t, int64_t lam, int64_t part) {
   const int64_t K = (int64_t)((uint32_t)t.C / (uint32_t)lam);
-  const int64_t S = 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
-  return ceil_div_small(S, 2 * K);
+  return 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
 }
 
 // f_VB2 (2 <= lambda <= c), h(a) = ceil(a lambda / c) - 1 for a >= 1:
@@ -847,10 +846,9 @@ __device__ void part_vb2(const TileArgs &t, const uint32_t lam[LPL], int64_t par
   for (int j = 0; j < LPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
 }
 
-__device__ __forceinline__ int64_t fin_vb2(const TileArgs &t, int64_t lam, int64_t part) {
+__device__ __forceinline__ int64_t sum_vb2(const TileArgs &t, int64_t lam, int64_t part) {
   const int64_t K = lam - 1;
-  const int64_t S = 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
-  return ceil_div_small(S, 2 * K);
+  return 2 * K * (t.nb - t.nf) + K * (t.nm - t.nb) + part;
 }
 
 // f_BJ1 (1 <= lambda <= c), p = c mod lambda, q = floor(w / lambda),
@@ -896,13 +894,10 @@ __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
     part[j] = ((int64_t)lam[j] - 2 * (int64_t)pm[j]) * (int64_t)Q[j] + (int64_t)A[j];
 }
 
-__device__ __forceinline__ int64_t fin_bj1(const TileArgs &t, int64_t lam, int64_t part) {
-  const uint32_t c32 = (uint32_t)t.C, l32 = (uint32_t)lam;
-  const int64_t p = (int64_t)(c32 % l32);
+__device__ __forceinline__ int64_t sum_bj1(const TileArgs &t, int64_t lam, int64_t part) {
+  const int64_t p = (int64_t)((uint32_t)t.C % (uint32_t)lam);
   const int64_t n = t.nz - t.nf;
-  const int64_t S = (part + t.sumNZ - n * p) >> 1;  // the sum is even and >= 0
-  const int64_t fc = (int64_t)(c32 / l32) * (lam - p);
-  return ceil_div_small(S, fc);
+  return (part + t.sumNZ - n * p) >> 1;  // the sum is even and >= 0
 }
 
 // ---------------------------------------------------------------------------
@@ -1105,15 +1100,58 @@ __device__ void part_mt_seg(const TileArgs &t, const int64_t lam_out[LPL], int64
   for (int j = 0; j < LPL; ++j) part[j] = base + (int64_t)acc[j];
 }
 
-__device__ __forceinline__ int64_t fin_bound(int bound, const TileArgs &t, int64_t lam, int64_t part) {
+// sum over the streamed items (sizes c excluded) of f(w, lambda), from a
+// tile's part
+__device__ __forceinline__ int64_t sum_bound(int bound, const TileArgs &t, int64_t lam, int64_t part) {
   switch (bound) {
-    case kMT: return fin_mt(t, lam, part);
-    case kRAD2: return fin_rad2(t, lam, part);
-    case kFS1: return fin_fs1(t, lam, part);
-    case kCCM1: return fin_ccm1(t, lam, part);
-    case kVB2: return fin_vb2(t, lam, part);
-    default: return fin_bj1(t, lam, part);
+    case kMT: return sum_mt(t, lam, part);
+    case kRAD2: return sum_rad2(t, lam, part);
+    case kFS1: return sum_fs1(t, lam, part);
+    case kCCM1: return sum_ccm1(t, lam, part);
+    case kVB2: return sum_vb2(t, lam, part);
+    default: return sum_bj1(t, lam, part);
   }
+}
+
+// f(c, lambda) of each function (Sec. 3.1): c (MT, RAD2), c lambda (FS1),
+// 2 floor(c / lambda) (CCM1), 2 (lambda - 1) (VB2), floor(c / lambda)
+// (lambda - c mod lambda) (BJ1).
+__device__ __forceinline__ int64_t fc_bound(int bound, int32_t C, int64_t lam) {
+  const uint32_t c32 = (uint32_t)C, l32 = (uint32_t)lam;
+  switch (bound) {
+    case kMT: case kRAD2: return C;
+    case kFS1: return (int64_t)C * lam;
+    case kCCM1: return 2 * (int64_t)(c32 / l32);
+    case kVB2: return 2 * (lam - 1);
+    default: return (int64_t)(c32 / l32) * (lam - (int64_t)(c32 % l32));
+  }
+}
+
+// The bound at lambda without the items of size c (each adds exactly 1):
+// ceil(S / f(c, lambda)).
+__device__ __forceinline__ int64_t fin_bound(int bound, const TileArgs &t, int64_t lam, int64_t part) {
+  return ceil_div_small(sum_bound(bound, t, lam, part), fc_bound(bound, t.C, lam));
+}
+
+// Node state of a served request: S(lambda) over all reduced items, the
+// nf items of size c included (each adds f(c, lambda)).
+__device__ __forceinline__ void store_state(int bound, const TileArgs &t, int64_t lam, int64_t part) {
+  t.node[lam - t.lo] = (long long)(sum_bound(bound, t, lam, part) + (int64_t)t.nf * fc_bound(bound, t.C, lam));
+}
+
+template <int LPL>
+__device__ __forceinline__ void store_state_lanes(int bound, const TileArgs &t, const int64_t lam[LPL],
+                                                  const int64_t part[LPL]) {
+  for (int j = 0; j < LPL; ++j)
+    if (lam[j] >= t.lo && lam[j] <= t.hi) store_state(bound, t, lam[j], part[j]);
+}
+
+// Parameters of a tile inside the bound's range (for the executed-work count).
+template <int LPL>
+__device__ __forceinline__ uint32_t lanes_in_range(const TileArgs &t, const int64_t lam[LPL]) {
+  uint32_t n = 0;
+  for (int j = 0; j < LPL; ++j) n += (uint32_t)__popcll(ballot64(lam[j] >= t.lo && lam[j] <= t.hi));
+  return n;
 }
 
 // L2 (Sec. 3.1) evaluated at the parameters where it can change: the range's
@@ -1166,6 +1204,44 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL
     const int64_t s3 = j3 > nbig ? t.pre[j3] - t.pre[nbig] : 0;
     const int64_t x = s3 - (C * n2 - s2);
     lbp[j] = nbig + (x > 0 ? ceil_div_small(x, C) : 0);
+  }
+}
+
+// L2 aggregates of the node state at every lambda of the tile, lambda in
+// [0, c/2]: n1 = #{w > c - lambda} and T = sum W2 + sum W3, from the sorted
+// sizes (binary lifting, as tile_l2) and their prefix sums.
+template <int LPL>
+__device__ void tile_l2_state(const TileArgs &t) {
+  const int64_t C = t.C;
+  const int32_t nbig = t.nb;
+  const int32_t r = t.r;
+  const int64_t half = C / 2;
+  int64_t lam[LPL], x1[LPL], x3[LPL];
+  int32_t p1[LPL], p3[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    lam[j] = t.lam0 + lane_id() + 64 * j;
+    const int64_t l = lam[j] <= half ? lam[j] : half;
+    x1[j] = C - l;
+    x3[j] = l - 1;
+    p1[j] = 0;
+    p3[j] = 0;
+  }
+  for (int32_t step = r > 0 ? (int32_t)(1u << (31 - __clz(r))) : 0; step > 0; step >>= 1) {
+    for (int j = 0; j < LPL; ++j) {
+      const int32_t q1 = p1[j] + step, q3 = p3[j] + step;
+      const int64_t v1 = t.sorted[min(q1, r) - 1];
+      const int64_t v3 = t.sorted[min(q3, r) - 1];
+      if (q1 <= r && v1 > x1[j]) p1[j] = q1;
+      if (q3 <= r && v3 > x3[j]) p3[j] = q3;
+    }
+  }
+  for (int j = 0; j < LPL; ++j) {
+    if (lam[j] > half) continue;
+    const int32_t n1 = p1[j], j3 = p3[j];
+    const int64_t s2 = t.pre[nbig] - t.pre[n1];
+    const int64_t s3 = j3 > nbig ? t.pre[j3] - t.pre[nbig] : 0;
+    t.node[lam[j]] = n1;
+    t.node[half + 1 + lam[j]] = s2 + s3;
   }
 }
 
@@ -1222,8 +1298,12 @@ __device__ uint64_t vb2_mirror_key(const TileArgs &t, int64_t mm, const int64_t 
     l2[j] = C - lam[j];
     o1[j] = in && l1[j] >= t.lo && l1[j] <= t.hi;
     o2[j] = in && l2[j] >= t.lo && l2[j] <= t.hi;
-    v1[j] = o1[j] ? fin_vb2(t, l1[j], part[j]) : 0;
-    v2[j] = o2[j] ? fin_vb2(t, l2[j], part2) : 0;
+    v1[j] = o1[j] ? fin_bound(kVB2, t, l1[j], part[j]) : 0;
+    v2[j] = o2[j] ? fin_bound(kVB2, t, l2[j], part2) : 0;
+    if (t.node) {
+      if (o1[j]) store_state(kVB2, t, l1[j], part[j]);
+      if (o2[j]) store_state(kVB2, t, l2[j], part2);
+    }
   }
   return umax64(tile_max<LPL>(l1, v1, o1), tile_max<LPL>(l2, v2, o2));
 }
@@ -1286,6 +1366,7 @@ __device__ __forceinline__ bool entry_args(const LaunchDesc &d, const BP_CONST E
   t.ndiv = p.ndiv;
   t.divs = as_global(d.divs + p.div_off);
   t.dcnt = as_global(d.dcnt + p.dc_off);
+  t.node = p.state_off >= 0 ? d.nodes + p.state_off + node_off(p.C, bound) : nullptr;
   early = (p.flags & kPlanEarlyExit) != 0;
   return true;
 }
@@ -1314,19 +1395,27 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   // a split BJ1/CCM1 segment tile divides its q range instead
   t.qc = chunk;
   t.qn = nch;
+  // its share of the r reduced items, for the executed-work count (the
+  // shares of a tile's chunks add up to r)
+  const uint64_t share = (uint64_t)((int64_t)t.r * (chunk + 1) / nch - (int64_t)t.r * chunk / nch);
+  uint64_t done = 0;
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
-    if (early && refuted_now(d, inst)) return;
+    if (early && refuted_now(d, inst)) break;
     t.lam0 = e.lam0 + tl * (64 * LPL);
     int64_t lam[LPL], lbp[LPL];
     bool ok[LPL];
+    if (e.mode == kModeL2State) {
+      tile_l2_state<LPL>(t);
+      continue;
+    }
     if (bound == kL2) {
       // tiles of L2 run over candidate indices, not parameters
       tile_l2<LPL>(t, lam, lbp, ok);
       flush_tile<LPL>(d, inst, kL2, t, lam, lbp, ok, early);
       continue;
     }
-    if (t.lam0 > t.hi) return;
+    if (t.lam0 > t.hi) break;
     // the dense half of a mirrored VB2 entry runs over [1, aux]
     TileArgs tv = t;
     if (e.mode == kModeMirror) {
@@ -1349,6 +1438,17 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       case kVB2: part_vb2<LPL>(tv, l32, part); break;
       default: part_bj1<LPL>(t, l32, part); break;
     }
+    if (e.mode == kModeMirror) {
+      // each dense lambda of the half also stands for c - lambda
+      int64_t own[LPL], mir[LPL];
+      for (int j = 0; j < LPL; ++j) {
+        own[j] = lam[j] <= e.aux ? lam[j] : -1;
+        mir[j] = lam[j] <= e.aux ? t.C - lam[j] : -1;
+      }
+      done += (uint64_t)(lanes_in_range<LPL>(t, own) + lanes_in_range<LPL>(t, mir)) * share;
+    } else {
+      done += (uint64_t)lanes_in_range<LPL>(t, lam) * share;
+    }
     if (nch > 1) {
       // A chunk of a split tile: store its partial sums in its own slot (no
       // other wave touches it) and move on; the combine kernel adds the
@@ -1362,12 +1462,14 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       if (lane_id() == 0) publish_key(d, inst, bound, t, key, early);
       continue;
     }
+    if (t.node) store_state_lanes<LPL>(bound, t, lam, part);
     for (int j = 0; j < LPL; ++j) {
       ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
       lbp[j] = ok[j] ? fin_bound(bound, t, lam[j], part[j]) : 0;
     }
     flush_tile<LPL>(d, inst, bound, t, lam, lbp, ok, early);
   }
+  if (done && lane_id() == 0) atomicAdd(&d.state[inst].evals_done, (unsigned long long)done);
 }
 
 // Split tiles, in segments of kSegTiles consecutive tiles of one entry: a
@@ -1429,6 +1531,7 @@ __global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__
       if (e.mode == kModeMirror) {
         key = vb2_mirror_key<LPL>(t, e.aux, lam, part);
       } else {
+        if (t.node) store_state_lanes<LPL>(e.bound, t, lam, part);
         for (int j = 0; j < LPL; ++j) {
           ok[j] = lam[j] >= t.lo && lam[j] <= t.hi;
           lbp[j] = ok[j] ? fin_bound(e.bound, t, lam[j], part[j]) : 0;
@@ -1502,6 +1605,7 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__
       if (b >= kMT && st.hiEff[b] >= p.lo[b]) P += st.hiEff[b] - p.lo[b] + 1;
     }
     o.evals = (int64_t)st.r * P;
+    o.evals_done = (int64_t)st.evals_done;
     if (st.status == BP_OK) {
       o.value[kL1] = (st.sumW + p.C - 1) / p.C;
       for (int b = kL2; b < kNB; ++b) {
@@ -1522,6 +1626,220 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__
     o.verdict = lb <= p.k ? 1 : 0;
     d.out[inst] = o;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Served requests from another node's state (incremental serving).  Every
+// quantity of the node state is a sum over the reduced items, so a request
+// whose reduced instance differs from its base's by a few items has
+//   S_f(lambda) = S_f,base(lambda) + sum_added f(w, lambda) - sum_removed f(w, lambda)
+// and likewise n1 and T of L2: O(P) work per changed item instead of O(P r).
+// The per-item terms are the functions of Sec. 3.1 evaluated exactly for one
+// size and the lane's parameter.
+
+// Per-lane constants of one parameter lambda.
+struct LamConst {
+  uint32_t lam, K, p;   // lambda, floor(c / lambda), c mod lambda
+  MagicU31 g;           // division by lambda (family (1) of bp_divide.h)
+  uint32_t rlo, rhi;    // VB2 reciprocal (family (2))
+};
+
+__device__ __forceinline__ LamConst lam_const(int bound, uint32_t C, uint32_t lam) {
+  LamConst k;
+  k.lam = lam;
+  k.K = lam ? C / lam : 0;
+  k.p = lam ? C - k.K * lam : 0;
+  k.g = magic_u31(lam ? lam : 1u);
+  k.rlo = k.rhi = 0;
+  if (bound == kVB2) {
+    const uint64_t R = vb2_recip(lam, C);
+    k.rlo = (uint32_t)R;
+    k.rhi = (uint32_t)(R >> 32);
+  }
+  return k;
+}
+
+// f(w, lambda) for 0 <= w <= c, lambda in the function's range (Sec. 3.1).
+__device__ __forceinline__ int64_t dff_term(int bound, uint32_t C, uint32_t w, const LamConst &k) {
+  const uint32_t lam = k.lam;
+  switch (bound) {
+    case kMT:  // c if w > c - lambda; w if lambda <= w <= c - lambda; 0 if w < lambda
+      if (w > C - lam) return C;
+      return w >= lam ? (int64_t)w : 0;
+    case kRAD2:  // 0 | c/3 | c/2 | c - f(c - w), the last one level deep
+      if (w < lam) return 0;
+      if (w <= C - 2 * lam) return C / 3;
+      if (w < 2 * lam) return C / 2;
+      return (int64_t)C - (C - w >= lam ? (int64_t)(C / 3) : 0);
+    case kFS1: {  // w lambda if c divides w (lambda + 1), else floor(w (lambda + 1) / c) c
+      const uint64_t n = (uint64_t)w * (lam + 1u);
+      const uint64_t q = n / C;
+      return q * C == n ? (int64_t)w * lam : (int64_t)(q * C);
+    }
+    case kCCM1:  // 2 K - 2 floor((c - w) / lambda) | K | 2 floor(w / lambda)
+      if (2ull * w > C) return 2 * ((int64_t)k.K - (int64_t)div_u31(2u * (C - w), k.g.m, k.g.s));
+      if (2ull * w == C) return k.K;
+      return 2 * (int64_t)div_u31(2u * w, k.g.m, k.g.s);
+    case kVB2: {  // with h(a) = max(0, ceil(a lambda / c) - 1): 2 (lambda - 1) - 2 h(c - w) | lambda - 1 | 2 h(w)
+      if (2ull * w > C) {
+        const uint32_t a = C - w;
+        return 2 * ((int64_t)lam - 1) - 2 * (int64_t)(a ? vb2_part(a, k.rlo, k.rhi) : 0u);
+      }
+      if (2ull * w == C) return (int64_t)lam - 1;
+      return 2 * (int64_t)(w ? vb2_part(w, k.rlo, k.rhi) : 0u);
+    }
+    default: {  // BJ1: floor(w / lambda) (lambda - p) + max(0, (w mod lambda) - p)
+      const uint32_t q = div_u31(2u * w, k.g.m, k.g.s);
+      const uint32_t rem = w - q * lam;
+      return (int64_t)q * (lam - k.p) + (rem > k.p ? (int64_t)(rem - k.p) : 0);
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t default_lo(int bound, int32_t C) {
+  switch (bound) {
+    case kL2: case kMT: return 0;
+    case kRAD2: return C / 4 + 1;
+    case kVB2: return 2;
+    default: return 1;
+  }
+}
+
+__device__ __forceinline__ int64_t find_node_task(const BP_CONST NodeTask *t, int64_t n, int64_t tile) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (t[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Clears the packed maxima of the launch's child requests.
+__global__ __launch_bounds__(256) void k_node_begin(unsigned long long *keys, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kNB; i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = 0ull;
+}
+
+// One block of kNodeTile threads per (child, bound, run of kNodeTile
+// parameters): each thread updates its parameter's state from the base,
+// stores it (when kept) and takes its bound value; one packed-key maximum
+// per block.
+__global__ __launch_bounds__(kNodeTile) void k_node_delta(const NodeTask *__restrict__ tasks, int64_t ntasks,
+                                                       int64_t ntiles, const int32_t *__restrict__ delta,
+                                                       long long *__restrict__ nodes, unsigned long long *keys) {
+  __shared__ unsigned long long wkey[kNodeTile / 64];
+  const BP_CONST NodeTask *tk = as_const(tasks);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t ti = find_node_task(tk, ntasks, tile);
+    const BP_CONST NodeTask &t = tk[ti];
+    const int32_t C = t.C;
+    // the bound and first parameter of this tile
+    int64_t local = tile - t.tile_begin;
+    int bound = kL2;
+    while (bound + 1 < kNB && local >= node_tile_count(C, bound)) {
+      local -= node_tile_count(C, bound);
+      ++bound;
+    }
+    const int64_t len = node_params(C, bound);
+    const int64_t boff = node_off(C, bound);
+    const int64_t idx = local * kNodeTile + threadIdx.x;
+    const bool valid = idx < len;
+    const int64_t lam = default_lo(bound, C) + idx;
+    uint64_t key = 0;
+    if (valid) {
+      const long long *base = nodes + t.base_off + boff;
+      long long *dst = t.dst_off >= 0 ? nodes + t.dst_off + boff : nullptr;
+      const BP_CONST int32_t *dl = as_const(delta + t.d_off);
+      const uint32_t uC = (uint32_t)C;
+      if (bound == kL2) {
+        const int64_t half = C / 2;
+        int64_t n1 = base[idx], T = base[half + 1 + idx];
+        for (int32_t j = 0; j < t.nd; ++j) {
+          const int32_t v = dl[j];
+          const int64_t sg = v > 0 ? 1 : -1;
+          const int64_t w = v > 0 ? v - 1 : -(int64_t)v - 1;
+          if (w > C - lam) n1 += sg;
+          const bool w2 = 2 * w > C && w <= C - lam;   // c/2 < w <= c - lambda
+          const bool w3 = w >= lam && 2 * w <= C;      // lambda <= w <= c/2
+          if (w2 || w3) T += sg * w;
+        }
+        if (dst) {
+          dst[idx] = n1;
+          dst[half + 1 + idx] = T;
+        }
+        const int64_t x = T - (int64_t)C * ((int64_t)t.nbig - n1);
+        key = pack_key(t.nbig + (x > 0 ? ceil_div_small(x, C) : 0), lam);
+      } else {
+        const LamConst kc = lam_const(bound, uC, (uint32_t)lam);
+        int64_t S = base[idx];
+        for (int32_t j = 0; j < t.nd; ++j) {
+          const int32_t v = dl[j];
+          const uint32_t w = v > 0 ? (uint32_t)(v - 1) : (uint32_t)(-(int64_t)v - 1);
+          const int64_t f = dff_term(bound, uC, w, kc);
+          S += v > 0 ? f : -f;
+        }
+        if (dst) dst[idx] = S;
+        key = pack_key(ceil_div_small(S, fc_bound(bound, C, lam)), lam);
+      }
+    }
+    const uint64_t wm = wave_max_u64(key);
+    if (lane_id() == 0) wkey[threadIdx.x >> 6] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t m = 0;
+      for (int w = 0; w < kNodeTile / 64; ++w) m = umax64(m, wkey[w]);
+      if (m) atomicMax(&keys[ti * kNB + bound], (unsigned long long)m);
+    }
+    __syncthreads();
+  }
+}
+
+// The records of the launch's child requests: L1 from the total size, the
+// other bounds from the packed maxima, lb, verdict (Alg. 1).
+__global__ __launch_bounds__(256) void k_node_finalize(const NodeTask *__restrict__ tasks, int64_t ntasks,
+                                                    const unsigned long long *__restrict__ keys, bp_bounds *out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntasks; i += (int64_t)gridDim.x * blockDim.x) {
+    const NodeTask &t = tasks[i];
+    const int64_t P = node_off(t.C, kNB) - node_off(t.C, kMT);
+    bp_bounds o;
+    o.k = t.k;
+    o.r = t.r;
+    o.status = BP_OK;
+    o.early_exit = 0;
+    o.evals = t.r * P;
+    o.evals_done = (int64_t)t.nd * P;
+    o.value[kL1] = (t.sumW + t.C - 1) / t.C;
+    o.argmax_lambda[kL1] = -1;
+    for (int b = kL2; b < kNB; ++b) {
+      const uint64_t key = keys[i * kNB + b];
+      o.value[b] = key ? (int64_t)(key >> 32) : 0;
+      o.argmax_lambda[b] = key ? (int64_t)(0xffffffffu - (uint32_t)key) : -1;
+    }
+    int64_t lb = -1;
+    int32_t arg = 0;
+    for (int b = 0; b < kNB; ++b)
+      if (o.value[b] > lb) { lb = o.value[b]; arg = b; }
+    o.lb = lb;
+    o.lb_arg = arg;
+    o.verdict = lb <= t.k ? 1 : 0;
+    out[t.out_idx] = o;
+  }
+}
+
+hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
+                             long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_begin, dim3(std::max<int64_t>(1, std::min<int64_t>(64, (ntasks * kNB + 255) / 256))),
+                     dim3(256), 0, s, keys, ntasks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ntiles > 0) {
+    hipLaunchKernelGGL(k_node_delta, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, ntiles))),
+                       dim3(kNodeTile), 0, s, tasks, ntasks, ntiles, delta, nodes, keys);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_node_finalize, dim3(std::max<int64_t>(1, std::min<int64_t>(64, (ntasks + 255) / 256))),
+                     dim3(256), 0, s, tasks, ntasks, keys, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -175,11 +175,13 @@ class Request:
     residual: np.ndarray
     unpacked: np.ndarray
     node: int
+    parent: int = -1     # index of the request of the node this one was reached from (-1: a root)
+    commits: tuple = ()  # (size, bin) pairs committed since that request
 
 
 def dfs_requests(seed: int, rate: float, duration: float, C: int = 10_000, nlo: int = 200, nhi: int = 5000,
                  wlo: int | None = None, whi: int | None = None, p_back: float = 0.3, restart_every: int = 64,
-                 max_requests: int | None = None):
+                 max_requests: int | None = None, instances: str = "all"):
     """Open-loop request stream of a simulated depth-first search.
 
     Poisson arrivals at `rate` per second for `duration` seconds.  A root has
@@ -188,34 +190,42 @@ def dfs_requests(seed: int, rate: float, duration: float, C: int = 10_000, nlo: 
     the bin with the least remaining capacity that holds it (decreasing best
     fit); with probability p_back the search backtracks 1-3 levels instead.
     Every `restart_every` nodes a new root starts.  Each node is one request
-    (residual form)."""
+    (residual form); a request also names the request of the node it was
+    reached from (`parent`, -1 for a root) and the (size, bin) commits since
+    that node (none when the search returned to a node it had checked).
+    instances="roots" keeps residual and unpacked of the roots only (None for
+    the others), for long streams."""
     g = _rng(seed)
     wlo = C // 20 if wlo is None else wlo
     whi = C // 2 if whi is None else whi
     t = 0.0
     out = []
-    stack = []
+    stack = []  # (residual, unpacked, index of the node's latest request)
     node = 0
     since_root = restart_every
     while True:
         t += g.exponential(1.0 / rate)
         if t > duration or (max_requests is not None and len(out) >= max_requests):
             break
+        parent, commits = -1, ()
         if since_root >= restart_every or not stack:
             n0 = int(g.integers(nlo, nhi + 1))
             sizes = np.sort(g.integers(wlo, whi + 1, size=n0))[::-1].astype(np.int32)
             m = best_fit_decreasing_bins(C, sizes)
-            stack = [(np.full(m, C, dtype=np.int32), sizes)]
+            stack = [(np.full(m, C, dtype=np.int32), sizes, -1)]
             since_root = 0
         elif g.random() < p_back and len(stack) > 1:
             for _ in range(int(g.integers(1, 4))):
                 if len(stack) > 1:
                     stack.pop()
+            parent = stack[-1][2]
         else:
-            res, unp = stack[-1]
+            res, unp, idx = stack[-1]
+            parent = idx
             res = res.copy()
             k = min(int(g.integers(1, 4)), len(unp))
             ok = True
+            placed = []
             for i in range(k):
                 w = int(unp[i])
                 fits = np.flatnonzero(res >= w)
@@ -224,10 +234,16 @@ def dfs_requests(seed: int, rate: float, duration: float, C: int = 10_000, nlo: 
                     break
                 j = fits[np.argmin(res[fits])]
                 res[j] -= w
+                placed.append((w, int(j)))
             if ok and k > 0:
-                stack.append((res, unp[k:].copy()))
-        res, unp = stack[-1]
-        out.append(Request(t, C, res.copy(), unp.copy(), node))
+                stack.append((res, unp[k:].copy(), idx))
+                commits = tuple(placed)
+        res, unp, _ = stack[-1]
+        if instances == "all" or parent < 0:
+            out.append(Request(t, C, res.copy(), unp.copy(), node, parent, commits))
+        else:
+            out.append(Request(t, C, None, None, node, parent, commits))
+        stack[-1] = (res, unp, len(out) - 1)
         node += 1
         since_root += 1
     return out

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(bp.bp_sweep) == 8 * 8 * 2 + 8
-    assert ctypes.sizeof(bp.bp_bounds) == 8 * 8 * 2 + 8 + 4 + 4 + 8 * 3 + 4 + 4
+    assert ctypes.sizeof(bp.bp_bounds) == 8 * 8 * 2 + 8 + 4 + 4 + 8 * 3 + 4 + 4 + 8
     assert ctypes.sizeof(bp.bp_batch) == 8 + 4 * 8
     assert bp.BOUNDS_DTYPE.itemsize == ctypes.sizeof(bp.bp_bounds)
 

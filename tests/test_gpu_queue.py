@@ -139,10 +139,124 @@ def test_served_requests_match_oracle(ctx):
     assert refuted_early == len(verdicts) - sum(verdicts)
 
 
+def submit_stream(q, reqs, root_flags=bp.BP_NO_EARLY_EXIT, child_flags=bp.BP_NO_EARLY_EXIT, with_instance=False,
+                  wave=None, results=None):
+    """Roots as partial packings, children as (parent ticket, commits); with
+    `wave`, the results of each wave of that many requests are drained into
+    `results` before the next wave goes in."""
+    tickets, by_ticket = {}, {}
+    for i, r in enumerate(reqs):
+        if wave and i and i % wave == 0:
+            results.update(drain(q, wave))
+        if r.parent < 0 or r.parent not in tickets:
+            t = q.submit(r.C, r.residual, r.unpacked, tag=i, flags=root_flags)
+        else:
+            kw = dict(residual=r.residual, unpacked=r.unpacked) if with_instance else {}
+            t = q.submit_child(r.C, len(r.residual), tickets[r.parent], r.commits, tag=i, flags=child_flags, **kw)
+        tickets[i] = t
+        by_ticket[t] = i
+    return tickets, by_ticket
+
+
+def check_against_full_path(ctx, reqs, res, by_ticket, what):
+    for t, got in res.items():
+        i = by_ticket[t]
+        r = reqs[i]
+        assert got.status == 0, (what, i, got.status)
+        alone = ctx.feasible(r.C, r.residual, r.unpacked, flags=bp.BP_NO_EARLY_EXIT)
+        assert fields(got.bounds) == (list(alone["value"]), list(alone["argmax"]), alone["lb"], alone["lb_arg"],
+                                      alone["verdict"], alone["r"], 0), (what, i, got.from_parent)
+        assert got.bounds.evals == alone["evals"]
+
+
+def test_child_requests_from_parent_sums(ctx):
+    # children submitted as (parent ticket, commits) without their instances:
+    # every record equals the full check of the node, and the oracle's on a sample
+    for seed, rate in ((3, 20_000.0), (4, 200_000.0)):
+        reqs = W.dfs_requests(seed, rate=rate, duration=1.0, max_requests=240)
+        say("served children from parent sums, seed", seed)
+        q = bp.Queue(ctx, 8 << 30, 4096)
+        tickets, by_ticket = submit_stream(q, reqs)
+        res = drain(q, len(reqs))
+        st = q.stats()
+        q.close()
+        assert st["from_parent"] > len(reqs) // 2, st
+        assert st["from_parent"] + st["full_sweeps"] == len(reqs)
+        check_against_full_path(ctx, reqs, res, by_ticket, ("seed", seed))
+        by_index = {by_ticket[t]: g for t, g in res.items()}
+        # the oracle on every 10th request
+        idx = list(range(0, len(reqs), 10))
+        want = O.bounds_many([(reqs[i].C, len(reqs[i].residual), O.residual_reduce(reqs[i].C, reqs[i].residual,
+                                                                                   reqs[i].unpacked)) for i in idx],
+                             threads=oracle_par.pool_threads(), l2_dense=True)
+        for i, w in zip(idx, want):
+            got = by_index[i]
+            assert list(got.bounds.value) == w["value"].tolist(), i
+            assert list(got.bounds.argmax_lambda) == w["argmax"].tolist(), i
+            assert (got.lb, got.bounds.lb_arg, got.verdict) == (w["lb"], w["lb_arg"], w["verdict"]), i
+        # a child computed from sums did O(P) work per changed item
+        kids = [g for g in res.values() if g.from_parent]
+        assert kids and all(0 <= g.bounds.evals_done < g.bounds.evals for g in kids)
+
+
+def test_child_requests_with_evictions_and_early_exit_roots(ctx):
+    # a 16 MiB budget keeps a few dozen node states (C = 10 000): evicted
+    # ancestors send children to the full sweeps on instances rebuilt from
+    # the commits; roots with early exit are bases only once they finished
+    reqs = W.dfs_requests(3, rate=200_000.0, duration=1.0, max_requests=320)
+    for root_flags in (bp.BP_NO_EARLY_EXIT, 0):
+        say("served children, small budget, root flags", root_flags)
+        q = bp.Queue(ctx, 16 << 20, 4096)
+        res = {}
+        tickets, by_ticket = submit_stream(q, reqs, root_flags=root_flags, wave=40, results=res)
+        res.update(drain(q, len(reqs) - len(res)))
+        st = q.stats()
+        q.close()
+        assert st["node_evictions"] > 0 and st["from_parent"] > 0, st
+        assert st["completed"] == len(reqs) == len(res)
+        check_against_full_path(ctx, reqs, res, by_ticket, ("small budget", root_flags))
+
+
+def test_child_request_errors(ctx):
+    C, m, res, unp = W.small_partial_packing(seed=3)
+    q = bp.Queue(ctx, 64 << 20, 64)
+    say("served child errors")
+    root = q.submit(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+    w = int(unp[0])
+    fits = [j for j in range(m) if res[j] >= w]
+    with pytest.raises(bp.BpError) as e:
+        q.submit_child(C, m, 10**12, [(w, fits[0])])
+    assert e.value.status == bp.BP_ERR_STATE
+    with pytest.raises(bp.BpError) as e:
+        q.submit_child(C, m, root, [(w, m)])
+    assert e.value.status == bp.BP_ERR_RANGE
+    full = [j for j in range(m) if res[j] < w]
+    if full:
+        with pytest.raises(bp.BpError) as e:
+            q.submit_child(C, m, root, [(w, full[0])])
+        assert e.value.status == bp.BP_ERR_RANGE
+    with pytest.raises(bp.BpError) as e:
+        q.submit_child(C, m + 1, root, [(w, fits[0])])
+    assert e.value.status == bp.BP_ERR_ARG
+    kid = q.submit_child(C, m, root, [(w, fits[0])], flags=bp.BP_NO_EARLY_EXIT)
+    out = drain(q, 2)
+    q.close()
+    res2 = res.copy()
+    res2[fits[0]] -= w
+    unp2 = list(unp)
+    unp2.remove(w)
+    want = O.bounds(C, m, O.residual_reduce(C, res2, unp2), l2_dense=True)
+    assert list(out[kid].bounds.value) == want["value"].tolist()
+    assert list(out[kid].bounds.argmax_lambda) == want["argmax"].tolist()
+
+
 def test_admission_limits(ctx):
     C, m, res, unp = W.large_residual(1)
-    q = bp.Queue(ctx, 1000, 4)
-    say("request larger than the budget")
+    with pytest.raises(bp.BpError) as e:
+        bp.Queue(ctx, 1000, 4)  # below the 1 MiB minimum
+    assert e.value.status == bp.BP_ERR_ARG
+    q = bp.Queue(ctx, 4 << 20, 4)
+    say("request larger than the budget's admission share")
     with pytest.raises(bp.BpError) as e:
         q.submit(C, res, unp)
     assert e.value.status == bp.BP_ERR_LIMIT
