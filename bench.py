@@ -642,10 +642,12 @@ def main():
         log("batched leg done")
     if not args.no_served:
         line["served"] = []
-        for flags in ((0,) if args.no_segments else (0, bp.BP_SEGMENTS)):
-            for rate, seed in ((20_000.0, 3), (200_000.0, 4)):
-                line["served"].append(bench_served(bp, W, ctx, rate, args.served_seconds, seed, flags=flags))
-                log(f"served leg at {rate:.0f}/s (flags {flags}) done")
+        legs = [(0, 20_000.0, 3), (0, 200_000.0, 4)]
+        if not args.no_segments:
+            legs.append((bp.BP_SEGMENTS, 200_000.0, 4))  # the roots' sweeps in segment form
+        for flags, rate, seed in legs:
+            line["served"].append(bench_served(bp, W, ctx, rate, args.served_seconds, seed, flags=flags))
+            log(f"served leg at {rate:.0f}/s (flags {flags}) done")
     if not args.no_cpu_baseline:
         import oracle as O
         items = O.residual_reduce(C, residual, unpacked)

@@ -90,7 +90,7 @@ struct InstState {
   int32_t maxw;
   int32_t status;    // BP_OK or an error found on the device
   int32_t pad;
-  unsigned long long evals_done;  // (item, parameter) evaluations of the tiles that ran
+  unsigned long long evals_skipped;  // (item, parameter) evaluations of the tiles an early exit skipped
 };
 
 // One (instance, bound) entry of the sweep schedule.  Its parameter range is

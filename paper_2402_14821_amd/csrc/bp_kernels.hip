@@ -554,7 +554,7 @@ __device__ void prep_finish(const LaunchDesc &d, int64_t inst) {
     if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
   }
   for (int b = 0; b < kNB; ++b) d.keys[inst * kNB + b] = 0ull;
-  st->evals_done = 0ull;
+  st->evals_skipped = 0ull;
   int refuted = 0;
   if ((p.flags & kPlanEarlyExit) && st->status == BP_OK && r > 0) {
     const int64_t l1 = (st->sumW + p.C - 1) / p.C;
@@ -1146,12 +1146,21 @@ __device__ __forceinline__ void store_state_lanes(int bound, const TileArgs &t, 
     if (lam[j] >= t.lo && lam[j] <= t.hi) store_state(bound, t, lam[j], part[j]);
 }
 
-// Parameters of a tile inside the bound's range (for the executed-work count).
+// Parameters of the range [lo, hi] inside [a, b].
+__device__ __forceinline__ int64_t overlap(int64_t a, int64_t b, int64_t lo, int64_t hi) {
+  const int64_t x = max(a, lo), y = min(b, hi);
+  return y >= x ? y - x + 1 : 0;
+}
+
+// Parameters of the bound's range a tile of entry e evaluates (a mirrored
+// VB2 tile: its dense half's lambdas and their mirrors c - lambda), for the
+// count of skipped work.
 template <int LPL>
-__device__ __forceinline__ uint32_t lanes_in_range(const TileArgs &t, const int64_t lam[LPL]) {
-  uint32_t n = 0;
-  for (int j = 0; j < LPL; ++j) n += (uint32_t)__popcll(ballot64(lam[j] >= t.lo && lam[j] <= t.hi));
-  return n;
+__device__ __forceinline__ int64_t tile_params(int32_t mode, int32_t aux, const TileArgs &t, int64_t lam0) {
+  const int64_t lam1 = lam0 + 64 * LPL - 1;
+  if (mode != kModeMirror) return overlap(lam0, lam1, t.lo, t.hi);
+  const int64_t b = min(lam1, (int64_t)aux);
+  return overlap(lam0, b, t.lo, t.hi) + overlap(lam0, b, (int64_t)t.C - t.hi, (int64_t)t.C - t.lo);
 }
 
 // L2 (Sec. 3.1) evaluated at the parameters where it can change: the range's
@@ -1395,13 +1404,21 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   // a split BJ1/CCM1 segment tile divides its q range instead
   t.qc = chunk;
   t.qn = nch;
-  // its share of the r reduced items, for the executed-work count (the
-  // shares of a tile's chunks add up to r)
-  const uint64_t share = (uint64_t)((int64_t)t.r * (chunk + 1) / nch - (int64_t)t.r * chunk / nch);
-  uint64_t done = 0;
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
-    if (early && refuted_now(d, inst)) break;
+    if (early && refuted_now(d, inst)) {
+      if (bound != kL2) {
+        // the work left out: this chunk's share of the r items (the shares
+        // of a tile's chunks add up to r) for each remaining tile's parameters
+        const uint32_t r32 = (uint32_t)t.r;
+        const uint64_t share = (uint64_t)(r32 * (uint32_t)(chunk + 1) / (uint32_t)nch - r32 * (uint32_t)chunk / (uint32_t)nch);
+        uint64_t skipped = 0;
+        for (int64_t u = tl; u < tile1; ++u)
+          skipped += (uint64_t)tile_params<LPL>(e.mode, e.aux, t, e.lam0 + u * (64 * LPL)) * share;
+        if (skipped && lane_id() == 0) atomicAdd(&d.state[inst].evals_skipped, (unsigned long long)skipped);
+      }
+      return;
+    }
     t.lam0 = e.lam0 + tl * (64 * LPL);
     int64_t lam[LPL], lbp[LPL];
     bool ok[LPL];
@@ -1415,7 +1432,7 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       flush_tile<LPL>(d, inst, kL2, t, lam, lbp, ok, early);
       continue;
     }
-    if (t.lam0 > t.hi) break;
+    if (t.lam0 > t.hi) return;
     // the dense half of a mirrored VB2 entry runs over [1, aux]
     TileArgs tv = t;
     if (e.mode == kModeMirror) {
@@ -1438,17 +1455,6 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       case kVB2: part_vb2<LPL>(tv, l32, part); break;
       default: part_bj1<LPL>(t, l32, part); break;
     }
-    if (e.mode == kModeMirror) {
-      // each dense lambda of the half also stands for c - lambda
-      int64_t own[LPL], mir[LPL];
-      for (int j = 0; j < LPL; ++j) {
-        own[j] = lam[j] <= e.aux ? lam[j] : -1;
-        mir[j] = lam[j] <= e.aux ? t.C - lam[j] : -1;
-      }
-      done += (uint64_t)(lanes_in_range<LPL>(t, own) + lanes_in_range<LPL>(t, mir)) * share;
-    } else {
-      done += (uint64_t)lanes_in_range<LPL>(t, lam) * share;
-    }
     if (nch > 1) {
       // A chunk of a split tile: store its partial sums in its own slot (no
       // other wave touches it) and move on; the combine kernel adds the
@@ -1469,7 +1475,6 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
     }
     flush_tile<LPL>(d, inst, bound, t, lam, lbp, ok, early);
   }
-  if (done && lane_id() == 0) atomicAdd(&d.state[inst].evals_done, (unsigned long long)done);
 }
 
 // Split tiles, in segments of kSegTiles consecutive tiles of one entry: a
@@ -1605,7 +1610,7 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__
       if (b >= kMT && st.hiEff[b] >= p.lo[b]) P += st.hiEff[b] - p.lo[b] + 1;
     }
     o.evals = (int64_t)st.r * P;
-    o.evals_done = (int64_t)st.evals_done;
+    o.evals_done = o.evals - (int64_t)st.evals_skipped;
     if (st.status == BP_OK) {
       o.value[kL1] = (st.sumW + p.C - 1) / p.C;
       for (int b = kL2; b < kNB; ++b) {

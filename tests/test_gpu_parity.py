@@ -113,8 +113,10 @@ def test_small_partial_packings(ctx):
         got = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
         same(got, want, ("cfg1", seed))
         assert got["r"] == len(items)
+        assert got["evals_done"] == got["evals"] == len(items) * 563  # P(150) = 563
         early = ctx.feasible(C, res, unp)
         assert early["verdict"] == want["verdict"]
+        assert 0 <= early["evals_done"] <= early["evals"]
         if want["verdict"] == 0:
             assert early["lb"] > m
 
@@ -128,7 +130,12 @@ def test_small_partial_packings_tight_bins(ctx):
         say("tight config-1 seed", seed)
         got = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
         same(got, want, ("tight", seed))
-        assert ctx.feasible(C, res, unp)["verdict"] == want["verdict"]
+        early = ctx.feasible(C, res, unp)
+        assert early["verdict"] == want["verdict"]
+        if early["early_exit"]:
+            assert early["evals_done"] < early["evals"]
+            if O.l1(C, items) > m:  # refuted before any sweep ran
+                assert early["evals_done"] == 0
 
 
 def test_large_residual_instance_full(ctx):
