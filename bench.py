@@ -130,6 +130,36 @@ def host_cpu():
     return {"nproc": os.cpu_count() or 1, "affinity": aff, "model": model}
 
 
+def plain_latency(bp, W, ctx, checks: int):
+    """Plain single-check latency on the small partial packing (host in, host
+    out): one bp_feasible call through ctypes with its arguments marshalled
+    beforehand, so the figure is the library call and not numpy conversions.
+    Returns the per-call microseconds."""
+    import ctypes
+
+    import numpy as np
+
+    lib = bp.load()
+    lat = []
+    smalls = []
+    for s in range(64):
+        Cs, ms_, rs, us = W.small_partial_packing(seed=s)
+        rs = np.ascontiguousarray(rs, dtype=np.int32)
+        us = np.ascontiguousarray(us, dtype=np.int32)
+        smalls.append((Cs, len(rs), rs.ctypes.data_as(bp._P32), us.ctypes.data_as(bp._P32), len(us), rs, us))
+    v32, lb64, rec_small = ctypes.c_int32(0), ctypes.c_int64(0), bp.bp_bounds()
+    pv, plb, prec = ctypes.byref(v32), ctypes.byref(lb64), ctypes.byref(rec_small)
+    fz = lib.bp_feasible
+    for i in range(checks):
+        Cs, ms_, prs, pus, nus, _, _ = smalls[i % len(smalls)]
+        t1 = time.perf_counter()
+        st = fz(ctx.handle, Cs, ms_, prs, pus, nus, 0, pv, plb, prec)
+        lat.append((time.perf_counter() - t1) * 1e6)
+        if st != 0:
+            raise bp.BpError(st, lib.bp_last_error().decode())
+    return lat
+
+
 def valu_rates(blocks_per_cu: int = 8, iters: int = 4000, reps: int = 3):
     """Issue rate of each opcode of the sweep's inner loops, measured by the
     microbenchmark library (hand-written gfx950 kernels, one opcode each on
@@ -461,6 +491,8 @@ def main():
     ap.add_argument("--no-segments", action="store_true",
                     help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
     ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--latency-only", action="store_true",
+                    help="only time the plain small checks (--latency-checks of them) and exit")
     ap.add_argument("--valu-rates", action="store_true",
                     help="only measure the VALU issue rate of each inner-loop opcode and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -490,6 +522,14 @@ def main():
 
     import paper_2402_14821_amd as bp
     from paper_2402_14821_amd import workloads as W
+
+    if args.latency_only:
+        with bp.Context(0) as lctx:
+            plain_latency(bp, W, lctx, 200)  # warm-up
+            lat = plain_latency(bp, W, lctx, args.latency_checks)
+        print(json.dumps({"plain_small_check_us": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                                                   "n": len(lat)}}), flush=True)
+        return
 
     if args.per_bound:
         with bp.Context(0) as pctx:
@@ -582,28 +622,7 @@ def main():
     traffic = load_traffic("k_sweep")
     valu_insts = load_valu_insts("k_sweep")
 
-    # plain single-check latency on the small partial packing (host in, host
-    # out): one bp_feasible call through ctypes with its arguments marshalled
-    # beforehand, so the figure is the library call and not numpy conversions
-    import ctypes
-    lib = bp.load()
-    lat = []
-    smalls = []
-    for s in range(64):
-        Cs, ms_, rs, us = W.small_partial_packing(seed=s)
-        rs = np.ascontiguousarray(rs, dtype=np.int32)
-        us = np.ascontiguousarray(us, dtype=np.int32)
-        smalls.append((Cs, len(rs), rs.ctypes.data_as(bp._P32), us.ctypes.data_as(bp._P32), len(us), rs, us))
-    v32, lb64, rec_small = ctypes.c_int32(0), ctypes.c_int64(0), bp.bp_bounds()
-    pv, plb, prec = ctypes.byref(v32), ctypes.byref(lb64), ctypes.byref(rec_small)
-    fz = lib.bp_feasible
-    for i in range(args.latency_checks):
-        Cs, ms_, prs, pus, nus, _, _ = smalls[i % len(smalls)]
-        t1 = time.perf_counter()
-        st = fz(ctx.handle, Cs, ms_, prs, pus, nus, 0, pv, plb, prec)
-        lat.append((time.perf_counter() - t1) * 1e6)
-        if st != 0:
-            raise bp.BpError(st, lib.bp_last_error().decode())
+    lat = plain_latency(bp, W, ctx, args.latency_checks)
 
     line = {
         "metric": "(item x param) bound evals/s + feasibility checks/s, batched vs plain; p99 us",

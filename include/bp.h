@@ -362,9 +362,11 @@ bp_status bp_queue_destroy(bp_queue *q);
  * plain integer division: every divisor d in [d_lo, d_hi] with numerators
  * n in [0, n_hi] (and the extreme numerators).  mode 0: floor(n / d) for
  * n < 2^31; mode 1: ceil(a lam / c) - 1 (f_VB2's quotient), d taken as c;
- * mode 2: the divisibility test d | n.  d_lo >= 1, d_hi < 2^31, n_hi < 2^31,
- * else BP_ERR_ARG (also for any other mode).  Returns the number of
- * mismatches found (0 = all exact) or a negative status. */
+ * mode 2: the divisibility test d | n; mode 3: floor(n / d) through an fp64
+ * reciprocal and one correction step; mode 4: floor((a lam - 1) / c) the
+ * same way, d taken as c.  d_lo >= 1, d_hi < 2^31, n_hi < 2^31, else
+ * BP_ERR_ARG (also for any other mode).  Returns the number of mismatches
+ * found (0 = all exact) or a negative status. */
 int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32_t mode);
 
 #ifdef __cplusplus

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -233,6 +234,18 @@ bp_status Ctx::init(int dev) {
   grid_fin = 64;
   const char *ng = getenv("BP_NO_GRAPH");
   use_graph = !(ng && ng[0] == '1');
+  const char *ns = getenv("BP_NO_SMALL_PATH");
+  small_path = !(ns && ns[0] == '1');
+  {
+    const hipError_t e = hipHostMalloc(&small_out, sizeof(bp_bounds) + 64, hipHostMallocCoherent);
+    if (e != hipSuccess) {
+      small_out = nullptr;
+      return fail(BP_ERR_NOMEM, "hipHostMalloc (coherent, %zu): %s", sizeof(bp_bounds) + 64, hipGetErrorString(e));
+    }
+    memset(small_out, 0, sizeof(bp_bounds) + 64);
+  }
+  if ((st = small_keys.reserve(sizeof(unsigned long long) * (kNB + 1)))) return st;
+  HIP_TRY(hipMemset(small_keys.p, 0, sizeof(unsigned long long) * (kNB + 1)));
   // BP_SEGMENT_KCUT=K: segment tiles of BJ1 wherever floor(c / lambda) <= K
   // (0 .. 64) instead of where the cost model puts the cut; same results.
   const char *kc = getenv("BP_SEGMENT_KCUT");
@@ -246,9 +259,11 @@ void Ctx::destroy() {
   if (last_run && any_run) (void)hipEventSynchronize(last_run);
   drop_graphs();
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
-                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf})
+                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf, &small_keys})
     b->release();
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
+  if (small_out) (void)hipHostFree(small_out);
+  small_out = nullptr;
   if (staged) (void)hipEventDestroy(staged);
   if (done) (void)hipEventDestroy(done);
   if (last_run) (void)hipEventDestroy(last_run);
@@ -1020,6 +1035,63 @@ bp_status host_validate_items(int32_t C, const int32_t *items, int64_t r) {
 
 }  // namespace bpi
 
+namespace bpi {
+
+// The one-launch path for small checks: the instance goes in the kernel's
+// arguments and the record comes back in host memory, so a check costs one
+// launch and one wait.  *done is false when the instance is too large for it.
+bp_status run_small(Ctx *c, const PlanIn &q, const int32_t *sizes, const int32_t *residual, bp_bounds *out,
+                    bool *done) {
+  *done = false;
+  if (!c->small_path) return BP_OK;
+  const int64_t nv = q.n_in + (q.form == kFormResidual ? q.m_res : 0);
+  if (nv > kSmallFusedMax) return BP_OK;
+  int64_t params = 0;  // L2 and the six functions, before any VB2 cut
+  for (int b = kL2; b < kNB; ++b) params += q.lo[b] <= q.hi[b] ? q.hi[b] - q.lo[b] + 1 : 0;
+  if (params * std::max<int64_t>(nv, 1) > kSmallFusedWork) return BP_OK;
+  SmallArgs a;
+  memset(&a, 0, offsetof(SmallArgs, v));
+  a.C = q.C;
+  a.m = q.form == kFormResidual ? q.m_res : 0;
+  a.n = (int32_t)q.n_in;
+  a.form = q.form;
+  a.k = q.k;
+  for (int b = 0; b < kNB; ++b) {
+    a.lo[b] = q.lo[b];
+    a.hi[b] = q.hi[b];
+  }
+  a.clamp = q.clamp ? 1u : 0u;
+  // about eight items per lane
+  a.slices = 1;
+  while (a.slices < 64 && (int64_t)a.slices * 8 < nv) a.slices <<= 1;
+  if (q.n_in) memcpy(a.v, sizes, sizeof(int32_t) * (size_t)q.n_in);
+  if (a.m) memcpy(a.v + q.n_in, residual, sizeof(int32_t) * (size_t)a.m);
+  bp_bounds *h = (bp_bounds *)c->small_out;
+  uint32_t *seq = (uint32_t *)((char *)c->small_out + sizeof(bp_bounds));
+  const uint32_t want = ++c->small_seq;
+  const int grid = (int)std::min<int64_t>(
+      kSmallFusedMaxGrid, std::max<int64_t>(1, (params * a.slices + kSmallFusedThreads - 1) / kSmallFusedThreads));
+  HIP_TRY(launch_small_check(a, grid, (unsigned long long *)c->small_keys.p, h, seq, want, c->stream));
+  // Wait for the kernel's sequence number in host memory; after two seconds
+  // without it, let the stream report what went wrong.
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0;; ++spin) {
+    if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) break;
+    if ((spin & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) break;
+      return fail(BP_ERR_DEVICE, "the small check did not report its record");
+    }
+  }
+  *out = *h;
+  *done = true;
+  if (out->status == BP_ERR_RANGE) return fail(BP_ERR_RANGE, "size or residual outside [0, C]");
+  if (out->status) return fail(out->status, "device status %d", out->status);
+  return BP_OK;
+}
+
+}  // namespace bpi
+
 bp_status bp_lower_bounds(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *items, int64_t r, const bp_sweep *sweep,
                           bp_bounds *out) {
   Ctx *c;
@@ -1029,6 +1101,8 @@ bp_status bp_lower_bounds(bp_ctx *ctx, int32_t C, int32_t k, const int32_t *item
   std::vector<PlanIn> pin(1);
   if ((st = make_plan_in(C, k, r, 0, kFormItems, sweep, false, &pin[0]))) return st;
   if ((st = host_validate_items(C, items, r))) return st;
+  bool done = false;
+  if ((st = run_small(c, pin[0], items, nullptr, out, &done)) || done) return st;
   return run_host_batch(c, pin, {items}, {nullptr}, out);
 }
 
@@ -1061,7 +1135,9 @@ bp_status bp_feasible(bp_ctx *ctx, int32_t C, int32_t m, const int32_t *residual
   if ((st = host_validate_items(C, unpacked, n))) return st;
   if ((st = host_validate_items(C, residual, m))) return st;
   bp_bounds o;
-  if ((st = run_host_batch(c, pin, {unpacked}, {residual}, &o))) return st;
+  bool done = false;
+  if ((st = run_small(c, pin[0], unpacked, residual, &o, &done))) return st;
+  if (!done && (st = run_host_batch(c, pin, {unpacked}, {residual}, &o))) return st;
   if (verdict) *verdict = o.verdict;
   if (lb) *lb = o.lb;
   if (bounds) *bounds = o;
@@ -1394,6 +1470,49 @@ int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32
       for (uint64_t t = 0; t <= 4; ++t) {
         one(q * d + t - 2);
         one(0x7fffffffull - t);
+      }
+    }
+  } else if (mode == 3) {
+    // floor(n / d) by family (4): every d in [d_lo, d_hi], n in [0, n_hi], around multiples of d and below 2^31
+    for (uint64_t d = d_lo; d <= d_hi; ++d) {
+      const double rd = 1.0 / (double)d;
+      auto one = [&](uint64_t n) {
+        if (n >= 0x80000000ull) return;
+        if (fdiv_u31((uint32_t)n, (uint32_t)d, rd) != (uint32_t)(n / d)) ++bad;
+      };
+      for (uint64_t n = 0; n <= n_hi; ++n) one(n);
+      for (uint64_t k = 1; k <= 64; ++k) {
+        one(d * k - 1);
+        one(d * k);
+        one(d * k + 1);
+      }
+      const uint64_t q = 0x7fffffffull / d;
+      for (uint64_t t = 0; t <= 4; ++t) {
+        one(q * d + t - 2);
+        one(0x7fffffffull - t);
+      }
+    }
+  } else if (mode == 4) {
+    // floor(N / c) by family (4) for N = a lam - 1 < c^2: c in [d_lo, d_hi], lam and a near 1, near c and
+    // where a lam is a multiple of c or one off
+    for (uint64_t c = d_lo; c <= d_hi; ++c) {
+      const double rc = 1.0 / (double)c;
+      auto one = [&](uint64_t a, uint64_t lam) {
+        if (a < 1 || a > c || lam < 1 || lam > c) return;
+        const int64_t N = (int64_t)(a * lam) - 1;
+        if (fdiv_u62(N, (int64_t)c, rc) != N / (int64_t)c) ++bad;
+      };
+      const uint64_t lams[] = {1, 2, 3, c / 3 + 1, c / 2, c / 2 + 1, c - 2, c - 1, c};
+      for (uint64_t lam : lams) {
+        if (lam < 1 || lam > c) continue;
+        for (uint64_t a = 1; a <= std::min<uint64_t>(c, n_hi); ++a) one(a, lam);
+        for (uint64_t a = c > 64 ? c - 64 : 1; a <= c; ++a) one(a, lam);
+        for (uint64_t k = 1; k <= 64; ++k) {
+          const uint64_t a = (k * c) / lam;
+          one(a, lam);
+          one(a + 1, lam);
+          if (a > 1) one(a - 1, lam);
+        }
       }
     }
   } else {

@@ -26,6 +26,8 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_pre
                                  hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
                              long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s);
+hipError_t launch_small_check(const SmallArgs &a, int grid, unsigned long long *gkeys, bp_bounds *out,
+                              uint32_t *seq_out, uint32_t seq, hipStream_t s);
 hipError_t noalloc_scratch(int device, unsigned char **out);
 hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
                           int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
@@ -118,6 +120,12 @@ struct Ctx {
   DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, out_buf,
       red_buf, bidx_buf, dcnt_buf;
   HostBuf stage_host, in_host, out_host, red_host;
+  // The one-launch small check writes its record, then its sequence number,
+  // to this coherent host memory: [bp_bounds][uint32 sequence].
+  void *small_out = nullptr;
+  uint32_t small_seq = 0;
+  DevBuf small_keys;  // the small check's maxima and workgroup count, zero between calls
+  bool small_path = true;  // BP_NO_SMALL_PATH=1 at context creation turns the one-launch path off
 
   bp_status init(int dev);
   void destroy();
@@ -135,6 +143,8 @@ struct Ctx {
   bp_status timing_mean(double ms[3], int64_t *runs);
 };
 
+bp_status run_small(Ctx *c, const PlanIn &q, const int32_t *sizes, const int32_t *residual, bp_bounds *out,
+                    bool *done);
 bp_status make_plan_in(int32_t C, int64_t k, int64_t n_in, int32_t m_res, int32_t form, const bp_sweep *sw,
                        bool early, PlanIn *q, bool segments = false);
 bp_status host_validate_items(int32_t C, const int32_t *items, int64_t r);

@@ -92,6 +92,31 @@ __host__ __device__ inline uint32_t vb2_part(uint32_t a, uint32_t r_lo, uint32_t
   return (uint32_t)(s >> 32);
 }
 
+// (4) Floors through an fp64 reciprocal, for per-lane divisors with no
+//     precomputed constant.  For 0 <= n < 2^31 and 1 <= d < 2^31 the product
+//     n * fl(1/d) (two roundings, relative error below 2^-52) is within
+//     2^31 * 2^-52 < 1 of n / d, so its truncation is floor(n / d) or one
+//     off, and the exact integer remainder n - q d moves it back.  The 62-bit
+//     form takes N < c^2 (N = a lambda - 1 with a, lambda <= c < 2^31): the
+//     quotient is below 2^31, N's own rounding to 53 bits and the two others
+//     keep the estimate within 2^31 * 3 2^-53 < 1, and one step of the
+//     correction loops suffices.
+__host__ __device__ inline uint32_t fdiv_u31(uint32_t n, uint32_t d, double rd) {
+  uint32_t q = (uint32_t)((double)n * rd);
+  const int64_t r = (int64_t)n - (int64_t)q * d;
+  if (r < 0) --q;
+  else if (r >= (int64_t)d) ++q;
+  return q;
+}
+
+__host__ __device__ inline int64_t fdiv_u62(int64_t N, int64_t c, double rc) {
+  int64_t q = (int64_t)((double)N * rc);
+  int64_t r = N - q * c;
+  while (r < 0) { --q; r += c; }
+  while (r >= c) { ++q; r -= c; }
+  return q;
+}
+
 // Constant of family (3) for divisor d in [1, 2^31): ceil(2^64 / d) mod 2^64.
 __host__ __device__ inline uint64_t divides_const(uint32_t d) { return ~0ull / d + 1ull; }
 

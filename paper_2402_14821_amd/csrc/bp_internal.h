@@ -215,6 +215,28 @@ __host__ __device__ inline int64_t node_tiles(int32_t C) {
   return n;
 }
 
+// Small checks in one launch (k_small_check): the instance travels in the
+// kernel arguments, one workgroup computes the whole record and writes it to
+// host memory.  Used for at most kSmallFusedMax input values and at most
+// kSmallFusedWork (item, parameter) evaluations.
+constexpr int kSmallFusedMax = 960;
+constexpr int64_t kSmallFusedWork = int64_t(1) << 18;
+constexpr int kSmallFusedThreads = 256;  // per workgroup; one parameter per thread, as many workgroups as needed
+constexpr int kSmallFusedMaxGrid = 256;
+struct SmallArgs {
+  int32_t C;
+  int32_t m;       // residual form: bins given as residuals (after the n sizes)
+  int32_t n;       // sizes
+  int32_t form;    // kFormResidual or kFormItems
+  int64_t k;
+  int64_t lo[kNB];
+  int64_t hi[kNB];
+  uint32_t clamp;  // the paper's VB2 cut
+  int32_t slices;  // lanes per (bound, parameter) pair: a power of two, 1 .. 64
+  int32_t v[kSmallFusedMax];  // the n sizes, then (residual form) the m residuals
+};
+static_assert(sizeof(SmallArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
 // Allocation-free check (bp_feasible_dev_noalloc): the tables and every
 // workspace of a one-instance launch inside one file-scope device array per
 // GPU, at the fixed offsets below.  The rest of the array holds the partial

@@ -1645,29 +1645,24 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__
 // Per-lane constants of one parameter lambda.
 struct LamConst {
   uint32_t lam, K, p;   // lambda, floor(c / lambda), c mod lambda
-  MagicU31 g;           // division by lambda (family (1) of bp_divide.h)
-  uint32_t rlo, rhi;    // VB2 reciprocal (family (2))
+  double rl;            // 1 / lambda
 };
 
-__device__ __forceinline__ LamConst lam_const(int bound, uint32_t C, uint32_t lam) {
+__device__ __forceinline__ LamConst lam_const(uint32_t C, uint32_t lam) {
   LamConst k;
   k.lam = lam;
-  k.K = lam ? C / lam : 0;
+  k.rl = 1.0 / (double)(lam ? lam : 1u);
+  k.K = lam ? fdiv_u31(C, lam, k.rl) : 0;
   k.p = lam ? C - k.K * lam : 0;
-  k.g = magic_u31(lam ? lam : 1u);
-  k.rlo = k.rhi = 0;
-  if (bound == kVB2) {
-    const uint64_t R = vb2_recip(lam, C);
-    k.rlo = (uint32_t)R;
-    k.rhi = (uint32_t)(R >> 32);
-  }
   return k;
 }
 
-// f(w, lambda) for 0 <= w <= c, lambda in the function's range (Sec. 3.1).
-__device__ __forceinline__ int64_t dff_term(int bound, uint32_t C, uint32_t w, const LamConst &k) {
+// f(w, lambda) for 0 <= w <= c, lambda in the function's range (Sec. 3.1);
+// rc = 1 / c.
+template <int BOUND>
+__device__ __forceinline__ int64_t dff_term_b(uint32_t C, uint32_t w, const LamConst &k, double rc) {
   const uint32_t lam = k.lam;
-  switch (bound) {
+  switch (BOUND) {
     case kMT:  // c if w > c - lambda; w if lambda <= w <= c - lambda; 0 if w < lambda
       if (w > C - lam) return C;
       return w >= lam ? (int64_t)w : 0;
@@ -1676,28 +1671,44 @@ __device__ __forceinline__ int64_t dff_term(int bound, uint32_t C, uint32_t w, c
       if (w <= C - 2 * lam) return C / 3;
       if (w < 2 * lam) return C / 2;
       return (int64_t)C - (C - w >= lam ? (int64_t)(C / 3) : 0);
-    case kFS1: {  // w lambda if c divides w (lambda + 1), else floor(w (lambda + 1) / c) c
-      const uint64_t n = (uint64_t)w * (lam + 1u);
-      const uint64_t q = n / C;
-      return q * C == n ? (int64_t)w * lam : (int64_t)(q * C);
+    case kFS1: {  // w lambda if c divides n = w (lambda + 1), else floor(n / c) c
+      // n < 2^38: q = floor((n + 0.5) / c) from the fp64 product is exact (the
+      // relative error 2^-52 stays below the distance 0.5 / c to an integer),
+      // and fma(-q, c, n) is the exact remainder
+      const double n = (double)w * (double)(lam + 1u);
+      const double q = floor((n + 0.5) * rc);
+      const double rem = fma(-q, (double)C, n);
+      return rem == 0.0 ? (int64_t)w * lam : (int64_t)q * C;
     }
     case kCCM1:  // 2 K - 2 floor((c - w) / lambda) | K | 2 floor(w / lambda)
-      if (2ull * w > C) return 2 * ((int64_t)k.K - (int64_t)div_u31(2u * (C - w), k.g.m, k.g.s));
+      if (2ull * w > C) return 2 * ((int64_t)k.K - (int64_t)fdiv_u31(C - w, lam, k.rl));
       if (2ull * w == C) return k.K;
-      return 2 * (int64_t)div_u31(2u * w, k.g.m, k.g.s);
-    case kVB2: {  // with h(a) = max(0, ceil(a lambda / c) - 1): 2 (lambda - 1) - 2 h(c - w) | lambda - 1 | 2 h(w)
+      return 2 * (int64_t)fdiv_u31(w, lam, k.rl);
+    case kVB2: {  // with h(a) = max(0, ceil(a lambda / c) - 1) = floor((a lambda - 1) / c) for a >= 1:
+                  // 2 (lambda - 1) - 2 h(c - w) | lambda - 1 | 2 h(w)
       if (2ull * w > C) {
-        const uint32_t a = C - w;
-        return 2 * ((int64_t)lam - 1) - 2 * (int64_t)(a ? vb2_part(a, k.rlo, k.rhi) : 0u);
+        const int64_t a = C - w;
+        return 2 * ((int64_t)lam - 1) - 2 * (a ? fdiv_u62(a * lam - 1, C, rc) : 0);
       }
       if (2ull * w == C) return (int64_t)lam - 1;
-      return 2 * (int64_t)(w ? vb2_part(w, k.rlo, k.rhi) : 0u);
+      return 2 * (w ? fdiv_u62((int64_t)w * lam - 1, C, rc) : 0);
     }
     default: {  // BJ1: floor(w / lambda) (lambda - p) + max(0, (w mod lambda) - p)
-      const uint32_t q = div_u31(2u * w, k.g.m, k.g.s);
+      const uint32_t q = fdiv_u31(w, lam, k.rl);
       const uint32_t rem = w - q * lam;
       return (int64_t)q * (lam - k.p) + (rem > k.p ? (int64_t)(rem - k.p) : 0);
     }
+  }
+}
+
+__device__ __forceinline__ int64_t dff_term(int bound, uint32_t C, uint32_t w, const LamConst &k, double rc) {
+  switch (bound) {
+    case kMT: return dff_term_b<kMT>(C, w, k, rc);
+    case kRAD2: return dff_term_b<kRAD2>(C, w, k, rc);
+    case kFS1: return dff_term_b<kFS1>(C, w, k, rc);
+    case kCCM1: return dff_term_b<kCCM1>(C, w, k, rc);
+    case kVB2: return dff_term_b<kVB2>(C, w, k, rc);
+    default: return dff_term_b<kBJ1>(C, w, k, rc);
   }
 }
 
@@ -1775,12 +1786,13 @@ __global__ __launch_bounds__(kNodeTile) void k_node_delta(const NodeTask *__rest
         const int64_t x = T - (int64_t)C * ((int64_t)t.nbig - n1);
         key = pack_key(t.nbig + (x > 0 ? ceil_div_small(x, C) : 0), lam);
       } else {
-        const LamConst kc = lam_const(bound, uC, (uint32_t)lam);
+        const LamConst kc = lam_const(uC, (uint32_t)lam);
+        const double rc = 1.0 / (double)C;
         int64_t S = base[idx];
         for (int32_t j = 0; j < t.nd; ++j) {
           const int32_t v = dl[j];
           const uint32_t w = v > 0 ? (uint32_t)(v - 1) : (uint32_t)(-(int64_t)v - 1);
-          const int64_t f = dff_term(bound, uC, w, kc);
+          const int64_t f = dff_term(bound, uC, w, kc, rc);
           S += v > 0 ? f : -f;
         }
         if (dst) dst[idx] = S;
@@ -1829,6 +1841,192 @@ __global__ __launch_bounds__(256) void k_node_finalize(const NodeTask *__restric
     o.verdict = lb <= t.k ? 1 : 0;
     out[t.out_idx] = o;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Small checks in one launch.  Every workgroup rebuilds the reduced instance
+// of Fig. 3 in its LDS (sizes, then one virtual item per loaded bin) from the
+// kernel arguments, with its totals, then takes its share of the (bound,
+// parameter) pairs, one per thread: the exact per-lane f of Sec. 3.1
+// (dff_term) summed over the items, or L2(I, lambda) from its three classes.
+// The workgroups' packed maxima meet in gkeys[0..kNB) (one atomic maximum per
+// bound per workgroup); the last workgroup to finish, counted in gkeys[kNB],
+// writes the record to `out` (host memory), clears gkeys for the next call
+// and then publishes `seq`.
+
+__global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a, unsigned long long *gkeys,
+                                                                   bp_bounds *out, uint32_t *seq_out, uint32_t seq) {
+  __shared__ uint32_t w[kSmallFusedMax];
+  __shared__ uint32_t wsum[kSmallFusedThreads / 64];
+  __shared__ unsigned long long key[kNB];
+  __shared__ unsigned long long tot_w;
+  __shared__ int32_t nbig_s, maxw_s, bad_s, last_s;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const uint32_t C = (uint32_t)a.C;
+  if (tid < kNB) key[tid] = 0ull;
+  if (tid == 0) {
+    tot_w = 0ull;
+    nbig_s = 0;
+    maxw_s = 0;
+    bad_s = 0;
+  }
+  // the sizes, validated
+  for (int i = tid; i < a.n; i += kSmallFusedThreads) {
+    int32_t x = a.v[i];
+    if (x < 0 || x > a.C) { bad_s = 1; x = 0; }
+    w[i] = (uint32_t)x;
+  }
+  int32_t r = a.n;
+  if (a.form == kFormResidual) {
+    // one virtual item of size c - residual per bin with residual < c, in bin order
+    uint32_t base = 0;
+    for (int j0 = 0; j0 < a.m; j0 += kSmallFusedThreads) {
+      const int j = j0 + tid;
+      const bool in = j < a.m;
+      int32_t res = in ? a.v[a.n + j] : a.C;
+      if (in && (res < 0 || res > a.C)) { bad_s = 1; res = a.C; }
+      const bool take = in && res < a.C;
+      const uint64_t bal = ballot64(take);
+      __syncthreads();
+      if ((tid & 63) == 0) wsum[wave] = (uint32_t)__popcll(bal);
+      __syncthreads();
+      uint32_t off = 0, tot = 0;
+      for (int v = 0; v < kSmallFusedThreads / 64; ++v) {
+        off += v < wave ? wsum[v] : 0u;
+        tot += wsum[v];
+      }
+      if (take) w[a.n + base + off + (uint32_t)__popcll(bal & lanemask_lt())] = C - (uint32_t)res;
+      base += tot;
+    }
+    r = a.n + (int32_t)base;
+  }
+  __syncthreads();
+  if (bad_s) r = 0;
+  // totals: sum, count of big sizes, largest size
+  for (int i = tid; i < r; i += kSmallFusedThreads) {
+    const uint32_t x = w[i];
+    atomicAdd(&tot_w, (unsigned long long)x);
+    if (2ull * x > C) atomicAdd(&nbig_s, 1);
+    atomicMax(&maxw_s, (int32_t)x);
+  }
+  __syncthreads();
+  const int64_t nbig = nbig_s;
+  int64_t hi[kNB];
+  for (int b = 0; b < kNB; ++b) hi[b] = a.hi[b];
+  if (a.clamp) {
+    const int64_t denom = (int64_t)r * maxw_s;
+    const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)a.C;
+    if (cap < hi[kVB2]) hi[kVB2] = cap;
+  }
+  // this workgroup's (bound, parameter) pairs: a group of S consecutive
+  // lanes per pair, each lane summing every S-th item, the group's partial
+  // sums added by shuffles
+  int64_t total = 0;
+  for (int b = kL2; b < kNB; ++b) total += a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
+  const double rc = 1.0 / (double)C;
+  const int S = a.slices;
+  const int sl = tid & (S - 1);
+  unsigned long long best[kNB] = {};
+  for (int64_t gt = (int64_t)blockIdx.x * kSmallFusedThreads + tid; gt < total * S;
+       gt += (int64_t)gridDim.x * kSmallFusedThreads) {
+    int b = kL2;
+    int64_t idx = gt / S;
+    for (; b < kNB; ++b) {
+      const int64_t len = a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
+      if (idx < len) break;
+      idx -= len;
+    }
+    const int64_t lam = a.lo[b] + idx;
+    int64_t p0 = 0, p1 = 0;  // L2: n1 and T; a function: its partial sum
+    if (b == kL2) {
+      for (int32_t i = sl; i < r; i += S) {
+        const int64_t x = w[i];
+        p0 += x > (int64_t)C - lam;
+        const bool in2 = 2 * x > (int64_t)C && x <= (int64_t)C - lam;
+        const bool in3 = x >= lam && 2 * x <= (int64_t)C;
+        p1 += (in2 || in3) ? x : 0;
+      }
+    } else {
+      const LamConst kc = lam_const(C, (uint32_t)lam);
+      auto sum = [&](auto term) {
+        for (int32_t i = sl; i < r; i += S) p0 += term(w[i]);
+      };
+      switch (b) {
+        case kMT: sum([&](uint32_t x) { return dff_term_b<kMT>(C, x, kc, rc); }); break;
+        case kRAD2: sum([&](uint32_t x) { return dff_term_b<kRAD2>(C, x, kc, rc); }); break;
+        case kFS1: sum([&](uint32_t x) { return dff_term_b<kFS1>(C, x, kc, rc); }); break;
+        case kCCM1: sum([&](uint32_t x) { return dff_term_b<kCCM1>(C, x, kc, rc); }); break;
+        case kVB2: sum([&](uint32_t x) { return dff_term_b<kVB2>(C, x, kc, rc); }); break;
+        default: sum([&](uint32_t x) { return dff_term_b<kBJ1>(C, x, kc, rc); }); break;
+      }
+    }
+    for (int o = 1; o < S; o <<= 1) {
+      p0 += __shfl_xor(p0, o, 64);
+      p1 += __shfl_xor(p1, o, 64);
+    }
+    if (sl == 0) {
+      int64_t v;
+      if (b == kL2) {
+        const int64_t y = p1 - (int64_t)C * (nbig - p0);
+        v = nbig + (y > 0 ? ceil_div_small(y, (int64_t)C) : 0);
+      } else {
+        v = ceil_div_small(p0, fc_bound(b, a.C, lam));
+      }
+      for (int q = kL2; q < kNB; ++q)
+        if (q == b) best[q] = umax64(best[q], pack_key(v, lam));
+    }
+  }
+  for (int q = kL2; q < kNB; ++q) {
+    const uint64_t m = wave_max_u64(best[q]);
+    if (lane_id() == 0 && m) atomicMax(&key[q], (unsigned long long)m);
+  }
+  __syncthreads();
+  if (tid < kNB && key[tid]) atomicMax(&gkeys[tid], key[tid]);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last_s = atomicAdd(&gkeys[kNB], 1ull) == gridDim.x - 1 ? 1 : 0;
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  if (tid == 0) {
+    unsigned long long gk[kNB];
+    for (int b = 0; b < kNB; ++b) gk[b] = __hip_atomic_load(&gkeys[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bp_bounds o;
+    o.k = a.k;
+    o.r = r;
+    o.status = bad_s ? BP_ERR_RANGE : BP_OK;
+    o.early_exit = 0;
+    int64_t P = 0;
+    for (int b = kMT; b < kNB; ++b) P += a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
+    o.evals = (int64_t)r * P;
+    o.evals_done = o.evals;
+    o.value[kL1] = r > 0 ? (int64_t)((tot_w + C - 1) / C) : 0;
+    o.argmax_lambda[kL1] = -1;
+    for (int b = kL2; b < kNB; ++b) {
+      o.value[b] = gk[b] ? (int64_t)(gk[b] >> 32) : 0;
+      o.argmax_lambda[b] = gk[b] ? (int64_t)(0xffffffffu - (uint32_t)gk[b]) : -1;
+    }
+    int64_t lb = -1;
+    int32_t arg = 0;
+    for (int b = 0; b < kNB; ++b)
+      if (o.value[b] > lb) { lb = o.value[b]; arg = b; }
+    o.lb = lb;
+    o.lb_arg = arg;
+    o.verdict = lb <= a.k ? 1 : 0;
+    *out = o;
+    // clean for the next call (every other workgroup is done with gkeys)
+    for (int b = 0; b <= kNB; ++b) __hip_atomic_store(&gkeys[b], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the record is visible to the host before the sequence number that announces it
+    __threadfence_system();
+    __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+hipError_t launch_small_check(const SmallArgs &a, int grid, unsigned long long *gkeys, bp_bounds *out,
+                              uint32_t *seq_out, uint32_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_check, dim3(grid), dim3(kSmallFusedThreads), 0, s, a, gkeys, out, seq_out, seq);
+  return hipGetLastError();
 }
 
 hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,

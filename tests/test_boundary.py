@@ -111,6 +111,24 @@ def test_divisibility_test_edge_divisors():
         assert bp.selftest_division(lo, hi, 4096, 2) == 0, (lo, hi)
 
 
+def test_fp64_floor_small_divisors_exhaustive():
+    # floor(n / d) = truncation of n * fl(1/d), one correction step: every d < 2^11, n < 2^13, multiples, top
+    assert bp.selftest_division(1, 2048, 8192, 3) == 0
+
+
+def test_fp64_floor_edge_divisors():
+    for lo, hi in [(2**15 - 3, 2**15 + 3), (2**20 - 1, 2**20 + 1), (2**30 - 2, 2**30 + 2), (2**31 - 4, 2**31 - 1),
+                   (99_999, 100_001), (999_999, 1_000_001), (1_999_999_973, 1_999_999_973)]:
+        assert bp.selftest_division(lo, hi, 4096, 3) == 0, (lo, hi)
+
+
+def test_fp64_floor_vb2_quotient():
+    # floor((a lambda - 1) / c) for a, lambda <= c: every c <= 300, and large capacities near the int32 top
+    assert bp.selftest_division(1, 300, 1 << 20, 4) == 0
+    for c in (10_000, 100_000, 1_000_000, 2**25, 2**31 - 1, 2**31 - 2, 1_999_999_973):
+        assert bp.selftest_division(c, c, 4096, 4) == 0, c
+
+
 def test_selftest_rejects_bad_ranges():
     assert bp.selftest_division(0, 10, 10, 0) == bp.BP_ERR_ARG
     assert bp.selftest_division(10, 5, 10, 0) == bp.BP_ERR_ARG

@@ -14,6 +14,7 @@ default shape, splits its tiles; with chunks of at least 65 536 items and no
 FS1 or RAD2 range (the bounds whose few tiles would still be split) it
 splits nothing.
 """
+import os
 import sys
 
 import numpy as np
@@ -63,7 +64,17 @@ def test_variants_alternate_in_one_context():
         if c["drop"]:
             lo, hi = c["lo"], c["hi"]
         want[name] = O.bounds(c["C"], c["k"], c["items"], lo, hi)
-    with bp.Context(0) as ctx:
+    # the pipeline itself: small checks would otherwise take the one-launch path
+    old = os.environ.get("BP_NO_SMALL_PATH")
+    os.environ["BP_NO_SMALL_PATH"] = "1"
+    try:
+        ctx = bp.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("BP_NO_SMALL_PATH", None)
+        else:
+            os.environ["BP_NO_SMALL_PATH"] = old
+    with ctx:
         default = ctx.get_tuning()
         for name in ("small", "large_split", "small_split", "large_whole", "small", "large_whole", "large_split",
                      "small_split"):

@@ -58,6 +58,59 @@ def rand_instance(rng, cmax=300, nmax=40):
     return C, items
 
 
+@pytest.fixture(scope="module")
+def ctx_pipe():
+    # a context whose small checks run the multi-kernel pipeline too
+    old = os.environ.get("BP_NO_SMALL_PATH")
+    os.environ["BP_NO_SMALL_PATH"] = "1"
+    try:
+        c = bp.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("BP_NO_SMALL_PATH", None)
+        else:
+            os.environ["BP_NO_SMALL_PATH"] = old
+    yield c
+    c.close()
+
+
+def test_small_checks_on_both_paths(ctx, ctx_pipe):
+    # the one-launch path (instance in the kernel arguments) and the pipeline
+    # on the same small checks: random instances with custom ranges and the
+    # VB2 cut, and partial packings; every record equal to the oracle's
+    rng = random.Random(909)
+    for t in range(120):
+        C, items = rand_instance(rng, cmax=400, nmax=60)
+        k = rng.randint(0, len(items) + 1)
+        dlo, dhi = zip(*(O.default_range(b, C) for b in range(O.NB)))
+        lo, hi = list(dlo), list(dhi)
+        if t % 3 == 1:
+            for b in range(1, O.NB):
+                if dlo[b] <= dhi[b]:
+                    x, y = sorted(rng.randint(dlo[b], dhi[b]) for _ in range(2))
+                    lo[b], hi[b] = x, y
+        want = O.bounds(C, k, items, lo, hi, l2_dense=True)
+        for c, name in ((ctx, "one launch"), (ctx_pipe, "pipeline")):
+            say("small both paths", t, name)
+            same(c.lower_bounds(C, k, items, bp.make_sweep(lo, hi)), want, (name, C, items, lo, hi))
+        if t % 6 == 0:
+            maxw = max(items) if items else 0
+            clo, chi = zip(*(O.default_range(b, C, len(items), maxw, clamp_vb2=True) for b in range(O.NB)))
+            sw = bp.default_sweep(C)
+            sw.flags = bp.BP_SWEEP_PAPER_VB2_CLAMP
+            wantc = O.bounds(C, k, items, list(clo), list(chi), l2_dense=True)
+            for c, name in ((ctx, "one launch"), (ctx_pipe, "pipeline")):
+                same(c.lower_bounds(C, k, items, sw), wantc, (name, "clamp", C))
+    for seed in range(100, 140):
+        C, m, res, unp = W.small_partial_packing(seed)
+        want = O.bounds(C, m, O.residual_reduce(C, res, unp))
+        for c, name in ((ctx, "one launch"), (ctx_pipe, "pipeline")):
+            got = c.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+            same(got, want, (name, seed))
+            assert got["evals_done"] == got["evals"]
+            assert c.feasible(C, res, unp)["verdict"] == want["verdict"]
+
+
 def test_fig3_worked_example(ctx):
     g = fig3()
     C, k = g["C"][0], g["bins"][0]
