@@ -112,6 +112,24 @@ def cpu_baseline(C, items, target_s: float):
                       f"{host['model']}; a single-thread probe puts the whole instance at {full_core_s:.1f} core-s)"}
 
 
+def tuning_cache_path() -> str:
+    """File of the autotuner's cache: $BP_TUNING_CACHE, else under ~/.cache
+    (or the temporary directory when that is not writable)."""
+    env = os.environ.get("BP_TUNING_CACHE")
+    if env:
+        return env
+    for base in (os.path.expanduser("~/.cache"), os.environ.get("TMPDIR", "/tmp")):
+        try:
+            os.makedirs(base, exist_ok=True)
+            path = os.path.join(base, "libbp_tuning.txt")
+            with open(path, "a"):
+                pass
+            return path
+        except OSError:
+            continue
+    return None
+
+
 def host_cpu():
     """Logical CPU count, the CPUs this process may use, and the CPU model."""
     model = "unknown"
@@ -247,7 +265,7 @@ def load_valu_insts(kernel: str):
 
 
 def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, plain_max: int = 4096,
-                  segments: bool = True):
+                  segments: bool = True, tuning_cache: str | None = None):
     """Uneven batch: one batched call vs one plain call per instance (host in, host out)."""
     import numpy as np
 
@@ -256,6 +274,15 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
     Cs, ks = b.C, b.k
     out = ctx.lower_bounds_batch(Cs, ks, items_list)  # warm-up (sizes the workspaces, captures the graph)
     assert (out["status"] == 0).all()
+    # the default shape, then the autotuner's (cached on disk by batch shape)
+    t0 = time.perf_counter()
+    ctx.lower_bounds_batch(Cs, ks, items_list)
+    t_default = time.perf_counter() - t0
+    default_tuning = ctx.get_tuning()
+    t0 = time.perf_counter()
+    tuned, tuned_ms, from_cache = ctx.autotune_batch_cached(Cs, ks, items_list, tuning_cache, reps=1)
+    t_tune = time.perf_counter() - t0
+    ctx.lower_bounds_batch(Cs, ks, items_list)  # warm-up of the tuned shape
     ts = []
     for _ in range(reps):
         t0 = time.perf_counter()
@@ -313,7 +340,9 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
             "stages_ms": {"prep": prep_ms, "sweep": sweep_ms, "finalize": fin_ms, "runs": runs},
             "sweep_roofline": {"bound": "alu", "achieved": ops / (sweep_ms * 1e-3) / 1e12, "peak": PEAK_VALU / 1e12,
                                "unit": "TOP/s", "frac": ops / (sweep_ms * 1e-3) / PEAK_VALU},
-            "tuning": ctx.get_tuning()}
+            "tuning": ctx.get_tuning(), "tuning_default": default_tuning,
+            "tuning_from_cache": from_cache, "tuning_s": t_tune, "tuning_sweep_ms": tuned_ms,
+            "batched_s_default_shape": t_default}
 
 
 def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps):
@@ -342,6 +371,151 @@ def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain
             "per_class_plain_checks_per_s": {
                 str(c): float((Cs[:n_plain] == c).sum() / per_s[Cs[:n_plain] == c].sum())
                 for c in sorted(set(int(x) for x in Cs))}}
+
+
+def triplet_windows(bp, C: int, width: int = 8192):
+    """Low-end and high-end windowed sweeps of capacity C: every DFF range
+    longer than two windows keeps its first (resp. last) `width` parameters;
+    shorter ranges and L2 stay whole."""
+    full = bp.default_sweep(int(C))
+    sides = []
+    for side in (0, 1):
+        lo, hi = [0] * bp.BP_NB, [-1] * bp.BP_NB
+        for b in range(1, bp.BP_NB):
+            dlo, dhi = int(full.lo[b]), int(full.hi[b])
+            if b == bp.BP_L2 or dhi - dlo + 1 <= 2 * width:
+                lo[b], hi[b] = (dlo, dhi) if dlo <= dhi else (1, 0)
+            else:
+                lo[b], hi[b] = (dlo, dlo + width - 1) if side == 0 else (dhi - width + 1, dhi)
+        sides.append(bp.make_sweep(lo, hi))
+    return sides
+
+
+def bench_triplets(bp, W, ctx, seed: int = 5, count: int = 1024, reps: int = 3):
+    """Triplet-tight batch: 1 024 instances, m ~ U[300, 1000] bins of three sizes
+    in (C/4, C/2) summing exactly to C, C ~ U[10^6, 2^31 - 1], half missing a
+    bin; every DFF range cut to windows of 8 192 at both ends, L2 exact."""
+    import numpy as np
+
+    tb = W.triplet_batch(seed, count=count)
+    Cs, ks, its, sweeps, owner = [], [], [], [], []
+    for i in range(len(tb)):
+        C, k, items = tb.instance(i)
+        for sw in triplet_windows(bp, C):
+            Cs.append(C)
+            ks.append(k)
+            its.append(items)
+            sweeps.append(sw)
+            owner.append(i)
+    Cs, ks = np.array(Cs), np.array(ks)
+    out = ctx.lower_bounds_batch(Cs, ks, its, sweeps)  # warm-up
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = ctx.lower_bounds_batch(Cs, ks, its, sweeps)
+        ts.append(time.perf_counter() - t0)
+    t = min(ts)
+    verdict = np.ones(len(tb), dtype=np.int32)
+    for j, i in enumerate(owner):
+        verdict[i] &= out["verdict"][j]
+    assert np.array_equal(verdict == 0, tb.expect_fail), "triplet verdicts differ from the construction"
+    evals = int(out["evals"].sum())
+    return {"workload": "1024 triplet-tight instances, m~U[300,1000], n=3m, C~U[1e6,2^31-1], half missing a bin; "
+                        "DFF ranges cut to windows of 8192 at both ends, L2 exact; host in/out",
+            "instances": len(tb), "launch_instances": len(Cs), "batched_s": t, "checks_per_s": len(tb) / t,
+            "evals": evals, "evals_per_s": evals / t, "fails": int((verdict == 0).sum())}
+
+
+def bench_fidelity(bp, W, ctx, reps: int = 3):
+    """Paper-fidelity study.  (1) The paper's VB2 cut (Sec. 4) against the
+    exact range: bounds and verdicts it changes, and time, on the single large
+    instance and the uneven batch.  (2) The order of the functions (Alg. 2
+    visits MT, RAD2, FS1, CCM1, VB2, BJ1 and returns after the first bound
+    above k; Table 1 ranks CCM1 strongest) against early exit: on instances
+    that only a DFF refutes (k = L1 < the best bound), the work done before
+    the refutation, on the GPU per schedule order and in Alg. 2's
+    sequential model."""
+    import numpy as np
+
+    res = {}
+    # (1) VB2 cut on the large instance
+    C, m, residual, unpacked = W.large_residual(seed=1)
+    items = ctx.residual_reduce(C, residual, unpacked)
+    rows = {}
+    for name, flags in (("exact", 0), ("paper_vb2_cut", bp.BP_SWEEP_PAPER_VB2_CLAMP)):
+        sw = bp.default_sweep(C)
+        sw.flags = flags
+        rec = ctx.lower_bounds(C, m, items, sw)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rec = ctx.lower_bounds(C, m, items, sw)
+        rows[name] = {"ms": (time.perf_counter() - t0) * 1e3 / reps, "vb2": int(rec["value"][bp.BP_VB2]),
+                      "vb2_argmax": int(rec["argmax"][bp.BP_VB2]), "lb": rec["lb"], "evals": rec["evals"]}
+    res["vb2_cut_large_instance"] = rows
+    # (1') VB2 cut on the uneven batch
+    b = W.uneven_batch(2, count=4096)
+    its = [b.instance(i)[2] for i in range(len(b))]
+    ex = ctx.lower_bounds_batch(b.C, b.k, its)
+    sweeps_cut = []
+    for c in b.C:
+        sw = bp.default_sweep(int(c))
+        sw.flags = bp.BP_SWEEP_PAPER_VB2_CLAMP
+        sweeps_cut.append(sw)
+    cut = ctx.lower_bounds_batch(b.C, b.k, its, sweeps_cut)
+    res["vb2_cut_uneven_batch"] = {
+        "instances": len(b),
+        "vb2_lower": int((cut["value"][:, bp.BP_VB2] < ex["value"][:, bp.BP_VB2]).sum()),
+        "lb_lower": int((cut["lb"] < ex["lb"]).sum()),
+        "verdicts_changed": int((cut["verdict"] != ex["verdict"]).sum()),
+        "evals_exact": int(ex["evals"].sum()), "evals_cut": int(cut["evals"].sum())}
+    # (2) order against early exit, on instances only a DFF refutes
+    pool = W.uneven_batch(7, count=2048, capacities=(1_000, 10_000))
+    pits = [pool.instance(i)[2] for i in range(len(pool))]
+    full = ctx.lower_bounds_batch(pool.C, pool.k, pits)
+    dff_best = full["value"][:, bp.BP_MT:].max(axis=1)
+    l1 = full["value"][:, bp.BP_L1]
+    sel = np.flatnonzero((dff_best > l1) & (full["value"][:, bp.BP_L2] <= l1))
+    sub = pool.subset(sel)
+    sub_its = [sub.instance(i)[2] for i in range(len(sub))]
+    k = l1[sel].astype(np.int32)  # L1 and L2 pass: the verdict needs a DFF
+    vals = full["value"][sel]
+    names = ["MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1"]
+    orders = {"alg2": [bp.BP_MT, bp.BP_RAD2, bp.BP_FS1, bp.BP_CCM1, bp.BP_VB2, bp.BP_BJ1],
+              "table1": [bp.BP_CCM1, bp.BP_MT, bp.BP_BJ1, bp.BP_VB2, bp.BP_FS1, bp.BP_RAD2],
+              "longest_first": None}
+    gpu = {}
+    exhaustive = 0
+    for name, order in orders.items():
+        ctx.set_order(order)
+        ctx.feasible_batch(sub.C, k, sub_its)  # warm-up
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            v, lb, rec = ctx.feasible_batch(sub.C, k, sub_its, records=True)
+        dt = (time.perf_counter() - t0) / reps
+        assert (v == 0).all(), "every selected instance is refuted by a DFF"
+        exhaustive = int(rec["evals"].sum())
+        gpu[name] = {"batched_s": dt, "evals_done": int(rec["evals_done"].sum()),
+                     "early_exits": int(rec["early_exit"].sum())}
+    ctx.set_order(None)
+    # sequential Alg. 2 model: bounds in order, each over its whole range, stop after the first above k
+    ranges = {}
+    seq = {}
+    for name, order in (("alg2", orders["alg2"]), ("table1", orders["table1"])):
+        work = 0
+        for j in range(len(sel)):
+            C = int(sub.C[j])
+            sw = ranges.setdefault(C, bp.default_sweep(C))
+            r = len(sub_its[j])
+            for bd in order:
+                work += r * max(0, int(sw.hi[bd]) - int(sw.lo[bd]) + 1)
+                if vals[j][bd] > k[j]:
+                    break
+        seq[name] = work
+    res["order_vs_early_exit"] = {
+        "instances": int(len(sel)), "pool": len(pool),
+        "refuting_function_counts": {n: int((vals[:, bp.BP_MT + i] > k).sum()) for i, n in enumerate(names)},
+        "gpu": gpu, "sequential_alg2_work": seq, "exhaustive_work": exhaustive}
+    return res
 
 
 def per_bound_table(bp, W, ctx, reps: int = 5):
@@ -425,32 +599,30 @@ def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: in
 
     th = threading.Thread(target=poller, daemon=True)
     th.start()
-    ticket = ctypes.c_uint64(0)
-    tickets = np.zeros(len(reqs), dtype=np.uint64)
-    rejected = dropped = 0
+    # the open-loop submitter runs natively (bp_queue_replay): a Python loop
+    # cannot keep 5 us between arrivals
+    n = len(reqs)
+    arr = (bp.bp_request * n)(*structs)
+    arrival = np.ascontiguousarray([r.t for r in reqs], dtype=np.float64)
+    parent = np.ascontiguousarray([r.parent for r in reqs], dtype=np.int64)
+    tickets = np.zeros(n, dtype=np.uint64)
+    status = np.zeros(n, dtype=np.int32)
+    late_c = ctypes.c_double(0)
+    submitted[0] = n  # an upper bound until the replay returns
     t0 = time.perf_counter()
-    late = 0.0
-    for i, r in enumerate(reqs):
-        if r.parent >= 0:
-            pt = int(tickets[r.parent])
-            if pt == 0:  # the parent was rejected or dropped: the search cannot go on from it
-                dropped += 1
-                continue
-            structs[i].parent = pt
-        while True:
-            now = time.perf_counter() - t0
-            if now >= r.t:
-                break
-        late = max(late, now - r.t)
-        st = lib.bp_queue_submit(q.handle, ctypes.byref(structs[i]), 0, ctypes.byref(ticket))
-        if st == bp.BP_ERR_AGAIN:
-            rejected += 1
-        elif st != 0:
-            raise bp.BpError(st, lib.bp_last_error().decode())
-        else:
-            tickets[i] = ticket.value
-            submitted[0] += 1
+    st = lib.bp_queue_replay(q.handle, ctypes.cast(arr, ctypes.c_void_p), arrival.ctypes.data_as(ctypes.c_void_p),
+                             parent.ctypes.data_as(ctypes.c_void_p), n, tickets.ctypes.data_as(ctypes.c_void_p),
+                             status.ctypes.data_as(ctypes.c_void_p), ctypes.byref(late_c))
+    if st != 0:
+        raise bp.BpError(st, lib.bp_last_error().decode())
     t_submit = time.perf_counter() - t0
+    late = late_c.value
+    rejected = int((status == bp.BP_ERR_AGAIN).sum())
+    dropped = int((status == bp.BP_ERR_STATE).sum())
+    other = status[(status != 0) & (status != bp.BP_ERR_AGAIN) & (status != bp.BP_ERR_STATE)]
+    if len(other):
+        raise bp.BpError(int(other[0]), "replay submit failed")
+    submitted[0] = int((status == 0).sum())
     done.set()
     th.join(timeout=120)
     t_end = time.perf_counter() - t0
@@ -657,8 +829,12 @@ def main():
     }
     log(f"large instance done: {ms_per_step:.3f} ms/step")
     if not args.no_batched:
-        line["batched"] = bench_batched(bp, W, ctx, segments=not args.no_segments)
+        line["batched"] = bench_batched(bp, W, ctx, segments=not args.no_segments, tuning_cache=tuning_cache_path())
         log("batched leg done")
+        line["triplets"] = bench_triplets(bp, W, ctx)
+        log("triplet leg done")
+        line["fidelity"] = bench_fidelity(bp, W, ctx)
+        log("fidelity study done")
     if not args.no_served:
         line["served"] = []
         legs = [(0, 20_000.0, 3), (0, 200_000.0, 4)]

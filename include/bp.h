@@ -235,8 +235,10 @@ bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const in
                                     const bp_sweep *per_inst, bp_bounds *d_out, void *stream);
 
 /* Batched feasibility check of reduced instances with k[i] bins each;
- * flags as in bp_feasible.  verdict[count], lb[count]. */
-bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb);
+ * flags as in bp_feasible.  verdict[count], lb[count] and bounds[count]
+ * (the records, with early_exit and evals_done) may each be NULL. */
+bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb,
+                            bp_bounds *bounds);
 
 /* Autotuner: times the sweep of this batch (host pointers, as
  * bp_lower_bounds_batch) under candidate shapes, one knob at a time starting
@@ -245,6 +247,29 @@ bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, 
  * may be NULL. */
 bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, int32_t reps,
                             bp_tuning *best, double *best_ms);
+
+/* Order in which a launch schedules the six functions' tiles (L2's tiles
+ * always go first): order[0..5] is a permutation of BP_MT .. BP_BJ1, tiles of
+ * earlier functions first, longest first within a function.  NULL restores
+ * the default, longest tile first over all functions.  Results do not
+ * depend on it; with early exit (Alg. 2 returns after the first function
+ * whose bound exceeds k; Alg. 4 skips work once lb > k) the work done
+ * before a refutation does.  BP_ERR_ARG if order is not a permutation. */
+bp_status bp_ctx_set_order(bp_ctx *ctx, const int32_t *order);
+
+/* The autotuner with a cache on disk.  The batch's shape is summarised as a
+ * key: the count of instances and of items (each rounded up to a power of
+ * two), the distinct capacities (rounded up to powers of two, at most eight)
+ * and the sweep flags of per_inst.  A line of cache_path (a text file, one
+ * "key lanes_params waves_per_cu tasks_per_wave min_chunk sweep_ms" per
+ * line) with this key sets that shape on the context without timing
+ * anything (*from_cache = 1); otherwise bp_autotune_batch runs and its
+ * result is appended (*from_cache = 0).  cache_path NULL: no cache.  An
+ * unreadable or malformed file is treated as empty; a failed append is
+ * BP_ERR_ARG after the shape is set.  *best, *best_ms, *from_cache may be
+ * NULL. */
+bp_status bp_autotune_batch_cached(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, int32_t reps,
+                                   const char *cache_path, bp_tuning *best, double *best_ms, int32_t *from_cache);
 
 /* Allocation-free variant of bp_feasible_dev, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
@@ -351,6 +376,20 @@ bp_status bp_queue_submit(bp_queue *q, const bp_request *req, int32_t blocking, 
 bp_status bp_queue_poll(bp_queue *q, bp_result *out, int32_t max, int32_t *got, int32_t timeout_us);
 
 bp_status bp_queue_stats_get(bp_queue *q, bp_queue_stats *out);
+
+/* Open-loop replay of a request stream, for load tests: request i is
+ * submitted (non-blocking) once arrival_s[i] seconds have passed since the
+ * call began (arrival_s non-decreasing).  parent_index[i] >= 0 names an
+ * earlier request of the stream: the request is submitted as that one's
+ * child (its parent field is set to that request's ticket); if that request
+ * was not admitted, this one is not submitted either (status[i] =
+ * BP_ERR_STATE), as a search cannot go on from a node it never checked.
+ * tickets[n] receives the tickets (0 when not admitted), status[n] each
+ * submit's status (BP_ERR_AGAIN when rejected), *lateness_s the largest
+ * delay between an arrival time and its submit.  The requests' arrays must
+ * stay valid during the call; reqs[i].parent is overwritten. */
+bp_status bp_queue_replay(bp_queue *q, bp_request *reqs, const double *arrival_s, const int64_t *parent_index,
+                          int64_t n, uint64_t *tickets, int32_t *status, double *lateness_s);
 
 /* Stop admitting, finish the batches on the device, complete still-queued
  * requests with BP_ERR_STATE, join the thread and free everything. */

@@ -117,14 +117,19 @@ _SIGNATURES = {
     "bp_ctx_set_tuning": ([_VP, ctypes.POINTER(bp_tuning)], _i32),
     "bp_autotune_batch": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _i32,
                            ctypes.POINTER(bp_tuning), ctypes.POINTER(ctypes.c_double)], _i32),
+    "bp_autotune_batch_cached": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _i32, ctypes.c_char_p,
+                                  ctypes.POINTER(bp_tuning), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int32)], _i32),
+    "bp_ctx_set_order": ([_VP, _P32], _i32),
     "bp_ctx_stage_times": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], _i32),
     "bp_lower_bounds_batch": ([_VP, ctypes.POINTER(bp_batch), ctypes.POINTER(bp_sweep), _VP], _i32),
     "bp_lower_bounds_batch_dev": ([_VP, ctypes.POINTER(bp_batch), _VP, ctypes.POINTER(bp_sweep), _VP, _VP], _i32),
-    "bp_feasible_batch": ([_VP, ctypes.POINTER(bp_batch), _u32, _P32, _P64], _i32),
+    "bp_feasible_batch": ([_VP, ctypes.POINTER(bp_batch), _u32, _P32, _P64, _VP], _i32),
     "bp_queue_create": ([_VP, ctypes.c_size_t, _i32, ctypes.POINTER(_VP)], _i32),
     "bp_queue_submit": ([_VP, ctypes.POINTER(bp_request), _i32, ctypes.POINTER(_u64)], _i32),
     "bp_queue_poll": ([_VP, _VP, _i32, _P32, _i32], _i32),
     "bp_queue_stats_get": ([_VP, ctypes.POINTER(bp_queue_stats)], _i32),
+    "bp_queue_replay": ([_VP, _VP, _VP, _VP, _i64, _VP, _VP, ctypes.POINTER(ctypes.c_double)], _i32),
     "bp_queue_destroy": ([_VP], _i32),
     "bp_selftest_division": ([_u32, _u32, _u32, _u32], _i64),
 }
@@ -339,6 +344,29 @@ class Context:
         _check(self._lib.bp_autotune_batch(self.handle, ctypes.byref(b.s), sw, reps, ctypes.byref(t), ctypes.byref(ms)))
         return {f: getattr(t, f) for f, _ in bp_tuning._fields_}, ms.value
 
+    def autotune_batch_cached(self, Cs, ks, items_list, cache_path: str | None, reps: int = 1, sweeps=None):
+        """The autotuner through a cache file: (tuning dict, sweep ms, from_cache)."""
+        b = _Batch(Cs, ks, items_list)
+        sw = None
+        if sweeps is not None:
+            arr = (bp_sweep * len(sweeps))(*sweeps)
+            sw = ctypes.cast(arr, ctypes.POINTER(bp_sweep))
+        t = bp_tuning()
+        ms = ctypes.c_double(0)
+        fc = ctypes.c_int32(0)
+        _check(self._lib.bp_autotune_batch_cached(self.handle, ctypes.byref(b.s), sw, reps,
+                                                  cache_path.encode() if cache_path else None, ctypes.byref(t),
+                                                  ctypes.byref(ms), ctypes.byref(fc)))
+        return {f: getattr(t, f) for f, _ in bp_tuning._fields_}, ms.value, bool(fc.value)
+
+    def set_order(self, order=None):
+        """Schedule the six functions' tiles in this order (None: longest first)."""
+        if order is None:
+            _check(self._lib.bp_ctx_set_order(self.handle, None))
+        else:
+            arr = _i32arr(order)
+            _check(self._lib.bp_ctx_set_order(self.handle, _p32(arr)))
+
     def stage_times(self, with_runs: bool = False):
         """Mean durations (ms) of prep, sweep and finalize over the calls made
         since timing was switched on; with_runs also returns how many."""
@@ -367,12 +395,15 @@ class Context:
         _check(self._lib.bp_lower_bounds_batch_dev(self.handle, ctypes.byref(b.s), _VP(d_items_ptr), sw,
                                                    _VP(d_out_ptr), _VP(stream_ptr)))
 
-    def feasible_batch(self, Cs, ks, items_list, flags: int = 0):
+    def feasible_batch(self, Cs, ks, items_list, flags: int = 0, records: bool = False):
+        """(verdict, lb), plus the records when records=True."""
         b = _Batch(Cs, ks, items_list)
         v = np.zeros(len(b.C), dtype=np.int32)
         lb = np.zeros(len(b.C), dtype=np.int64)
-        _check(self._lib.bp_feasible_batch(self.handle, ctypes.byref(b.s), flags, _p32(v), lb.ctypes.data_as(_P64)))
-        return v, lb
+        rec = np.zeros(len(b.C), dtype=BOUNDS_DTYPE) if records else None
+        _check(self._lib.bp_feasible_batch(self.handle, ctypes.byref(b.s), flags, _p32(v), lb.ctypes.data_as(_P64),
+                                           rec.ctypes.data_as(_VP) if records else None))
+        return (v, lb, rec) if records else (v, lb)
 
 
 class Queue:

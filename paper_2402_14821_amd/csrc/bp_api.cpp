@@ -621,6 +621,8 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
     const bool la = ent[a].bound == kL2, lb = ent[b].bound == kL2;
     if (la != lb) return la;
+    const int32_t ra = order_rank[ent[a].bound], rb = order_rank[ent[b].bound];
+    if (ra != rb) return ra < rb;
     return task_cost[a] > task_cost[b];
   });
   std::vector<Entry> seq;
@@ -872,6 +874,25 @@ bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning) {
   if ((st = c->wait_staging())) return st;
   c->tune = *tuning;
   c->apply_tuning();
+  return BP_OK;
+}
+
+bp_status bp_ctx_set_order(bp_ctx *ctx, const int32_t *order) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  int32_t rank[kNB] = {};
+  if (order) {
+    bool seen[kNB] = {};
+    for (int i = 0; i < 6; ++i) {
+      const int32_t b = order[i];
+      if (b < kMT || b > kBJ1 || seen[b]) return fail(BP_ERR_ARG, "order is not a permutation of the six functions");
+      seen[b] = true;
+      rank[b] = i + 1;
+    }
+  }
+  if ((st = c->wait_staging())) return st;
+  memcpy(c->order_rank, rank, sizeof rank);
   return BP_OK;
 }
 
@@ -1302,7 +1323,8 @@ bp_status bp_lower_bounds_batch_dev(bp_ctx *ctx, const bp_batch *batch, const in
   return c->run(batch->count, ntasks, nullptr, 0, d_items, d_items, d_out, (hipStream_t)stream);
 }
 
-bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb) {
+bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, int32_t *verdict, int64_t *lb,
+                            bp_bounds *bounds) {
   Ctx *c;
   bp_status st = get_ctx(ctx, &c);
   if (st) return st;
@@ -1324,6 +1346,7 @@ bp_status bp_feasible_batch(bp_ctx *ctx, const bp_batch *batch, uint32_t flags, 
     if (verdict) verdict[i] = o[i].verdict;
     if (lb) lb[i] = o[i].lb;
   }
+  if (bounds) memcpy(bounds, o.data(), sizeof(bp_bounds) * (size_t)batch->count);
   return BP_OK;
 }
 
@@ -1393,6 +1416,86 @@ bp_status bp_autotune_batch(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *
   c->apply_tuning();
   if (best) *best = cur;
   if (best_ms) *best_ms = cur_ms;
+  return BP_OK;
+}
+
+static int64_t pow2_ceil64(int64_t x) {
+  int64_t p = 1;
+  while (p < x && p < (int64_t(1) << 62)) p <<= 1;
+  return p;
+}
+
+// Shape key of a batch for the tuning cache (no spaces).
+static std::string batch_key(const bp_batch *b, const bp_sweep *per) {
+  std::vector<int64_t> caps;
+  for (int32_t i = 0; i < b->count; ++i) {
+    const int64_t c = pow2_ceil64(b->C[i]);
+    if (std::find(caps.begin(), caps.end(), c) == caps.end()) caps.push_back(c);
+  }
+  std::sort(caps.begin(), caps.end());
+  if (caps.size() > 8) caps.resize(8);
+  uint32_t flags = 0;
+  if (per)
+    for (int32_t i = 0; i < b->count; ++i) flags |= per[i].flags;
+  char buf[64];
+  std::string key = "n" + std::to_string(pow2_ceil64(b->count)) + ".r" +
+                    std::to_string(pow2_ceil64(b->count ? b->off[b->count] : 0)) + ".c";
+  for (size_t i = 0; i < caps.size(); ++i) key += (i ? "-" : "") + std::to_string(caps[i]);
+  snprintf(buf, sizeof buf, ".f%u", flags);
+  return key + buf;
+}
+
+bp_status bp_autotune_batch_cached(bp_ctx *ctx, const bp_batch *batch, const bp_sweep *per_inst, int32_t reps,
+                                   const char *cache_path, bp_tuning *best, double *best_ms, int32_t *from_cache) {
+  Ctx *c;
+  bp_status st = get_ctx(ctx, &c);
+  if (st) return st;
+  if ((st = check_batch(batch))) return st;
+  if (batch->count == 0 || !batch->items) return fail(BP_ERR_ARG, "empty batch");
+  const std::string key = batch_key(batch, per_inst);
+  if (from_cache) *from_cache = 0;
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      bp_tuning t;
+      double ms = 0;
+      bool found = false;
+      while (fgets(line, sizeof line, f)) {
+        char k[256];
+        bp_tuning u;
+        double v = 0;
+        if (sscanf(line, "%255s %d %d %d %d %lf", k, &u.lanes_params, &u.waves_per_cu, &u.tasks_per_wave,
+                   &u.min_chunk, &v) == 6 &&
+            key == k && check_tuning(&u) == BP_OK) {
+          t = u;  // the last matching line wins
+          ms = v;
+          found = true;
+        }
+      }
+      fclose(f);
+      if (found) {
+        if ((st = c->wait_staging())) return st;
+        c->tune = t;
+        c->apply_tuning();
+        if (best) *best = t;
+        if (best_ms) *best_ms = ms;
+        if (from_cache) *from_cache = 1;
+        return BP_OK;
+      }
+    }
+  }
+  bp_tuning t;
+  double ms = 0;
+  if ((st = bp_autotune_batch(ctx, batch, per_inst, reps, &t, &ms))) return st;
+  if (best) *best = t;
+  if (best_ms) *best_ms = ms;
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return fail(BP_ERR_ARG, "cannot append to the tuning cache %s", cache_path);
+    fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), t.lanes_params, t.waves_per_cu, t.tasks_per_wave, t.min_chunk, ms);
+    fclose(f);
+  }
   return BP_OK;
 }
 

@@ -102,6 +102,7 @@ struct Ctx {
   std::map<LaunchShape, uint64_t> graph_used;  // last use (run counter) of each cached graph
   uint64_t run_count = 0;
   bp_tuning tune = {2, 32, 32, 2048};  // parameters per lane, waves per CU, tasks per wave, min chunk
+  int32_t order_rank[kNB] = {};         // schedule rank of each function (bp_ctx_set_order); all 0: longest first
   int grid_sweep = 0, grid_prep_small = 0, grid_prep_large = 0, grid_comb = 0, grid_fin = 0;
   void drop_graphs();
   LaunchShape shape_of(int64_t count, int64_t ntasks) const;

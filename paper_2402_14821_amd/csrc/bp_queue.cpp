@@ -835,6 +835,37 @@ bp_status bp_queue_submit(bp_queue *qh, const bp_request *req, int32_t blocking,
   return BP_OK;
 }
 
+bp_status bp_queue_replay(bp_queue *qh, bp_request *reqs, const double *arrival_s, const int64_t *parent_index,
+                          int64_t n, uint64_t *tickets, int32_t *status, double *lateness_s) {
+  Queue *q;
+  bp_status st = get_queue(qh, &q);
+  if (st) return st;
+  if (n < 0 || (n > 0 && (!reqs || !arrival_s || !parent_index || !tickets || !status)))
+    return fail(BP_ERR_ARG, "bad replay arguments");
+  const double t0 = now_us();
+  double late = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    tickets[i] = 0;
+    const int64_t p = parent_index[i];
+    if (p >= i) return fail(BP_ERR_ARG, "request %lld names a later parent", (long long)i);
+    if (p >= 0) {
+      if (tickets[p] == 0) {
+        status[i] = BP_ERR_STATE;
+        continue;
+      }
+      reqs[i].parent = tickets[p];
+    }
+    const double due = t0 + arrival_s[i] * 1e6;
+    double now = now_us();
+    while (now < due) now = now_us();
+    late = std::max(late, now - due);
+    status[i] = bp_queue_submit(qh, &reqs[i], 0, &tickets[i]);
+    if (status[i] != BP_OK) tickets[i] = 0;
+  }
+  if (lateness_s) *lateness_s = late * 1e-6;
+  return BP_OK;
+}
+
 bp_status bp_queue_poll(bp_queue *qh, bp_result *out, int32_t max, int32_t *got, int32_t timeout_us) {
   Queue *q;
   bp_status st = get_queue(qh, &q);

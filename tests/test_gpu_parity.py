@@ -496,6 +496,37 @@ def test_results_do_not_depend_on_the_sweep_shape(ctx, shape):
         ctx.set_tuning(**old)
 
 
+def test_autotuner_cache_and_schedule_order(ctx, tmp_path):
+    rng = random.Random(818)
+    insts = [rand_instance(rng, cmax=3000, nmax=250) for _ in range(64)]
+    Cs = [c for c, _ in insts]
+    ks = [rng.randint(0, len(it) + 1) for _, it in insts]
+    its = [it for _, it in insts]
+    want = O.bounds_many([(C, k, it) for (C, it), k in zip(insts, ks)])
+    cache = str(tmp_path / "tuning.txt")
+    say("autotuner cache")
+    t1, ms1, hit1 = ctx.autotune_batch_cached(Cs, ks, its, cache, reps=1)
+    t2, ms2, hit2 = ctx.autotune_batch_cached(Cs, ks, its, cache, reps=1)
+    assert not hit1 and hit2 and t1 == t2 and ctx.get_tuning() == t2
+    with open(cache) as fh:
+        assert len(fh.read().splitlines()) == 1
+    # results do not depend on the schedule order; records of the batched check carry the work done
+    for order in ([bp.BP_MT, bp.BP_RAD2, bp.BP_FS1, bp.BP_CCM1, bp.BP_VB2, bp.BP_BJ1],
+                  [bp.BP_CCM1, bp.BP_MT, bp.BP_BJ1, bp.BP_VB2, bp.BP_FS1, bp.BP_RAD2], None):
+        ctx.set_order(order)
+        out = ctx.lower_bounds_batch(Cs, ks, its)
+        for i in range(len(insts)):
+            same(row_dict(out[i]), want[i], ("order", order, i))
+        v, lb, rec = ctx.feasible_batch(Cs, ks, its, records=True)
+        assert np.array_equal(v, [w["verdict"] for w in want])
+        assert (rec["evals_done"] <= rec["evals"]).all()
+        assert (rec["evals_done"][rec["early_exit"] == 0] == rec["evals"][rec["early_exit"] == 0]).all()
+    with pytest.raises(bp.BpError):
+        ctx.set_order([bp.BP_MT] * 6)
+    ctx.set_order(None)
+    ctx.set_tuning(2, 32, 32, 2048)
+
+
 def test_autotuner_keeps_results(ctx):
     rng = random.Random(909)
     insts = [rand_instance(rng, cmax=50000, nmax=400) for _ in range(24)]

@@ -250,6 +250,46 @@ def test_child_request_errors(ctx):
     assert list(out[kid].bounds.argmax_lambda) == want["argmax"].tolist()
 
 
+def test_open_loop_replay(ctx):
+    # bp_queue_replay submits at the arrival times from native code, children
+    # through their parents' tickets; every record equals the node's full check
+    import ctypes
+    reqs = W.dfs_requests(4, rate=50_000.0, duration=1.0, max_requests=300)
+    say("open-loop replay of", len(reqs))
+    keep, structs = [], []
+    for i, r in enumerate(reqs):
+        if r.parent < 0:
+            res = np.ascontiguousarray(r.residual, dtype=np.int32)
+            unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
+            keep.append((res, unp))
+            structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
+                                         unp.ctypes.data_as(bp._P32), i, bp.BP_NO_EARLY_EXIT, 0, 0, None, 0, 0))
+        else:
+            cm = (bp.bp_commit * max(1, len(r.commits)))(*[bp.bp_commit(w, b) for w, b in r.commits])
+            keep.append(cm)
+            structs.append(bp.bp_request(r.C, len(r.residual), 0, None, None, i, bp.BP_NO_EARLY_EXIT, 0, 0, cm,
+                                         len(r.commits), 0))
+    n = len(reqs)
+    arr = (bp.bp_request * n)(*structs)
+    arrival = np.ascontiguousarray([r.t for r in reqs], dtype=np.float64)
+    parent = np.ascontiguousarray([r.parent for r in reqs], dtype=np.int64)
+    tickets = np.zeros(n, dtype=np.uint64)
+    status = np.zeros(n, dtype=np.int32)
+    late = ctypes.c_double(0)
+    q = bp.Queue(ctx, 8 << 30, 4096)
+    lib = bp.load()
+    st = lib.bp_queue_replay(q.handle, ctypes.cast(arr, ctypes.c_void_p), arrival.ctypes.data_as(ctypes.c_void_p),
+                             parent.ctypes.data_as(ctypes.c_void_p), n, tickets.ctypes.data_as(ctypes.c_void_p),
+                             status.ctypes.data_as(ctypes.c_void_p), ctypes.byref(late))
+    assert st == 0 and (status == 0).all() and (tickets > 0).all()
+    res = drain(q, n)
+    stats = q.stats()
+    q.close()
+    assert stats["from_parent"] > n // 2
+    by_ticket = {int(t): i for i, t in enumerate(tickets)}
+    check_against_full_path(ctx, reqs, res, by_ticket, "replay")
+
+
 def test_admission_limits(ctx):
     C, m, res, unp = W.large_residual(1)
     with pytest.raises(bp.BpError) as e:
