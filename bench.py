@@ -518,6 +518,68 @@ def bench_fidelity(bp, W, ctx, reps: int = 3):
     return res
 
 
+def bench_search(bp, W, ctx, time_limit: float = 0.5, n: int = 100, ablation: bool = False):
+    """The resolution procedure of Sec. 5 around the check, on synthetic
+    Weibull instances built as the paper builds them (scale 1000, c = sigma x
+    the largest size): n = 100, shape 0.5 .. 5.0 in steps of 0.5, sigma 1.0 ..
+    2.0 in steps of 0.2, one seed per shape (60 instances; the paper has 552
+    with n in {100, 200} and shape steps of 0.1).  Every instance is solved
+    with the DFF check (bp_feasible on the GPU) and with L1 and L2 only
+    (bp_lower_bounds with empty DFF ranges, on the GPU), under the same time
+    limit each; with ablation, the DFF search again without the dominance
+    rules and without the symmetry rules (the paper's ablation table)."""
+    import numpy as np
+
+    shapes = [0.5 * i for i in range(1, 11)]
+    sigmas = [1.0, 1.2, 1.4, 1.6, 1.8, 2.0]
+    modes = [("DFFs", bp.BP_SOLVE_DFFS, 0), ("L2", bp.BP_SOLVE_L2, 0)]
+    if ablation:
+        modes += [("DFFs_no_dominance", bp.BP_SOLVE_DFFS, bp.BP_SOLVE_OFF_FILL | bp.BP_SOLVE_OFF_SINGLE),
+                  ("DFFs_no_symmetry", bp.BP_SOLVE_DFFS, bp.BP_SOLVE_OFF_SYMMETRY),
+                  ("DFFs_no_knapsack", bp.BP_SOLVE_DFFS, bp.BP_SOLVE_OFF_KNAPSACK)]
+    insts = []
+    for shape in shapes:
+        for sigma in sigmas:
+            C, sizes = W.weibull_instance(seed=int(round(shape * 10)), n=n, shape=shape, sigma=sigma)
+            insts.append((shape, sigma, C, sizes))
+    bp.solve(insts[0][2], insts[0][3], ctx=ctx, max_nodes=1)  # warm-up (plans, graphs)
+    out = {"workload": f"{len(insts)} Weibull instances, n={n}, shape 0.5..5.0 step 0.5, sigma 1.0..2.0 step 0.2, "
+                       "scale 1000, seed = 10 x shape", "time_limit_s": time_limit, "modes": {}}
+    solved_by = {}
+    for name, mode, disable in modes:
+        agg = {"solved": 0, "solved_time_s": 0.0, "solved_nodes": 0, "nodes": 0, "checks": 0, "check_fails": 0,
+               "filter_fails": 0, "check_s": 0.0, "total_s": 0.0, "root_lb_sum": 0}
+        solved_by[name] = set()
+        for idx, (shape, sigma, C, sizes) in enumerate(insts):
+            res, bin_of = bp.solve(C, sizes, ctx=ctx, mode=mode, time_limit_s=time_limit, disable=disable)
+            load = np.bincount(bin_of, weights=sizes, minlength=res["bins"])
+            assert load.max() <= C and bin_of.max() < res["bins"], "invalid packing"
+            agg["nodes"] += res["nodes"]
+            agg["checks"] += res["checks"]
+            agg["check_fails"] += res["check_fails"]
+            agg["filter_fails"] += res["filter_fails"]
+            agg["check_s"] += res["check_seconds"]
+            agg["total_s"] += res["seconds"]
+            agg["root_lb_sum"] += res["lower"]
+            if res["status"] == bp.BP_SOLVE_OPTIMAL:
+                agg["solved"] += 1
+                agg["solved_time_s"] += res["seconds"]
+                agg["solved_nodes"] += res["nodes"]
+                solved_by[name].add(idx)
+        agg["check_us_mean"] = agg["check_s"] * 1e6 / max(1, agg["checks"])
+        agg["check_share"] = agg["check_s"] / max(1e-12, agg["total_s"])
+        out["modes"][name] = agg
+        log(f"search leg {name}: {agg['solved']}/{len(insts)} solved")
+    out["solved_only_by_DFFs"] = len(solved_by["DFFs"] - solved_by["L2"])
+    out["solved_only_by_L2"] = len(solved_by["L2"] - solved_by["DFFs"])
+    both = solved_by["DFFs"] & solved_by["L2"]
+    out["both_solved"] = len(both)
+    out["paper_weibull_table"] = {"instances": 552, "L2_solved": 375, "DFFs_GPU_solved": 418,
+                                  "DFFs_CPU_solved": 402, "time_limit_s": 600,
+                                  "note": "the paper's own runs (RTX 3080, 10 min per instance); context only"}
+    return out
+
+
 def per_bound_table(bp, W, ctx, reps: int = 5):
     """Sweep stage time of each DFF bound alone on the single large residual
     instance, dense and segment form (the other ranges empty), from the
@@ -663,6 +725,10 @@ def main():
     ap.add_argument("--no-segments", action="store_true",
                     help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
     ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--no-search", action="store_true", help="skip the Weibull search leg")
+    ap.add_argument("--search-seconds", type=float, default=0.5, help="time limit per instance and mode")
+    ap.add_argument("--search-ablation", action="store_true",
+                    help="only run the Weibull search leg, with the rule ablation, and exit")
     ap.add_argument("--latency-only", action="store_true",
                     help="only time the plain small checks (--latency-checks of them) and exit")
     ap.add_argument("--valu-rates", action="store_true",
@@ -701,6 +767,11 @@ def main():
             lat = plain_latency(bp, W, lctx, args.latency_checks)
         print(json.dumps({"plain_small_check_us": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
                                                    "n": len(lat)}}), flush=True)
+        return
+
+    if args.search_ablation:
+        with bp.Context(0) as sctx:
+            print(json.dumps({"search": bench_search(bp, W, sctx, args.search_seconds, ablation=True)}), flush=True)
         return
 
     if args.per_bound:
@@ -835,6 +906,9 @@ def main():
         log("triplet leg done")
         line["fidelity"] = bench_fidelity(bp, W, ctx)
         log("fidelity study done")
+    if not args.no_search:
+        line["search"] = bench_search(bp, W, ctx, args.search_seconds)
+        log("search leg done")
     if not args.no_served:
         line["served"] = []
         legs = [(0, 20_000.0, 3), (0, 200_000.0, 4)]

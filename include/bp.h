@@ -395,6 +395,80 @@ bp_status bp_queue_replay(bp_queue *q, bp_request *reqs, const double *arrival_s
  * requests with BP_ERR_STATE, join the thread and free everything. */
 bp_status bp_queue_destroy(bp_queue *q);
 
+/* ---- the propagator and the search around the check ---------------------- */
+
+/* A caller's feasibility check for bp_solve: the lower bound *lb of the
+ * partial packing (residual[m] of the k = m bins, unpacked[n]).  Return
+ * BP_OK, or an error that stops the search. */
+typedef bp_status (*bp_check_fn)(void *user, int32_t C, int32_t m, const int32_t *residual,
+                                 const int32_t *unpacked, int64_t n, int64_t *lb);
+
+enum { BP_SOLVE_DFFS = 0, BP_SOLVE_L2 = 1, BP_SOLVE_NO_CHECK = 2 };
+enum { BP_SOLVE_OPTIMAL = 1, BP_SOLVE_LIMIT = 0 };
+/* bp_solve_opts.disable: rules switched off (all on by default) */
+enum {
+  BP_SOLVE_OFF_KNAPSACK = 1u << 0,  /* the knapsack filtering of Alg. 1 */
+  BP_SOLVE_OFF_FILL = 1u << 1,      /* dominance: an item that fills a bin exactly goes there */
+  BP_SOLVE_OFF_SINGLE = 1u << 2,    /* dominance: a bin into which no two items fit takes the heaviest */
+  BP_SOLVE_OFF_SYMMETRY = 1u << 3   /* on backtracking, bins of the same load leave same-size items */
+};
+
+typedef struct bp_solve_opts {
+  int32_t mode;          /* the check at every node: BP_SOLVE_DFFS (the whole collection, bp_feasible),
+                            BP_SOLVE_L2 (L1 and L2 only), BP_SOLVE_NO_CHECK (filtering alone) */
+  uint32_t check_flags;  /* flags of bp_feasible for BP_SOLVE_DFFS (BP_SEGMENTS, BP_NO_EARLY_EXIT) */
+  int64_t max_nodes;     /* search nodes per attempt (0: no limit) */
+  double time_limit_s;   /* for the whole solve (0: no limit) */
+  bp_check_fn check;     /* non-NULL: this check replaces the library's (ctx may then be NULL) */
+  void *user;
+  uint32_t disable;      /* BP_SOLVE_OFF_* bits */
+  int32_t reserved;
+} bp_solve_opts;
+
+typedef struct bp_solve_result {
+  int32_t status;        /* BP_SOLVE_OPTIMAL: bins is the optimum; BP_SOLVE_LIMIT: a limit stopped an attempt */
+  int32_t bins;          /* bins of the packing returned */
+  int32_t lower;         /* the root's lower bound (the first k tried) */
+  int32_t upper;         /* first fit decreasing's bins */
+  int32_t attempts;      /* values of k tried */
+  int32_t limit_reached;
+  int64_t nodes;         /* search nodes over all attempts */
+  int64_t fails;         /* nodes whose subtree held no packing */
+  int64_t checks;        /* feasibility checks (Alg. 1) */
+  int64_t check_fails;   /* checks with lb > k */
+  double seconds;
+  double check_seconds;  /* time inside the checks */
+  int64_t filter_fails;  /* nodes the filtering rules failed before the check */
+} bp_solve_result;
+
+/* Bin packing by the paper's resolution procedure (Sec. 5): k starts at the
+ * root's lower bound and grows until an attempt packs the n items into k
+ * bins; first fit decreasing bounds it from above.  An attempt is a
+ * depth-first search with decreasing best fit, the two symmetry-breaking
+ * rules on backtracking and the two dominance rules of Sec. 5 (exact fill;
+ * the heaviest item into a bin that takes at most one more).  Every node
+ * runs the filtering of Alg. 1 (load coherence, basic load tightening, item
+ * elimination and commitment, then the same through the knapsack test of
+ * bp_subset_sum_gap) to a fixpoint and then the feasibility check of Alg. 1.
+ * The reductions and the symmetry constraint the paper's solvers add from
+ * other work are not built.  bin_of[n] (optional) receives the packing, in
+ * the caller's item order.  Sizes in [0, C], n <= BP_MAX_ITEMS.  Errors:
+ * BP_ERR_ARG (NULL, C < 1, unknown mode, the library's check without a
+ * context), BP_ERR_RANGE (a size outside [0, C]), BP_ERR_LIMIT, or the
+ * check's own error, which stops the search. */
+bp_status bp_solve(bp_ctx *ctx, int32_t C, int64_t n, const int32_t *sizes, const bp_solve_opts *opts,
+                   int32_t *bin_of, bp_solve_result *out);
+
+/* The knapsack test of the propagator (the bin packability, load tightening
+ * and item reasoning of Alg. 1 rest on it): an approximate subset-sum test
+ * over x[n], sorted non-increasing, host memory.  Returns 1 when it proves
+ * that no subset of x sums into [alpha, beta]; then every subset sum is
+ * <= *below or >= *above (*above is 2^61 - 1 when no sum exceeds beta).
+ * Returns 0 when it proves nothing (alpha <= 0 <= beta is always 0: the
+ * empty set).  BP_ERR_ARG for NULL pointers, n < 0, or x not sorted. */
+int32_t bp_subset_sum_gap(const int32_t *x, int32_t n, int64_t alpha, int64_t beta, int64_t *below,
+                          int64_t *above);
+
 /* ---- self test of the host-side division constants ----------------------- */
 
 /* Checks, on the host, the multiply-shift constants the kernels use against

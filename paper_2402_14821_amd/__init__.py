@@ -74,6 +74,25 @@ class bp_tuning(ctypes.Structure):
     _fields_ = [("lanes_params", _i32), ("waves_per_cu", _i32), ("tasks_per_wave", _i32), ("min_chunk", _i32)]
 
 
+BP_SOLVE_DFFS, BP_SOLVE_L2, BP_SOLVE_NO_CHECK = 0, 1, 2
+BP_SOLVE_LIMIT, BP_SOLVE_OPTIMAL = 0, 1
+BP_SOLVE_OFF_KNAPSACK, BP_SOLVE_OFF_FILL, BP_SOLVE_OFF_SINGLE, BP_SOLVE_OFF_SYMMETRY = 1, 2, 4, 8
+bp_check_fn = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _P32, _P32,
+                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64))
+
+
+class bp_solve_opts(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("check_flags", _u32), ("max_nodes", _i64), ("time_limit_s", ctypes.c_double),
+                ("check", bp_check_fn), ("user", ctypes.c_void_p), ("disable", _u32), ("reserved", _i32)]
+
+
+class bp_solve_result(ctypes.Structure):
+    _fields_ = [("status", _i32), ("bins", _i32), ("lower", _i32), ("upper", _i32), ("attempts", _i32),
+                ("limit_reached", _i32), ("nodes", _i64), ("fails", _i64), ("checks", _i64),
+                ("check_fails", _i64), ("seconds", ctypes.c_double), ("check_seconds", ctypes.c_double),
+                ("filter_fails", _i64)]
+
+
 class bp_queue_stats(ctypes.Structure):
     _fields_ = [("submitted", _u64), ("completed", _u64), ("rejected", _u64), ("batches", _u64),
                 ("in_flight", _u64), ("bytes_in_use", _u64), ("bytes_peak", _u64), ("budget", _u64),
@@ -132,6 +151,8 @@ _SIGNATURES = {
     "bp_queue_replay": ([_VP, _VP, _VP, _VP, _i64, _VP, _VP, ctypes.POINTER(ctypes.c_double)], _i32),
     "bp_queue_destroy": ([_VP], _i32),
     "bp_selftest_division": ([_u32, _u32, _u32, _u32], _i64),
+    "bp_solve": ([_VP, _i32, _i64, _P32, ctypes.POINTER(bp_solve_opts), _P32, ctypes.POINTER(bp_solve_result)], _i32),
+    "bp_subset_sum_gap": ([_P32, _i32, _i64, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
 }
 
 _lib = None
@@ -222,6 +243,46 @@ def feasible_dev_noalloc(C: int, m: int, d_residual_ptr: int, n: int, d_unpacked
     """bp_feasible_dev_noalloc on the current HIP device (no context)."""
     _check(load().bp_feasible_dev_noalloc(C, m, _VP(d_residual_ptr), _VP(d_unpacked_ptr), n, flags,
                                           _VP(d_out_ptr), _VP(stream_ptr)))
+
+
+def solve(C: int, sizes, ctx: "Context | None" = None, mode: int = BP_SOLVE_DFFS, check_flags: int = 0,
+          max_nodes: int = 0, time_limit_s: float = 0.0, check=None, disable: int = 0):
+    """bp_solve: (result dict, bin_of).  check(C, residual, unpacked) -> lb
+    replaces the library's check (then ctx may be None); disable holds
+    BP_SOLVE_OFF_* bits."""
+    lib = load()
+    w = _i32arr(sizes)
+    cb = bp_check_fn()
+    if check is not None:
+        def _cb(user, C_, m_, pres, punp, n_, plb):
+            try:
+                res = np.ctypeslib.as_array(pres, shape=(m_,)).copy() if m_ else np.zeros(0, np.int32)
+                unp = np.ctypeslib.as_array(punp, shape=(n_,)).copy() if n_ else np.zeros(0, np.int32)
+                plb[0] = int(check(C_, res, unp))
+                return BP_OK
+            except Exception:  # an exception cannot cross the C boundary: stop the search
+                return BP_ERR_STATE
+        cb = bp_check_fn(_cb)
+    opts = bp_solve_opts(mode, check_flags, max_nodes, time_limit_s, cb, None, disable, 0)
+    out = bp_solve_result()
+    bin_of = np.zeros(max(len(w), 1), dtype=np.int32)
+    _check(lib.bp_solve(ctx.handle if ctx is not None else None, C, len(w), _p32(w) if len(w) else None,
+                        ctypes.byref(opts), _p32(bin_of), ctypes.byref(out)))
+    res = {f: getattr(out, f) for f, _ in bp_solve_result._fields_}
+    return res, bin_of[: len(w)].copy()
+
+
+def subset_sum_gap(sizes, alpha: int, beta: int):
+    """bp_subset_sum_gap over sizes (sorted here, largest first): None when
+    nothing is proved, else (below, above) with every subset sum <= below or
+    >= above."""
+    x = np.sort(_i32arr(sizes))[::-1].copy()
+    below, above = _i64(), _i64()
+    r = load().bp_subset_sum_gap(_p32(x) if len(x) else None, len(x), alpha, beta, ctypes.byref(below),
+                                 ctypes.byref(above))
+    if r < 0:
+        _check(r)
+    return (below.value, above.value) if r == 1 else None
 
 
 def selftest_division(d_lo: int, d_hi: int, n_hi: int, mode: int) -> int:

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbp.so")
 ARCH = os.environ.get("BP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_queue.cpp"]
+SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_queue.cpp", "bp_solve.cpp"]
 # VALU issue-rate microbenchmark (bench.py --valu-rates), a library of its own
 UBENCH_SOURCES = ["bp_ubench.hip"]
 UBENCH_LIB = os.path.join(HERE, "libbp_ubench.so")

@@ -236,6 +236,10 @@ bp_status Ctx::init(int dev) {
   use_graph = !(ng && ng[0] == '1');
   const char *ns = getenv("BP_NO_SMALL_PATH");
   small_path = !(ns && ns[0] == '1');
+  if (const char *sw = getenv("BP_SMALL_PATH_WORK")) {
+    const long long v = atoll(sw);
+    if (v > 0) small_work = v;
+  }
   {
     const hipError_t e = hipHostMalloc(&small_out, sizeof(bp_bounds) + 64, hipHostMallocCoherent);
     if (e != hipSuccess) {
@@ -1069,7 +1073,7 @@ bp_status run_small(Ctx *c, const PlanIn &q, const int32_t *sizes, const int32_t
   if (nv > kSmallFusedMax) return BP_OK;
   int64_t params = 0;  // L2 and the six functions, before any VB2 cut
   for (int b = kL2; b < kNB; ++b) params += q.lo[b] <= q.hi[b] ? q.hi[b] - q.lo[b] + 1 : 0;
-  if (params * std::max<int64_t>(nv, 1) > kSmallFusedWork) return BP_OK;
+  if (params * std::max<int64_t>(nv, 1) > c->small_work) return BP_OK;
   SmallArgs a;
   memset(&a, 0, offsetof(SmallArgs, v));
   a.C = q.C;

@@ -127,6 +127,7 @@ struct Ctx {
   uint32_t small_seq = 0;
   DevBuf small_keys;  // the small check's maxima and workgroup count, zero between calls
   bool small_path = true;  // BP_NO_SMALL_PATH=1 at context creation turns the one-launch path off
+  int64_t small_work = kSmallFusedWork;  // BP_SMALL_PATH_WORK=<evals> at context creation overrides
 
   bp_status init(int dev);
   void destroy();

@@ -166,6 +166,19 @@ def windows(lo: int, hi: int, width: int):
     return [(lo, lo + width - 1), (hi - width + 1, hi)]
 
 
+# ---- Weibull instances for the search (Sec. 5) -----------------------------------
+
+def weibull_instance(seed: int, n: int = 100, shape: float = 1.0, sigma: float = 1.4, scale: float = 1000.0):
+    """n sizes from a Weibull distribution of the given shape and scale
+    (rounded, at least 1) and capacity c = sigma * max size (rounded), as the
+    paper's Weibull instances (Sec. 5: n in {100, 200}, shape 0.5 .. 5.0,
+    scale 1000, sigma in {1.0, 1.2, .., 2.0}).  Returns (C, sizes)."""
+    g = _rng(seed)
+    w = np.maximum(1, np.rint(scale * g.weibull(shape, size=n))).astype(np.int64)
+    C = int(round(sigma * int(w.max())))
+    return C, w.astype(np.int32)
+
+
 # ---- configuration 4: requests of a simulated depth-first search ---------------
 
 @dataclass

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     with open(os.path.join(ROOT, "include", "bp.h")) as fh:
         text = fh.read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|bp_status|int64_t)\s*(bp_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|bp_status|int64_t|int32_t)\s*(bp_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -35,6 +35,8 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(bp.bp_bounds) == 8 * 8 * 2 + 8 + 4 + 4 + 8 * 3 + 4 + 4 + 8
     assert ctypes.sizeof(bp.bp_batch) == 8 + 4 * 8
     assert bp.BOUNDS_DTYPE.itemsize == ctypes.sizeof(bp.bp_bounds)
+    assert ctypes.sizeof(bp.bp_solve_opts) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(bp.bp_solve_result) == 6 * 4 + 4 * 8 + 2 * 8 + 8
 
 
 def test_version_and_error_text():
