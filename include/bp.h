@@ -157,7 +157,8 @@ bp_status bp_ctx_set_tuning(bp_ctx *ctx, const bp_tuning *tuning);
 
 /* Stage timing for diagnostics and measurement.  With enable = 1 the context
  * launches the pipeline kernels one by one instead of replaying its graph and
- * records HIP events around each on the call's stream.  bp_ctx_stage_times
+ * records HIP events around each on the call's stream; every check takes the
+ * pipeline then, also one small enough for the one-launch path.  bp_ctx_stage_times
  * waits for every call made since timing was last switched on (set_timing
  * restarts the count) and returns the mean durations in milliseconds:
  * ms[0] reduction + sort + prefix (prep), ms[1] sweeps, ms[2] combine of

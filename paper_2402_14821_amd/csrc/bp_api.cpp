@@ -240,6 +240,19 @@ bp_status Ctx::init(int dev) {
     const long long v = atoll(sw);
     if (v > 0) small_work = v;
   }
+  small_grid = std::min(num_cu, kSmallFusedMaxGrid);
+  if (const char *sg = getenv("BP_SMALL_GRID")) {
+    const int v = atoi(sg);
+    if (v > 0 && v <= kSmallFusedMaxGrid) small_grid = v;
+  }
+  if (const char *sv = getenv("BP_SMALL_WAVES")) {
+    const int v = atoi(sv);
+    if (v > 0 && v <= 16) small_waves = v;
+  }
+  if (const char *si = getenv("BP_SMALL_ITEMS")) {
+    const int v = atoi(si);
+    if (v > 0 && v <= 1024) small_items = v;
+  }
   {
     const hipError_t e = hipHostMalloc(&small_out, sizeof(bp_bounds) + 64, hipHostMallocCoherent);
     if (e != hipSuccess) {
@@ -248,8 +261,7 @@ bp_status Ctx::init(int dev) {
     }
     memset(small_out, 0, sizeof(bp_bounds) + 64);
   }
-  if ((st = small_keys.reserve(sizeof(unsigned long long) * (kNB + 1)))) return st;
-  HIP_TRY(hipMemset(small_keys.p, 0, sizeof(unsigned long long) * (kNB + 1)));
+  if ((st = small_keys.reserve(kSmallBufBytes))) return st;
   // BP_SEGMENT_KCUT=K: segment tiles of BJ1 wherever floor(c / lambda) <= K
   // (0 .. 64) instead of where the cost model puts the cut; same results.
   const char *kc = getenv("BP_SEGMENT_KCUT");
@@ -1068,7 +1080,7 @@ namespace bpi {
 bp_status run_small(Ctx *c, const PlanIn &q, const int32_t *sizes, const int32_t *residual, bp_bounds *out,
                     bool *done) {
   *done = false;
-  if (!c->small_path) return BP_OK;
+  if (!c->small_path || c->timing) return BP_OK;  // stage timing measures the pipeline
   const int64_t nv = q.n_in + (q.form == kFormResidual ? q.m_res : 0);
   if (nv > kSmallFusedMax) return BP_OK;
   int64_t params = 0;  // L2 and the six functions, before any VB2 cut
@@ -1086,17 +1098,21 @@ bp_status run_small(Ctx *c, const PlanIn &q, const int32_t *sizes, const int32_t
     a.hi[b] = q.hi[b];
   }
   a.clamp = q.clamp ? 1u : 0u;
-  // about eight items per lane
+  // S lanes per (bound, parameter) pair, each summing every S-th item: about
+  // small_items items per lane, and no more lanes than small_waves waves per
+  // SIMD hold (four SIMDs per compute unit)
   a.slices = 1;
-  while (a.slices < 64 && (int64_t)a.slices * 8 < nv) a.slices <<= 1;
+  while (a.slices < 64 && (int64_t)a.slices * c->small_items < nv &&
+         params * a.slices < (int64_t)c->num_cu * 4 * 64 * c->small_waves)
+    a.slices <<= 1;
   if (q.n_in) memcpy(a.v, sizes, sizeof(int32_t) * (size_t)q.n_in);
   if (a.m) memcpy(a.v + q.n_in, residual, sizeof(int32_t) * (size_t)a.m);
   bp_bounds *h = (bp_bounds *)c->small_out;
   uint32_t *seq = (uint32_t *)((char *)c->small_out + sizeof(bp_bounds));
   const uint32_t want = ++c->small_seq;
   const int grid = (int)std::min<int64_t>(
-      kSmallFusedMaxGrid, std::max<int64_t>(1, (params * a.slices + kSmallFusedThreads - 1) / kSmallFusedThreads));
-  HIP_TRY(launch_small_check(a, grid, (unsigned long long *)c->small_keys.p, h, seq, want, c->stream));
+      c->small_grid, std::max<int64_t>(1, (params * a.slices + kSmallFusedThreads - 1) / kSmallFusedThreads));
+  HIP_TRY(launch_small_check(a, grid, c->small_keys.p, h, seq, want, c->stream));
   // Wait for the kernel's sequence number in host memory; after two seconds
   // without it, let the stream report what went wrong.
   const auto t0 = std::chrono::steady_clock::now();

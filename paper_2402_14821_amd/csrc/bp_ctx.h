@@ -26,8 +26,8 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_pre
                                  hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
                              long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s);
-hipError_t launch_small_check(const SmallArgs &a, int grid, unsigned long long *gkeys, bp_bounds *out,
-                              uint32_t *seq_out, uint32_t seq, hipStream_t s);
+hipError_t launch_small_check(const SmallArgs &a, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
+                              uint32_t seq, hipStream_t s);
 hipError_t noalloc_scratch(int device, unsigned char **out);
 hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
                           int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
@@ -125,9 +125,12 @@ struct Ctx {
   // to this coherent host memory: [bp_bounds][uint32 sequence].
   void *small_out = nullptr;
   uint32_t small_seq = 0;
-  DevBuf small_keys;  // the small check's maxima and workgroup count, zero between calls
+  DevBuf small_keys;  // the small check's per-workgroup maxima and head (kSmallBufBytes)
   bool small_path = true;  // BP_NO_SMALL_PATH=1 at context creation turns the one-launch path off
   int64_t small_work = kSmallFusedWork;  // BP_SMALL_PATH_WORK=<evals> at context creation overrides
+  int small_grid = 0;                    // at most this many workgroups (default: one per compute unit; BP_SMALL_GRID)
+  int small_items = 8;                   // BP_SMALL_ITEMS=<items per lane>
+  int small_waves = 4;                   // BP_SMALL_WAVES=<waves per SIMD the lanes may fill>
 
   bp_status init(int dev);
   void destroy();

@@ -215,14 +215,24 @@ __host__ __device__ inline int64_t node_tiles(int32_t C) {
   return n;
 }
 
-// Small checks in one launch (k_small_check): the instance travels in the
-// kernel arguments, one workgroup computes the whole record and writes it to
-// host memory.  Used for at most kSmallFusedMax input values and at most
-// kSmallFusedWork (item, parameter) evaluations.
+// Small checks in one launch (k_small_check, then k_small_final): the
+// instance travels in the kernel arguments, the workgroups split the (bound,
+// parameter) pairs and write their maxima, and a one-workgroup kernel after
+// them writes the record to host memory.  Used for at most kSmallFusedMax
+// input values and at most Ctx::small_work (item, parameter) evaluations.
 constexpr int kSmallFusedMax = 960;
-constexpr int64_t kSmallFusedWork = int64_t(1) << 18;
-constexpr int kSmallFusedThreads = 256;  // per workgroup; one parameter per thread, as many workgroups as needed
-constexpr int kSmallFusedMaxGrid = 256;
+constexpr int64_t kSmallFusedWork = int64_t(1) << 26;  // below the pipeline's time up to about 1e8 evaluations
+constexpr int kSmallFusedThreads = 1024;  // per workgroup
+constexpr int kSmallFusedMaxGrid = 2048;
+// what workgroup 0 of k_small_check leaves for k_small_final
+struct SmallHead {
+  uint64_t tot_w;  // sum of the reduced sizes
+  int64_t evals;   // r x the DFF parameters after any VB2 cut
+  int32_t r;
+  int32_t bad;     // a size or residual outside [0, C]
+};
+// the buffer: kNB keys per workgroup, then the head
+constexpr size_t kSmallBufBytes = sizeof(unsigned long long) * kNB * kSmallFusedMaxGrid + sizeof(SmallHead);
 struct SmallArgs {
   int32_t C;
   int32_t m;       // residual form: bins given as residuals (after the n sizes)

@@ -1847,20 +1847,21 @@ __global__ __launch_bounds__(256) void k_node_finalize(const NodeTask *__restric
 // Small checks in one launch.  Every workgroup rebuilds the reduced instance
 // of Fig. 3 in its LDS (sizes, then one virtual item per loaded bin) from the
 // kernel arguments, with its totals, then takes its share of the (bound,
-// parameter) pairs, one per thread: the exact per-lane f of Sec. 3.1
-// (dff_term) summed over the items, or L2(I, lambda) from its three classes.
-// The workgroups' packed maxima meet in gkeys[0..kNB) (one atomic maximum per
-// bound per workgroup); the last workgroup to finish, counted in gkeys[kNB],
-// writes the record to `out` (host memory), clears gkeys for the next call
-// and then publishes `seq`.
+// parameter) pairs, S lanes per pair: the exact f of Sec. 3.1 summed over
+// the items, or L2(I, lambda) from its three classes.  Each workgroup writes
+// its packed maxima to its own slots with plain stores (no atomics, no
+// fences: a device-scope fence or atomic per workgroup costs more than the
+// sums at these sizes); k_small_final, next on the stream, takes the maxima
+// over the workgroups, writes the record to `out` (host memory) and then
+// publishes `seq`.
 
-__global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a, unsigned long long *gkeys,
-                                                                   bp_bounds *out, uint32_t *seq_out, uint32_t seq) {
+__global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a, unsigned long long *part,
+                                                                   SmallHead *head) {
   __shared__ uint32_t w[kSmallFusedMax];
   __shared__ uint32_t wsum[kSmallFusedThreads / 64];
   __shared__ unsigned long long key[kNB];
   __shared__ unsigned long long tot_w;
-  __shared__ int32_t nbig_s, maxw_s, bad_s, last_s;
+  __shared__ int32_t nbig_s, maxw_s, bad_s;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const uint32_t C = (uint32_t)a.C;
@@ -1926,12 +1927,13 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
   for (int b = kL2; b < kNB; ++b) total += a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
   const double rc = 1.0 / (double)C;
   const int S = a.slices;
+  const int sh = __builtin_ctz((unsigned)S);
   const int sl = tid & (S - 1);
   unsigned long long best[kNB] = {};
   for (int64_t gt = (int64_t)blockIdx.x * kSmallFusedThreads + tid; gt < total * S;
        gt += (int64_t)gridDim.x * kSmallFusedThreads) {
     int b = kL2;
-    int64_t idx = gt / S;
+    int64_t idx = gt >> sh;
     for (; b < kNB; ++b) {
       const int64_t len = a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
       if (idx < len) break;
@@ -1982,50 +1984,71 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
     if (lane_id() == 0 && m) atomicMax(&key[q], (unsigned long long)m);
   }
   __syncthreads();
-  if (tid < kNB && key[tid]) atomicMax(&gkeys[tid], key[tid]);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) last_s = atomicAdd(&gkeys[kNB], 1ull) == gridDim.x - 1 ? 1 : 0;
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  if (tid == 0) {
-    unsigned long long gk[kNB];
-    for (int b = 0; b < kNB; ++b) gk[b] = __hip_atomic_load(&gkeys[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bp_bounds o;
-    o.k = a.k;
-    o.r = r;
-    o.status = bad_s ? BP_ERR_RANGE : BP_OK;
-    o.early_exit = 0;
+  if (tid < kNB) part[(size_t)blockIdx.x * kNB + tid] = key[tid];
+  if (blockIdx.x == 0 && tid == 0) {
     int64_t P = 0;
     for (int b = kMT; b < kNB; ++b) P += a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
-    o.evals = (int64_t)r * P;
-    o.evals_done = o.evals;
-    o.value[kL1] = r > 0 ? (int64_t)((tot_w + C - 1) / C) : 0;
+    SmallHead h;
+    h.tot_w = tot_w;
+    h.evals = (int64_t)r * P;
+    h.r = r;
+    h.bad = bad_s;
+    *head = h;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_small_final(const unsigned long long *part, int grid,
+                                                      const SmallHead *head, uint32_t C, int64_t k, bp_bounds *out,
+                                                      uint32_t *seq_out, uint32_t seq) {
+  __shared__ unsigned long long red[256];
+  const int tid = threadIdx.x;
+  const int b = tid & (kNB - 1);
+  unsigned long long mx = 0ull;
+  for (int g = tid / kNB; g < grid; g += 256 / kNB) mx = umax64(mx, part[(size_t)g * kNB + b]);
+  red[tid] = mx;
+  __syncthreads();
+  for (int st = 128; st >= kNB; st >>= 1) {
+    if (tid < st) red[tid] = umax64(red[tid], red[tid + st]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const SmallHead h = *head;
+    bp_bounds o;
+    o.k = k;
+    o.r = h.r;
+    o.status = h.bad ? BP_ERR_RANGE : BP_OK;
+    o.early_exit = 0;
+    o.evals = h.evals;
+    o.evals_done = h.evals;
+    o.value[kL1] = h.r > 0 ? (int64_t)((h.tot_w + C - 1) / C) : 0;
     o.argmax_lambda[kL1] = -1;
-    for (int b = kL2; b < kNB; ++b) {
-      o.value[b] = gk[b] ? (int64_t)(gk[b] >> 32) : 0;
-      o.argmax_lambda[b] = gk[b] ? (int64_t)(0xffffffffu - (uint32_t)gk[b]) : -1;
+    for (int q = kL2; q < kNB; ++q) {
+      const unsigned long long gk = red[q];
+      o.value[q] = gk ? (int64_t)(gk >> 32) : 0;
+      o.argmax_lambda[q] = gk ? (int64_t)(0xffffffffu - (uint32_t)gk) : -1;
     }
     int64_t lb = -1;
     int32_t arg = 0;
-    for (int b = 0; b < kNB; ++b)
-      if (o.value[b] > lb) { lb = o.value[b]; arg = b; }
+    for (int q = 0; q < kNB; ++q)
+      if (o.value[q] > lb) { lb = o.value[q]; arg = q; }
     o.lb = lb;
     o.lb_arg = arg;
-    o.verdict = lb <= a.k ? 1 : 0;
+    o.verdict = lb <= k ? 1 : 0;
     *out = o;
-    // clean for the next call (every other workgroup is done with gkeys)
-    for (int b = 0; b <= kNB; ++b) __hip_atomic_store(&gkeys[b], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the record is visible to the host before the sequence number that announces it
     __threadfence_system();
     __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
-hipError_t launch_small_check(const SmallArgs &a, int grid, unsigned long long *gkeys, bp_bounds *out,
-                              uint32_t *seq_out, uint32_t seq, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_check, dim3(grid), dim3(kSmallFusedThreads), 0, s, a, gkeys, out, seq_out, seq);
+hipError_t launch_small_check(const SmallArgs &a, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
+                              uint32_t seq, hipStream_t s) {
+  if (grid < 1 || grid > kSmallFusedMaxGrid) return hipErrorInvalidValue;
+  unsigned long long *part = (unsigned long long *)buf;
+  SmallHead *head = (SmallHead *)(part + (size_t)kNB * kSmallFusedMaxGrid);
+  hipLaunchKernelGGL(k_small_check, dim3(grid), dim3(kSmallFusedThreads), 0, s, a, part, head);
+  hipLaunchKernelGGL(k_small_final, dim3(1), dim3(256), 0, s, (const unsigned long long *)part, grid,
+                     (const SmallHead *)head, (uint32_t)a.C, a.k, out, seq_out, seq);
   return hipGetLastError();
 }
 

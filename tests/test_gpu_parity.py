@@ -111,6 +111,32 @@ def test_small_checks_on_both_paths(ctx, ctx_pipe):
             assert c.feasible(C, res, unp)["verdict"] == want["verdict"]
 
 
+def test_small_path_at_larger_capacities(ctx, ctx_pipe):
+    # the one-launch path takes checks up to 2^26 evaluations: capacities up
+    # to 92 500 and up to 960 inputs, in both forms, with one lane or several
+    # per parameter and more pairs than one pass of the grid holds
+    g = np.random.default_rng(77)
+    cases = [(2500, 100, 50), (2500, 900, 60), (10000, 300, 0), (30000, 150, 60), (92500, 150, 60),
+             (92500, 30, 10), (15000, 600, 300), (1, 5, 3), (7, 0, 12)]
+    for C, n, m in cases:
+        unp = np.minimum(C, np.maximum(0, (C * g.uniform(0.0, 0.8, n)).astype(np.int32))).astype(np.int32)
+        res = (C * g.uniform(0, 1, m)).astype(np.int32)
+        res[: m // 5] = C  # some empty bins
+        if m:
+            want = O.bounds(C, m, O.residual_reduce(C, res, unp))
+            for c, name in ((ctx, "one launch"), (ctx_pipe, "pipeline")):
+                say("small path larger", C, n, m, name)
+                got = c.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT)
+                same(got, want, (name, C, n, m))
+                assert got["evals_done"] == got["evals"]
+        else:
+            k = int(g.integers(0, n + 1))
+            want = O.bounds(C, k, list(unp))
+            for c, name in ((ctx, "one launch"), (ctx_pipe, "pipeline")):
+                say("small path larger items", C, n, name)
+                same(c.lower_bounds(C, k, unp, bp.default_sweep(C)), want, (name, C, n))
+
+
 def test_fig3_worked_example(ctx):
     g = fig3()
     C, k = g["C"][0], g["bins"][0]
