@@ -234,6 +234,8 @@ bp_status Ctx::init(int dev) {
   grid_fin = 64;
   const char *ng = getenv("BP_NO_GRAPH");
   use_graph = !(ng && ng[0] == '1');
+  const char *nv = getenv("BP_NO_VALUE_PREP");
+  value_prep = !(nv && nv[0] == '1');
   const char *ns = getenv("BP_NO_SMALL_PATH");
   small_path = !(ns && ns[0] == '1');
   if (const char *sw = getenv("BP_SMALL_PATH_WORK")) {
@@ -275,7 +277,8 @@ void Ctx::destroy() {
   if (last_run && any_run) (void)hipEventSynchronize(last_run);
   drop_graphs();
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
-                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf, &small_keys})
+                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf, &small_keys, &vcnt_buf, &vsum_buf, &vtot_buf,
+                    &vlat_buf, &vflag_buf})
     b->release();
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (small_out) (void)hipHostFree(small_out);
@@ -334,15 +337,18 @@ static int pow2_at_least(int64_t x) {
 // dispatching thousands of waves that would find no task.
 Ctx::LaunchShape Ctx::shape_of(int64_t count, int64_t ntasks) const {
   bool with_large = false;
-  for (int64_t i = 0; i < count && !with_large; ++i) with_large = plan_vec[i].large != 0;
+  for (int64_t i = 0; i < count && !with_large; ++i) with_large = plan_vec[i].large == 1;
   LaunchShape sh;
   sh.v = (with_large ? 1 : 0) | (nsplit > 0 ? 2 : 0);
   sh.lpl = tune.lanes_params;
-  sh.prep_small = std::min(grid_prep_small, pow2_at_least(std::max<int64_t>(count, 1)));
+  // (the small-instance prep kernel also counts the sizes of value-table instances)
+  sh.prep_small = std::min(grid_prep_small, pow2_at_least(std::max<int64_t>(count, vt_list.empty() ? 1 : 64)));
   sh.prep_large = std::min(grid_prep_large, pow2_at_least(std::max<int64_t>(count, 1)));
+  sh.vt = vt_list.empty() ? 0 : std::max(1, num_cu);
   sh.sweep = std::min(grid_sweep, std::max(64, pow2_at_least(ntasks)));
   sh.comb = std::min(grid_comb, pow2_at_least(std::max<int64_t>(nsplit, 1)));
-  sh.fin = std::min(grid_fin, pow2_at_least((count + 255) / 256));
+  // the value tables' counts are cleared by the finalize grid
+  sh.fin = std::min(grid_fin, std::max(vt_list.empty() ? 1 : 16, pow2_at_least((count + 255) / 256)));
   return sh;
 }
 
@@ -369,7 +375,8 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hip
     graph_used.erase(lru);
   }
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, (sh.v & 1) != 0,
+  hipError_t le = launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin,
+                                  (sh.v & 1) != 0,
                                   (sh.v & 2) != 0, stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
@@ -400,8 +407,9 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   const int64_t count = (int64_t)pin.size();
   std::vector<InstPlan> &pl = plan_vec;
   pl.assign((size_t)count, InstPlan{});
-  int64_t ws = 0, pre = 0, bidx = 0, dcnt = 0;
+  int64_t ws = 0, pre = 0, bidx = 0, dcnt = 0, vt = 0, vtt = 0, vl = 0;
   div_vec.clear();
+  vt_list.clear();
   std::vector<Entry> ent;
   std::vector<double> tile_cost_v;
   std::vector<int64_t> rcap_v;
@@ -425,6 +433,15 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
                   (long long)i, (long long)rcap, kLargeCap);
     p.r_cap = (int32_t)rcap;
     p.large = rcap > kSmallCap ? 1 : 0;
+    if (p.large && value_prep && q.C <= kVtMaxC && (int64_t)q.C <= kVtRatio * rcap) {
+      // prepared from value tables by kernels over the whole GPU
+      p.large = 2;
+      p.vt_off = vt;
+      vt += (int64_t)q.C + 2;
+      p.vtt_off = vtt;
+      vtt += 4 * (((int64_t)q.C + 2 + kVtChunk - 1) / kVtChunk);
+      vt_list.push_back((int32_t)i);
+    }
     p.flags = (q.clamp ? kPlanClampVB2 : 0u) | (q.early_exit ? kPlanEarlyExit : 0u);
     p.state_off = q.state_off;
     if (q.state_off >= 0) {
@@ -576,8 +593,15 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       e.ntiles = (nl + tile - 1) / tile;
       push(e, dense_tc);
     }
+    if (p.large == 2 && p.ndiv > 0) {
+      p.vl_off = vl;
+      vl += 2 * (int64_t)p.ndiv;
+    }
   }
   ws_items = ws;
+  vt_items = vt;
+  vtt_items = vtt;
+  vl_items = vl;
   pre_items = pre;
   bidx_items = bidx;
   dcnt_items = dcnt;
@@ -679,7 +703,8 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   const size_t off_plan = align256(sizeof(LaunchDesc));
   const size_t off_ent = off_plan + align256(sizeof(InstPlan) * (size_t)count);
   const size_t off_div = off_ent + align256(sizeof(Entry) * entry_vec.size());
-  const size_t off_in = off_div + align256(sizeof(int32_t) * std::max<size_t>(div_vec.size(), 1));
+  const size_t off_vl = off_div + align256(sizeof(int32_t) * std::max<size_t>(div_vec.size(), 1));
+  const size_t off_in = off_vl + align256(sizeof(int32_t) * std::max<size_t>(vt_list.size(), 1));
   const size_t total = off_in + (host_in ? align256(sizeof(int32_t) * (size_t)std::max<int64_t>(host_in_len, 1)) : 0);
   if ((st = stage_host.reserve(total))) return st;
   void *old_dev = stage_buf.p;
@@ -694,6 +719,18 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if ((st = reserve_dev(acc_buf, sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
   if ((st = reserve_dev(bidx_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(bidx_items, 1)))) return st;
   if ((st = reserve_dev(dcnt_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(dcnt_items, 1)))) return st;
+  // value tables: the counts and lattice bins are zero at rest (a new
+  // allocation is cleared here, each launch clears what it used)
+  bool clear_vt = false;
+  if (!vt_list.empty()) {
+    const void *old_c = vcnt_buf.p, *old_l = vlat_buf.p, *old_f = vflag_buf.p;
+    if ((st = reserve_dev(vcnt_buf, sizeof(int32_t) * (size_t)vt_items))) return st;
+    if ((st = reserve_dev(vsum_buf, sizeof(long long) * (size_t)vt_items))) return st;
+    if ((st = reserve_dev(vtot_buf, sizeof(long long) * (size_t)std::max<int64_t>(vtt_items, 1)))) return st;
+    if ((st = reserve_dev(vlat_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(vl_items, 1)))) return st;
+    if ((st = reserve_dev(vflag_buf, sizeof(int32_t) * vt_list.size()))) return st;
+    clear_vt = vt_dirty || vcnt_buf.p != old_c || vlat_buf.p != old_l || vflag_buf.p != old_f;
+  }
   char *h = (char *)stage_host.p;
   char *dv = (char *)stage_buf.p;
   LaunchDesc *d = (LaunchDesc *)h;
@@ -714,6 +751,13 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->divs = (const int32_t *)(dv + off_div);
   d->dcnt = (int32_t *)dcnt_buf.p;
   d->nodes = nodes;
+  d->vcnt = (int32_t *)vcnt_buf.p;
+  d->vsum = (long long *)vsum_buf.p;
+  d->vtot = (long long *)vtot_buf.p;
+  d->vlat = (int32_t *)vlat_buf.p;
+  d->vflag = (int32_t *)vflag_buf.p;
+  d->vlist = (const int32_t *)(dv + off_vl);
+  d->nvt = (int64_t)vt_list.size();
   for (int64_t i = 0; i < count; ++i)
     if (plan_vec[(size_t)i].state_off >= 0 && !nodes)
       return fail(BP_ERR_STATE, "instance %lld asks for a node state but the context has no node arena", (long long)i);
@@ -726,29 +770,42 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   memcpy(h + off_plan, plan_vec.data(), sizeof(InstPlan) * (size_t)count);
   memcpy(h + off_ent, entry_vec.data(), sizeof(Entry) * entry_vec.size());
   if (!div_vec.empty()) memcpy(h + off_div, div_vec.data(), sizeof(int32_t) * div_vec.size());
+  if (!vt_list.empty()) memcpy(h + off_vl, vt_list.data(), sizeof(int32_t) * vt_list.size());
   if (host_in && host_in_len > 0) memcpy(h + off_in, host_in, sizeof(int32_t) * (size_t)host_in_len);
   if (any_run) HIP_TRY(hipStreamWaitEvent(s, last_run, 0));
   HIP_TRY(hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(staged, s));
+  if (!vt_list.empty()) {
+    if (clear_vt) {
+      // outside any captured graph: a plain stream operation before the launch
+      HIP_TRY(hipMemsetAsync(vcnt_buf.p, 0, vcnt_buf.cap, s));
+      HIP_TRY(hipMemsetAsync(vlat_buf.p, 0, vlat_buf.cap, s));
+      HIP_TRY(hipMemsetAsync(vflag_buf.p, 0, vflag_buf.cap, s));
+    }
+    vt_dirty = true;  // until the whole launch is queued
+  }
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
   const LaunchShape sh = shape_of(count, ntasks);
   const bool with_large = (sh.v & 1) != 0, with_combine = (sh.v & 2) != 0;
   if (timing) {
     hipEvent_t *ev = nullptr;
     if ((st = timing_slot(&ev))) return st;
-    HIP_TRY(launch_pipeline_timed(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, with_large,
+    HIP_TRY(launch_pipeline_timed(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin,
+                                  with_large,
                                   with_combine, s, ev));
   } else if (use_graph) {
     hipGraphExec_t ex = nullptr;
     if ((st = ensure_graph(d_desc, sh, &ex))) return st;
     HIP_TRY(hipGraphLaunch(ex, s));
   } else {
-    HIP_TRY(launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, with_large,
+    HIP_TRY(launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin,
+                            with_large,
                             with_combine, s));
   }
   HIP_TRY(hipEventRecord(last_run, s));
   any_run = true;
   ++run_count;
+  if (!vt_list.empty()) vt_dirty = false;  // queued whole: its finalize clears the tables
   return BP_OK;
 }
 
@@ -1236,6 +1293,7 @@ bp_status bp_feasible_dev_noalloc(int32_t C, int32_t m, const int32_t *d_residua
   }
   planner.tune = bp_tuning{2, 32, 32, 2048};
   planner.apply_tuning();
+  planner.value_prep = false;  // no value tables in the static workspace
   std::vector<PlanIn> pin(1);
   bp_status st = make_plan_in(C, m, n, m, kFormResidual, nullptr, !(flags & BP_NO_EARLY_EXIT), &pin[0], false);
   if (st) return st;

@@ -19,11 +19,12 @@ void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]);
 
 // kernels (bp_kernels.hip)
 hipError_t set_kernel_attrs();
-hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                           int grid_comb, int grid_fin, bool with_large, bool with_combine, hipStream_t s);
+hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_vt,
+                           int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
+                           hipStream_t s);
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
-                                 hipStream_t s, hipEvent_t ev[4]);
+                                 int grid_vt, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
+                                 bool with_combine, hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
                              long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s);
 hipError_t launch_small_check(const SmallArgs &a, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
@@ -82,14 +83,15 @@ struct Ctx {
   hipEvent_t tev[kTimingRing][4] = {};
   int64_t t_runs = 0, t_folded = 0;
   double t_sum[3] = {0, 0, 0};
-  // Grids and kernels of one launch: variant bit 0 = large-instance prep, bit
-  // 1 = combine; each grid at most the machine-filling size of its kernel.
+  // Grids and kernels of one launch: variant bit 0 = large-instance prep
+  // block, bit 1 = combine; vt = grid of the value-table prep (0: none);
+  // each grid at most the machine-filling size of its kernel.
   struct LaunchShape {
-    int v, lpl, prep_small, prep_large, sweep, comb, fin;
+    int v, lpl, prep_small, prep_large, vt, sweep, comb, fin;
     bool operator<(const LaunchShape &o) const {
-      const int a[7] = {v, lpl, prep_small, prep_large, sweep, comb, fin};
-      const int b[7] = {o.v, o.lpl, o.prep_small, o.prep_large, o.sweep, o.comb, o.fin};
-      for (int i = 0; i < 7; ++i)
+      const int a[8] = {v, lpl, prep_small, prep_large, vt, sweep, comb, fin};
+      const int b[8] = {o.v, o.lpl, o.prep_small, o.prep_large, o.vt, o.sweep, o.comb, o.fin};
+      for (int i = 0; i < 8; ++i)
         if (a[i] != b[i]) return a[i] < b[i];
       return false;
     }
@@ -107,6 +109,13 @@ struct Ctx {
   void drop_graphs();
   LaunchShape shape_of(int64_t count, int64_t ntasks) const;
   int64_t ws_items = 0, pre_items = 0, bidx_items = 0, dcnt_items = 0, nentries = 0, acc_len = 0, nsplit = 0;
+  // value-table prep (InstPlan::large == 2): table entries, chunk words and
+  // lattice bins of this launch, its instances, and whether the planner may
+  // choose it (BP_NO_VALUE_PREP=1 at context creation: never)
+  int64_t vt_items = 0, vtt_items = 0, vl_items = 0;
+  std::vector<int32_t> vt_list;
+  bool value_prep = true;
+  bool vt_dirty = false;  // a launch with value tables was not queued whole: clear them before the next
   std::vector<int32_t> div_vec;  // divisor lists of this launch (staged with the plan)
   // divisors of c by c, and c's divisor lattice: per divisor its bin
   // sum_j e_j stride_j (e_j its exponent of the j-th prime of c, stride_j =
@@ -119,7 +128,7 @@ struct Ctx {
   std::vector<Entry> entry_vec;
 
   DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, out_buf,
-      red_buf, bidx_buf, dcnt_buf;
+      red_buf, bidx_buf, dcnt_buf, vcnt_buf, vsum_buf, vtot_buf, vlat_buf, vflag_buf;
   HostBuf stage_host, in_host, out_host, red_host;
   // The one-launch small check writes its record, then its sequence number,
   // to this coherent host memory: [bp_bounds][uint32 sequence].

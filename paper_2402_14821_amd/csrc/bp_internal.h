@@ -33,6 +33,17 @@ constexpr int kSmallCap = 8192;         // items per small-instance prep block (
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
 static_assert(kLargeCap == BP_MAX_ITEMS, "the check's item limit is the large prep block's capacity");
+// Value-table prep of large instances (several kernels over the whole GPU
+// instead of one block): a count per size value, suffix-scanned into
+// #{w >= v} and sum{w : w >= v}, from which the sorted sizes, their prefix
+// sums, the class bounds and the threshold tables are read off.  Used when
+// the instance is large and c is at most kVtMaxC and kVtRatio times its
+// reduced count (the tables hold c + 2 entries).
+constexpr int kVtChunk = 2048;           // values per block of the suffix scan
+constexpr int kVtThreads = 256;
+constexpr int32_t kVtMaxC = 1 << 21;
+constexpr int64_t kVtRatio = 16;
+constexpr int kVtMaxChunks = (kVtMaxC + 2 + kVtChunk - 1) / kVtChunk;
 
 // Input form of an instance.
 enum : int32_t { kFormItems = 0, kFormResidual = 1 };
@@ -52,7 +63,7 @@ struct InstPlan {
   int32_t form;
   int32_t r_cap;     // n_in + m_res: upper bound of the reduced count
   uint32_t flags;    // kPlanClampVB2 | kPlanEarlyExit | kPlanSegments
-  int32_t large;     // 1: prepared by the large-instance block
+  int32_t large;     // 1: prepared by the large-instance block; 2: by the value-table kernels
   int32_t bshift;    // kPlanSegments: bucket width 2^bshift of the threshold table
   int32_t nbk;       // kPlanSegments: entries of the threshold table
   int64_t bidx_off;  // kPlanSegments: offset of the threshold table
@@ -61,6 +72,9 @@ struct InstPlan {
   int32_t ndiv;      // divisors of c listed for the mirrored VB2 tiles (0: none)
   int32_t pad2;
   int64_t state_off; // >= 0: the instance's node state (see node_layout) at LaunchDesc::nodes + state_off
+  int64_t vt_off;    // large == 2: offset of the c + 2 value-table entries (LaunchDesc::vcnt, vsum)
+  int64_t vtt_off;   // large == 2: offset of the chunk totals, then the chunk offsets (2 x 2 x chunks, LaunchDesc::vtot)
+  int64_t vl_off;    // large == 2, ndiv > 0: offset of the 2 x ndiv lattice bins (LaunchDesc::vlat)
 };
 constexpr uint32_t kPlanClampVB2 = 1u;
 constexpr uint32_t kPlanEarlyExit = 2u;
@@ -131,6 +145,13 @@ struct LaunchDesc {
   const int32_t *divs;      // per mirrored instance: divisors of c (ascending), their lattice bins, prime count, (prime, exponent) pairs
   int32_t *dcnt;            // per divisor d: #{small sizes divisible by d}, then the same for big sizes
   long long *nodes;         // node-state arena of served requests (InstPlan::state_off)
+  int32_t *vcnt;            // value tables (large == 2): counts per size, then #{w >= v} within the chunk; zero between launches
+  long long *vsum;          //   sum{w >= v} within the chunk
+  long long *vtot;          //   per chunk: (count, sum) totals, then (count, sum) of the chunks above it
+  int32_t *vlat;            //   divisor-lattice bins of the mirrored VB2; zero between launches
+  int32_t *vflag;           //   per listed instance: an input outside [0, c] was seen; zero between launches
+  const int32_t *vlist;     //   the instances prepared this way
+  int64_t nvt;
   bp_bounds *out;           // [count] results
   int64_t count;            // instances
   int64_t nentries;

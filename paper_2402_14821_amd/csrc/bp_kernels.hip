@@ -569,17 +569,379 @@ __device__ void clear_sweep_state(const LaunchDesc &d) {
   if (blockIdx.x == 0 && threadIdx.x < kQueues) d.counter[threadIdx.x * kQueueStride] = 0ull;
 }
 
+// Every reduced size of the value-table instances adds 1 to its value's
+// count: a grid-stride loop of the small-instance prep kernel, which runs
+// first in every launch (the counts are zero then).  A size or residual
+// outside [0, c] sets the instance's flag.
+__device__ void vt_hist(const LaunchDesc &d) {
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t jj = 0; jj < d.nvt; ++jj) {
+    const int64_t inst = d.vlist[jj];
+    const BP_CONST InstPlan &p = as_const(d.plan)[inst];
+    const int32_t C = p.C;
+    const int64_t tot = p.n_in + (p.form == kFormResidual ? p.m_res : 0);
+    int32_t *cnt = d.vcnt + p.vt_off;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += gsz) {
+      int32_t w;
+      if (i < p.n_in) {
+        w = d.in[p.in_off + i];
+        if (w < 0 || w > C) {
+          bad = true;
+          continue;
+        }
+      } else {
+        const int32_t res = d.in2[p.res_off + (i - p.n_in)];
+        if (res < 0 || res > C) {
+          bad = true;
+          continue;
+        }
+        if (res == C) continue;  // an empty bin adds no virtual item (Fig. 3)
+        w = C - res;
+      }
+      atomicAdd(&cnt[w], 1);
+    }
+    if (bad) atomicOr(&d.vflag[jj], 1);
+  }
+}
+
 template <int NT, int CAP, int LARGE>
 __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   PrepSmem<NT, CAP> &sm = *reinterpret_cast<PrepSmem<NT, CAP> *>(smem_raw);
   const LaunchDesc d = *as_const(dp);
-  if (!LARGE) clear_sweep_state(d);
+  if (!LARGE) {
+    clear_sweep_state(d);
+    vt_hist(d);
+  }
   for (int64_t inst = blockIdx.x; inst < d.count; inst += gridDim.x) {
     if (as_const(d.plan)[inst].large != LARGE) continue;
     prep_instance<NT, CAP>(d, inst, sm);
     __syncthreads();
     if (threadIdx.x == 0) prep_finish(d, inst);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Value-table prep of large instances (InstPlan::large == 2), over the whole
+// GPU instead of one block:
+//   vt_hist    every reduced size adds 1 to the count of its value (in the
+//              small-instance prep kernel, which runs first);
+//   k_vt_scan  per chunk of kVtChunk values, suffix sums of the counts and
+//              of count x value within the chunk, and the chunk totals; for
+//              a mirrored VB2, each value present adds its count to its
+//              divisor-lattice bin (per block in LDS, then one atomic per bin);
+//   k_vt_emit  the chunks' offsets (suffix sums of the totals, in LDS), then
+//              per chunk every value v present fills its run of sorted
+//              positions [#{w > v}, #{w >= v}) with v, av and the prefix
+//              sums; the threshold table, the multiple counts of the mirrored
+//              VB2 and the instance state are read off the same tables.
+// The counts, lattice bins and input flags are zero at the start of a
+// launch: the allocation clears them, and k_finalize clears what a launch
+// used.
+
+// Block-wide inclusive scan of two 64-bit sums (kVtThreads threads); also
+// returns the block totals.  Uses red[2][kVtThreads / 64].
+__device__ __forceinline__ void vt_block_scan(uint64_t a, uint64_t b, uint64_t (*red)[kVtThreads / 64],
+                                              uint64_t *ia, uint64_t *ib, uint64_t *ta, uint64_t *tb) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t sa = wave_incl_scan_u64(a), sb = wave_incl_scan_u64(b);
+  __syncthreads();
+  if (lane == 63) {
+    red[0][wave] = sa;
+    red[1][wave] = sb;
+  }
+  __syncthreads();
+  uint64_t pa = 0, pb = 0, xa = 0, xb = 0;
+  for (int w = 0; w < kVtThreads / 64; ++w) {
+    pa += w < wave ? red[0][w] : 0ull;
+    pb += w < wave ? red[1][w] : 0ull;
+    xa += red[0][w];
+    xb += red[1][w];
+  }
+  *ia = sa + pa;
+  *ib = sb + pb;
+  *ta = xa;
+  *tb = xb;
+}
+
+__global__ __launch_bounds__(kVtThreads) void k_vt_scan(const LaunchDesc *__restrict__ dp) {
+  __shared__ uint64_t red[2][kVtThreads / 64];
+  __shared__ uint64_t pmul[32];
+  __shared__ int32_t pa_s[64];
+  __shared__ int32_t np_s;
+  __shared__ uint32_t lat[2][kMaxDivs];
+  constexpr int PER = kVtChunk / kVtThreads;
+  const LaunchDesc d = *as_const(dp);
+  for (int64_t jj = 0; jj < d.nvt; ++jj) {
+    const BP_CONST InstPlan &p = as_const(d.plan)[d.vlist[jj]];
+    const int64_t C = p.C;
+    const uint32_t uC = (uint32_t)C;
+    const int64_t nv = C + 2;
+    const int64_t nch = (nv + kVtChunk - 1) / kVtChunk;
+    int32_t *cnt = d.vcnt + p.vt_off;
+    long long *sum = d.vsum + p.vt_off;
+    const int nd = p.ndiv;
+    if ((int64_t)blockIdx.x >= nch) continue;  // (block-uniform)
+    __syncthreads();
+    if (nd > 0) {
+      for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        lat[0][k] = 0u;
+        lat[1][k] = 0u;
+      }
+      if (threadIdx.x == 0) {
+        // the test constants of p_j^e, e = 1..a_j (c < 2^31: at most 30 prime powers, 9 primes)
+        const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
+        const int np = dv[2 * nd];
+        const BP_GLOBAL int32_t *pa = dv + 2 * nd + 1;
+        int o = 0;
+        for (int j = 0; j < np; ++j) {
+          pa_s[2 * j] = pa[2 * j];
+          pa_s[2 * j + 1] = pa[2 * j + 1];
+          uint32_t q = 1;
+          for (int e = 1; e <= pa[2 * j + 1]; ++e) {
+            q *= (uint32_t)pa[2 * j];
+            pmul[o++] = divides_const(q);
+          }
+        }
+        np_s = np;
+      }
+      __syncthreads();
+    }
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+      const int64_t v0 = c * kVtChunk + (int64_t)threadIdx.x * PER;
+      uint32_t cn[PER];
+      uint64_t mc = 0, ms = 0;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int64_t v = v0 + k;
+        cn[k] = v < nv ? (uint32_t)cnt[v] : 0u;
+        mc += cn[k];
+        ms += (uint64_t)cn[k] * (uint64_t)v;
+      }
+      if (nd > 0) {
+        // the divisor-lattice bin of each value present: big (c/2 < w < c)
+        // or small (0 < 2w < c) class
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const uint32_t uw = (uint32_t)(v0 + k);
+          if (!cn[k]) continue;
+          const int cls = (2ull * uw > uC && uw < uC) ? 1 : ((uw > 0 && 2ull * uw < uC) ? 0 : -1);
+          if (cls < 0) continue;
+          int bin = 0, stride = 1, o = 0;
+          for (int j = 0; j < np_s; ++j) {
+            const int aj = pa_s[2 * j + 1];
+            int e = 0;
+            while (e < aj && divides_u32(uw, pmul[o + e])) ++e;
+            bin += e * stride;
+            stride *= aj + 1;
+            o += aj;
+          }
+          atomicAdd(&lat[cls][bin], cn[k]);
+        }
+      }
+      uint64_t ic, is, tc, ts;
+      vt_block_scan(mc, ms, red, &ic, &is, &tc, &ts);
+      // suffix within the chunk: everything held by the threads after this
+      // one, then this thread's values downwards
+      uint64_t rc = tc - ic, rs = ts - is;
+#pragma unroll
+      for (int k = PER - 1; k >= 0; --k) {
+        const int64_t v = v0 + k;
+        rc += cn[k];
+        rs += (uint64_t)cn[k] * (uint64_t)v;
+        if (v < nv) {
+          cnt[v] = (int32_t)rc;
+          sum[v] = (long long)rs;
+        }
+      }
+      if (threadIdx.x == 0) {
+        d.vtot[p.vtt_off + 2 * c] = (long long)tc;
+        d.vtot[p.vtt_off + 2 * c + 1] = (long long)ts;
+      }
+    }
+    if (nd > 0) {
+      __syncthreads();
+      for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        if (lat[0][k]) atomicAdd(&d.vlat[p.vl_off + k], (int32_t)lat[0][k]);
+        if (lat[1][k]) atomicAdd(&d.vlat[p.vl_off + nd + k], (int32_t)lat[1][k]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__restrict__ dp) {
+  __shared__ long long offc[kVtMaxChunks + 1], offs[kVtMaxChunks + 1];
+  __shared__ uint64_t red[2][kVtThreads / 64];
+  __shared__ uint32_t lat[2][kMaxDivs];
+  // runs longer than kVtShortRun, filled by the whole block: (value, first
+  // position, length), at most one per value of the chunk
+  constexpr int kVtShortRun = 16;
+  constexpr int PER = kVtChunk / kVtThreads;
+  __shared__ int32_t lrun_v[kVtChunk], lrun_s[kVtChunk], lrun_n[kVtChunk];
+  __shared__ int32_t nlong;
+  const LaunchDesc d = *as_const(dp);
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t jj = 0; jj < d.nvt; ++jj) {
+    const int64_t inst = d.vlist[jj];
+    const BP_CONST InstPlan &p = as_const(d.plan)[inst];
+    const int64_t C = p.C;
+    const int64_t nv = C + 2;
+    const int64_t nch = (nv + kVtChunk - 1) / kVtChunk;
+    const int32_t *cnt = d.vcnt + p.vt_off;
+    const long long *sum = d.vsum + p.vt_off;
+    const long long *tot = d.vtot + p.vtt_off;
+    // offsets of the chunks: the totals of the chunks above each, a block scan
+    // of up to E totals per thread
+    {
+      const int E = (int)((nch + kVtThreads - 1) / kVtThreads);
+      const int64_t c0 = (int64_t)threadIdx.x * E;
+      uint64_t mc = 0, ms = 0;
+      for (int k = 0; k < E; ++k)
+        if (c0 + k < nch) {
+          mc += (uint64_t)tot[2 * (c0 + k)];
+          ms += (uint64_t)tot[2 * (c0 + k) + 1];
+        }
+      uint64_t ic, is, tc, ts;
+      vt_block_scan(mc, ms, red, &ic, &is, &tc, &ts);
+      uint64_t rc = tc - ic, rs = ts - is;
+      for (int k = E - 1; k >= 0; --k) {
+        const int64_t c = c0 + k;
+        if (c < nch) {
+          offc[c] = (long long)rc;
+          offs[c] = (long long)rs;
+          rc += (uint64_t)tot[2 * c];
+          rs += (uint64_t)tot[2 * c + 1];
+        }
+      }
+      __syncthreads();
+    }
+    auto cnt_ge = [&](int64_t v) -> int64_t { return (int64_t)cnt[v] + offc[v / kVtChunk]; };  // v in [0, c + 1]
+    auto sum_ge = [&](int64_t v) -> int64_t { return (int64_t)sum[v] + offs[v / kVtChunk]; };
+    const bool ok = d.vflag[jj] == 0;
+    if (ok) {
+      int32_t *sorted = d.sorted + p.ws_off;
+      uint32_t *av = d.av + p.ws_off;
+      int64_t *pre = d.pre + p.pre_off;
+      // position i of value v's run: the size, av and the prefix sum through i
+      auto put = [&](int64_t v, int64_t i, int64_t above, int64_t sum_above) {
+        sorted[i] = (int32_t)v;
+        av[i] = (2 * v > C) ? (uint32_t)(C - v) : (uint32_t)v;
+        pre[i + 1] = sum_above + (i + 1 - above) * v;
+      };
+      if (blockIdx.x == 0 && threadIdx.x == 0) pre[0] = 0;
+      for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        if (threadIdx.x == 0) nlong = 0;
+        __syncthreads();
+        const int64_t v0 = c * kVtChunk + (int64_t)threadIdx.x * PER;
+        for (int k = 0; k < PER; ++k) {
+          const int64_t v = v0 + k;
+          if (v > C) break;
+          const int64_t ge = cnt_ge(v), gt = cnt_ge(v + 1), n = ge - gt;
+          if (n <= 0) continue;
+          const int64_t sgt = sum_ge(v + 1);
+          if (gt == 0) d.state[inst].maxw = (int32_t)v;  // the run at position 0: the largest size
+          if (n <= kVtShortRun) {
+            for (int64_t i = gt; i < ge; ++i) put(v, i, gt, sgt);
+          } else {
+            const int slot = atomicAdd(&nlong, 1);
+            lrun_v[slot] = (int32_t)v;
+            lrun_s[slot] = (int32_t)gt;
+            lrun_n[slot] = (int32_t)n;
+          }
+        }
+        __syncthreads();
+        for (int q = 0; q < nlong; ++q) {
+          const int64_t v = lrun_v[q], gt = lrun_s[q];
+          const int64_t sgt = sum_ge(v + 1);
+          for (int64_t i = gt + threadIdx.x; i < gt + lrun_n[q]; i += blockDim.x) put(v, i, gt, sgt);
+        }
+        __syncthreads();
+      }
+      if (p.flags & kPlanSegments) {
+        int32_t *bidx = d.bidx + p.bidx_off;
+        for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < p.nbk; b += gsz) {
+          const int64_t v = b << p.bshift;
+          bidx[b] = v <= C + 1 ? (int32_t)cnt_ge(v) : 0;
+        }
+      }
+    }
+    if (blockIdx.x != jj % gridDim.x) continue;
+    // one block per instance: the multiple counts of the mirrored VB2 and the state
+    const int nd = p.ndiv;
+    if (nd > 0 && ok) {
+      const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
+      const BP_GLOBAL int32_t *dbin = dv + nd;
+      const int np = dv[2 * nd];
+      const BP_GLOBAL int32_t *pa = dv + 2 * nd + 1;
+      for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        lat[0][k] = (uint32_t)d.vlat[p.vl_off + k];
+        lat[1][k] = (uint32_t)d.vlat[p.vl_off + nd + k];
+      }
+      __syncthreads();
+      // superset sums along each prime's axis: bin e takes bin e + 1's count
+      int stride = 1;
+      for (int j = 0; j < np; ++j) {
+        const int aj = pa[2 * j + 1];
+        for (int e = aj - 1; e >= 0; --e) {
+          for (int b = threadIdx.x; b < nd; b += blockDim.x) {
+            if ((b / stride) % (aj + 1) == e) {
+              lat[0][b] += lat[0][b + stride];
+              lat[1][b] += lat[1][b + stride];
+            }
+          }
+          __syncthreads();
+        }
+        stride *= aj + 1;
+      }
+      int32_t *dc = d.dcnt + p.dc_off;
+      for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        const int bk = dbin[k];
+        dc[k] = (int32_t)lat[0][bk];
+        dc[nd + k] = (int32_t)lat[1][bk];
+      }
+    }
+    if (threadIdx.x == 0) {
+      InstState *st = &d.state[inst];
+      const int64_t r = cnt_ge(0);
+      if (ok) {
+        st->status = BP_OK;
+        st->r = (int32_t)r;
+        st->nf = (int32_t)cnt_ge(C);
+        st->nb = (int32_t)cnt_ge(C / 2 + 1);
+        st->nm = (int32_t)cnt_ge((C + 1) / 2);
+        st->nz = (int32_t)cnt_ge(1);
+        if (r == 0) st->maxw = 0;  // else written with the run at position 0, by whichever block holds it
+        st->sumW = sum_ge(0);
+        st->sumBig = sum_ge(C / 2 + 1) - sum_ge(C);
+        st->sumNZ = sum_ge(1) - sum_ge(C);
+      } else {
+        st->status = BP_ERR_RANGE;
+        st->r = 0;
+        st->nf = st->nb = st->nm = st->nz = 0;
+        st->maxw = 0;
+        st->sumW = st->sumBig = st->sumNZ = 0;
+      }
+      for (int b = 0; b < kNB; ++b) st->hiEff[b] = p.hi[b];
+      if ((p.flags & kPlanClampVB2) && ok && r > 0) {
+        // the VB2 cut needs the largest size here: the largest v with #{w >= v} > 0
+        int64_t lo = 0, hi = C;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi + 1) >> 1;
+          if (cnt_ge(mid) > 0) lo = mid;
+          else hi = mid - 1;
+        }
+        const int64_t denom = r * lo;
+        const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)p.C;
+        if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
+      }
+      for (int b = 0; b < kNB; ++b) d.keys[inst * kNB + b] = 0ull;
+      st->evals_skipped = 0ull;
+      int refuted = 0;
+      if ((p.flags & kPlanEarlyExit) && ok && r > 0) refuted = (st->sumW + p.C - 1) / p.C > p.k;
+      d.refuted[inst] = refuted;
+    }
     __syncthreads();
   }
 }
@@ -1631,6 +1993,14 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__
     o.verdict = lb <= p.k ? 1 : 0;
     d.out[inst] = o;
   }
+  // the value tables' counts and lattice bins back to zero for the next launch
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x, gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t jj = 0; jj < d.nvt; ++jj) {
+    const BP_CONST InstPlan &p = as_const(d.plan)[d.vlist[jj]];
+    for (int64_t v = gt; v < (int64_t)p.C + 2; v += gsz) d.vcnt[p.vt_off + v] = 0;
+    for (int64_t k = gt; k < 2 * (int64_t)p.ndiv; k += gsz) d.vlat[p.vl_off + k] = 0;
+    if (gt == 0) d.vflag[jj] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2166,11 +2536,8 @@ static hipError_t launch_combine(const LaunchDesc *d_desc, int lpl, int grid_com
   return hipGetLastError();
 }
 
-// The large-instance prep runs only when the launch holds a large instance and
-// the combine only when it has split tiles (either would find no work); the
-// small-instance prep always runs, as it clears the sweep's task counters.
-hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_sweep,
-                           int grid_comb, int grid_fin, bool with_large, bool with_combine, hipStream_t s) {
+static hipError_t launch_prep(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_vt,
+                              bool with_large, hipStream_t s) {
   hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
                      prep_smem_small(), s, d_desc);
   hipError_t e = hipGetLastError();
@@ -2180,6 +2547,23 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_smal
                        prep_smem_large(), s, d_desc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  if (grid_vt > 0) {
+    hipLaunchKernelGGL(k_vt_scan, dim3(grid_vt), dim3(kVtThreads), 0, s, d_desc);
+    hipLaunchKernelGGL(k_vt_emit, dim3(grid_vt), dim3(kVtThreads), 0, s, d_desc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The large-instance prep runs only when the launch holds a large instance
+// (the block form when with_large, the value-table kernels when grid_vt > 0)
+// and the combine only when it has split tiles (either would find no work);
+// the small-instance prep always runs, as it clears the sweep's task counters.
+hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_vt,
+                           int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
+                           hipStream_t s) {
+  hipError_t e = launch_prep(d_desc, grid_prep_small, grid_prep_large, grid_vt, with_large, s);
+  if (e != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   if (with_combine && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
@@ -2188,18 +2572,11 @@ hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_smal
 
 // The same launches with events around the stages (diagnostic timing).
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
-                                 hipStream_t s, hipEvent_t ev[4]) {
+                                 int grid_vt, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
+                                 bool with_combine, hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipEventRecord(ev[0], s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
-                     prep_smem_small(), s, d_desc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (with_large) {
-    hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
-                       prep_smem_large(), s, d_desc);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  if ((e = launch_prep(d_desc, grid_prep_small, grid_prep_large, grid_vt, with_large, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -2250,7 +2627,7 @@ hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, 
   hipLaunchKernelGGL(k_noalloc_tables, dim3(1), dim3(64), 0, s, t, (NoAllocTables *)base);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_pipeline((const LaunchDesc *)base, lpl, grid_prep_small, grid_prep_large, grid_sweep, grid_comb,
+  return launch_pipeline((const LaunchDesc *)base, lpl, grid_prep_small, grid_prep_large, 0, grid_sweep, grid_comb,
                          grid_fin, with_large, with_combine, s);
 }
 

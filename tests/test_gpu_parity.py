@@ -74,6 +74,86 @@ def ctx_pipe():
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_block():
+    # a context whose large instances are prepared by one block (LDS sort)
+    old = os.environ.get("BP_NO_VALUE_PREP")
+    os.environ["BP_NO_VALUE_PREP"] = "1"
+    try:
+        c = bp.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("BP_NO_VALUE_PREP", None)
+        else:
+            os.environ["BP_NO_VALUE_PREP"] = old
+    yield c
+    c.close()
+
+
+def test_value_table_prep_matches_block_prep_and_oracle(ctx, ctx_block):
+    # large instances (more than 8192 reduced items, c <= 16 r) prepared from
+    # value tables over the whole GPU, against the one-block prep and the
+    # oracle: both input forms, the segment sums with the mirrored VB2
+    # (divisor lattice), the VB2 cut, heavy duplicates, tiny c, the largest r
+    g = np.random.default_rng(31)
+    cases = [(12000, 9000, 0, 0), (12000, 7000, 3000, bp.BP_SEGMENTS), (5040, 8500, 500, bp.BP_SEGMENTS),
+             (16000, 6000, 3000, -1), (2, 9000, 0, 0), (1000, 16384, 0, bp.BP_SEGMENTS), (77, 4000, 5000, 0)]
+    for C, n, m, flags in cases:
+        unp = g.integers(0, C + 1, size=n).astype(np.int32)
+        if m:
+            res = g.integers(0, C + 1, size=m).astype(np.int32)
+            res[: m // 4] = C  # empty bins
+            items = O.residual_reduce(C, res, unp)
+            k = m
+        else:
+            items = list(unp)
+            k = int(O.bounds(C, 0, items[:50])["lb"]) + n // 4
+        if flags == -1:  # the paper's VB2 cut
+            maxw = max(items) if len(items) else 0
+            lo, hi = zip(*(O.default_range(b, C, len(items), maxw, clamp_vb2=True) for b in range(O.NB)))
+            want = O.bounds(C, k, items, list(lo), list(hi))
+        else:
+            want = O.bounds(C, k, items)
+        for c, name in ((ctx, "value tables"), (ctx_block, "block")):
+            say("value prep", C, n, m, flags, name)
+            if flags == -1:
+                sw = bp.default_sweep(C)
+                sw.flags = bp.BP_SWEEP_PAPER_VB2_CLAMP
+                got = c.lower_bounds(C, k, np.asarray(items, dtype=np.int32), sw)
+            elif m:
+                got = c.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT | flags)
+            else:
+                sw = bp.default_sweep(C)
+                sw.flags = bp.BP_SWEEP_SEGMENTS if flags else 0
+                got = c.lower_bounds(C, k, unp, sw)
+            same(got, want, (name, C, n, m, flags))
+            assert got["r"] == len(items)
+    # a residual outside [0, c] and a size outside [0, c] in device memory:
+    # the device-side range error from both preps, and clean tables after it
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    d_out = torch.zeros(bp.BOUNDS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    C = 20000
+    unp = g.integers(0, C + 1, size=9000).astype(np.int32)
+    res = g.integers(0, C + 1, size=100).astype(np.int32)
+    for bad_res, bad_unp in ((C + 1, None), (None, -3)):
+        r2, u2 = res.copy(), unp.copy()
+        if bad_res is not None:
+            r2[17] = bad_res
+        if bad_unp is not None:
+            u2[4321] = bad_unp
+        d_res, d_unp = torch.from_numpy(r2).to(dev), torch.from_numpy(u2).to(dev)
+        for c, name in ((ctx, "value tables"), (ctx_block, "block")):
+            say("value prep range error", name, bad_res, bad_unp)
+            c.feasible_dev(C, len(r2), d_res.data_ptr(), len(u2), d_unp.data_ptr(), d_out.data_ptr(), stream)
+            torch.cuda.synchronize()
+            got = row_dict(np.frombuffer(d_out.cpu().numpy().tobytes(), dtype=bp.BOUNDS_DTYPE)[0])
+            assert got["status"] == bp.BP_ERR_RANGE, name
+    want = O.bounds(C, 100, O.residual_reduce(C, res, unp))
+    same(ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT), want, "after the range errors")
+
+
 def test_small_checks_on_both_paths(ctx, ctx_pipe):
     # the one-launch path (instance in the kernel arguments) and the pipeline
     # on the same small checks: random instances with custom ranges and the
