@@ -268,6 +268,8 @@ bp_status Ctx::init(int dev) {
   // (0 .. 64) instead of where the cost model puts the cut; same results.
   const char *kc = getenv("BP_SEGMENT_KCUT");
   if (kc && kc[0]) seg_kcut = std::min(std::max(atoi(kc), 0), (int)kSegMaxK);
+  if (const char *lk = getenv("BP_LUT_KCUT")) lut_kcut = std::max<long long>(atoll(lk), 0);
+  if (const char *lq = getenv("BP_LUT_QCHUNK")) lut_qchunk = std::min(std::max(atoi(lq), 1), 1 << 20);
   return BP_OK;
 }
 
@@ -518,6 +520,37 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         push(e, (double)tile * (2.0 * ((double)(tile + bw) * dens * 2.0 + 30.0)) + 400.0);
         continue;
       }
+      if (q.segments && p.large == 2 && (b == kBJ1 || b == kCCM1)) {
+        // Value-table instance: lambda with K = floor(c / lambda) (BJ1) or
+        // floor(floor(c/2) / lambda) (CCM1) up to kcut read 2K thresholds
+        // from the tables, about lut_q slots per q and parameter (measured on
+        // MI355X: table gathers are latency-bound) against r dense
+        // evaluations; smaller lambda stay dense.  The lookup range is cut
+        // into bands [L, 2L), whose tiles are split into q chunks of
+        // kLutQPerChunk, so that no task walks a long chain of loads.
+        const double lut_q = b == kBJ1 ? 112.0 : 56.0;
+        const int64_t knum = b == kBJ1 ? (int64_t)q.C : (int64_t)q.C / 2;
+        const int64_t kcut = lut_kcut >= 0 ? lut_kcut : std::max<int64_t>(1, (int64_t)((double)rcap * unit_cost(b) / lut_q));
+        const int64_t lstar = std::max<int64_t>(q.lo[b], knum / (kcut + 1) + 1);
+        if (lstar > q.lo[b]) {
+          e.lam0 = q.lo[b];
+          e.ntiles = (std::min(lstar - 1, q.hi[b]) - q.lo[b] + tile) / tile;
+          push(e, dense_tc);
+        }
+        for (int64_t L = lstar; L <= q.hi[b];) {
+          // the band's tiles: whole tiles from L, up to about 2L
+          const int64_t nt = std::max<int64_t>(1, (L + tile - 1) / tile);
+          const int64_t end = std::min(q.hi[b], L + nt * tile - 1);
+          const int64_t kfirst = knum / L;
+          e.mode = kModeLookup;
+          e.lam0 = L;
+          e.ntiles = (end - L + tile) / tile;
+          e.aux = (int32_t)std::min<int64_t>(64, std::max<int64_t>(1, (kfirst + lut_qchunk - 1) / lut_qchunk));
+          push(e, (double)tile * (double)std::max<int64_t>(kfirst, 1) * lut_q + 400.0);
+          L = end + 1;
+        }
+        continue;
+      }
       if (q.segments && (b == kBJ1 || b == kCCM1)) {
         // A tile whose smallest parameter is lambda has K = floor(c / lambda)
         // (BJ1) or floor(floor(c/2) / lambda) (CCM1) and 2K windows of about
@@ -626,7 +659,12 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   for (size_t j = 0; j < ent.size(); ++j) {
     Entry &e = ent[j];
     const double tc = tile_cost_v[j];
-    if (split_seg && e.mode == kModeSegments && (e.bound == kBJ1 || e.bound == kCCM1)) {
+    if (e.mode == kModeLookup) {
+      e.nchunks = e.aux;  // chunks of the q range, set by the band
+      e.aux = 0;
+      e.tpt = 1;
+      task_cost[j] = tc / e.nchunks;
+    } else if (split_seg && e.mode == kModeSegments && (e.bound == kBJ1 || e.bound == kCCM1)) {
       const int64_t C = pin[e.inst].C;
       const int64_t knum = e.bound == kBJ1 ? C : C / 2;
       const int64_t kfirst = knum / std::max<int64_t>(1, e.lam0);  // the entry's largest window count

@@ -76,6 +76,8 @@ struct Ctx {
   bool any_run = false;
   bool use_graph = true;
   int seg_kcut = -1;  // BJ1 segment tiles for K <= seg_kcut; -1: chosen by the cost model
+  int64_t lut_kcut = -1;  // lookup tiles for K <= lut_kcut (BP_LUT_KCUT); -1: chosen by the cost model
+  int lut_qchunk = kLutQPerChunk;  // q values per chunk of a lookup tile (BP_LUT_QCHUNK)
   bool timing = false;
   // Stage timing: one set of 4 events per timed run, reused round-robin; a
   // set is folded into the sums (waiting for it) before it is reused.

@@ -39,7 +39,7 @@ static_assert(kLargeCap == BP_MAX_ITEMS, "the check's item limit is the large pr
 // sums, the class bounds and the threshold tables are read off.  Used when
 // the instance is large and c is at most kVtMaxC and kVtRatio times its
 // reduced count (the tables hold c + 2 entries).
-constexpr int kVtChunk = 2048;           // values per block of the suffix scan
+constexpr int kVtChunk = 2048;           // values per block of the suffix scan (2^kVtChunkLog)
 constexpr int kVtThreads = 256;
 constexpr int32_t kVtMaxC = 1 << 21;
 constexpr int64_t kVtRatio = 16;
@@ -86,7 +86,12 @@ constexpr uint32_t kPlanSegments = 4u;
 // c - lambda.
 // kModeL2State: tiles over every lambda in [0, c/2] that store the L2
 // aggregates of the node state (no maximum).
-enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2, kModeL2State = 3 };
+// kModeLookup (BJ1, CCM1 of value-table instances): each lane walks its own
+// thresholds q lambda and c - q lambda and reads #{w >= t} and sum{w >= t}
+// from the value tables.
+enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2, kModeL2State = 3, kModeLookup = 4 };
+constexpr int kVtChunkLog = 11;  // kVtChunk = 2^kVtChunkLog
+constexpr int kLutQPerChunk = 8;  // q values per chunk of a split lookup tile (each a chain of table loads)
 constexpr int kMaxDivs = 256;         // most divisors of c a mirrored instance may have
 constexpr int kMirrorMinItems = 256;  // fewer items: the per-parameter gcd outweighs the saved half
 

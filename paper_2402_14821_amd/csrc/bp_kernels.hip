@@ -811,6 +811,11 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
         if (c < nch) {
           offc[c] = (long long)rc;
           offs[c] = (long long)rs;
+          if (c % gridDim.x == blockIdx.x) {
+            // for the lookup tiles of the sweep, after the totals
+            d.vtot[p.vtt_off + 2 * nch + 2 * c] = (long long)rc;
+            d.vtot[p.vtt_off + 2 * nch + 2 * c + 1] = (long long)rs;
+          }
           rc += (uint64_t)tot[2 * c];
           rs += (uint64_t)tot[2 * c + 1];
         }
@@ -979,6 +984,9 @@ struct TileArgs {
   const BP_GLOBAL int32_t *divs; // ascending
   const BP_GLOBAL int32_t *dcnt; // [small x ndiv][big x ndiv] multiple counts
   long long *node;               // served request: this bound's block of the node state, indexed by lambda - lo
+  const BP_GLOBAL int32_t *vc;   // value tables (lookup tiles): #{w >= v} and sum{w >= v} within each chunk,
+  const BP_GLOBAL long long *vs; //   plus the chunk's offsets vo[2 chunk], vo[2 chunk + 1]
+  const BP_GLOBAL long long *vo;
 };
 
 // Largest number of items whose per-item increments, each at most maxinc,
@@ -1409,6 +1417,101 @@ __device__ void part_ccm1_seg(const TileArgs &t, const int64_t lam_out[LPL], int
   for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j];
 }
 
+// #{w >= v} and sum{w >= v} over all reduced sizes, 0 <= v <= c + 1, from
+// the value tables.
+__device__ __forceinline__ void lut_ge(const TileArgs &t, int64_t v, int64_t &cnt, int64_t &sum) {
+  const int64_t c = v >> kVtChunkLog;
+  cnt = (int64_t)t.vc[v] + (int64_t)t.vo[2 * c];
+  sum = (int64_t)t.vs[v] + (int64_t)t.vo[2 * c + 1];
+}
+
+// U(th) = sum over the sizes 0 < w < c of max(0, w - th), 0 <= th <= c:
+// sum{w >= th} - th #{w >= th} over all sizes, less the nf sizes c.
+__device__ __forceinline__ int64_t lut_u(const TileArgs &t, int64_t th) {
+  int64_t n, s;
+  lut_ge(t, th, n, s);
+  return s - th * n - (int64_t)t.nf * ((int64_t)t.C - th);
+}
+
+// f_BJ1 by lookups: the telescoping form of part_bj1_seg,
+//   S = sum_{q=1..K} U(c - q lambda) - U(q lambda),
+// each lane over its own K = floor(c / lambda), this chunk's share of the q
+// range.  Returns the same part as part_bj1 (part = 2S - W + n p).
+template <int LPL>
+__device__ void part_bj1_lut(const TileArgs &t, const int64_t lam_out[LPL], int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t l0 = uniform64(max(t.lo, t.lam0));
+  const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
+  int64_t lam[LPL], K[LPL], acc[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    lam[j] = min(max(lam_out[j], l0), l1);
+    K[j] = C / lam[j];
+    acc[j] = 0;
+  }
+  const int64_t kmax = C / l0;
+  const int64_t qa = 1 + kmax * t.qc / t.qn, qb = kmax * (t.qc + 1) / t.qn;
+  // four q at a time, their loads in flight together (a q past a lane's K
+  // reads threshold 0 and is not added)
+  for (int64_t q0 = qa; q0 <= qb; q0 += 4) {
+    int64_t u[4][LPL];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int j = 0; j < LPL; ++j) {
+        const int64_t q = q0 + v;
+        const bool in = q <= qb && q <= K[j];
+        u[v][j] = lut_u(t, in ? C - q * lam[j] : 0) - lut_u(t, in ? q * lam[j] : 0);
+        if (!in) u[v][j] = 0;
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int j = 0; j < LPL; ++j) acc[j] += u[v][j];
+  }
+  const int64_t n = t.nz - t.nf;
+  for (int j = 0; j < LPL; ++j)
+    part[j] = 2 * acc[j] - (t.qc == 0 ? t.sumNZ - n * (C % lam[j]) : 0);
+}
+
+// f_CCM1 by lookups: the counts of part_ccm1_seg, sum_{q >= 1} #{small w >=
+// q lambda} - #{big w <= c - q lambda}, each lane over its own q <= floor(c/2)
+// / lambda (larger q add nothing), this chunk's share of the q range.
+template <int LPL>
+__device__ void part_ccm1_lut(const TileArgs &t, const int64_t lam_out[LPL], int64_t part[LPL]) {
+  const int64_t C = t.C;
+  const int64_t l0 = uniform64(max(t.lo, t.lam0));
+  const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
+  const int64_t half = C / 2;
+  const int64_t scap = (C - 1) / 2 + 1;  // the small sizes are those below it (and above 0)
+  const int64_t nbig = t.nb - t.nf;
+  int64_t ns, ss;
+  lut_ge(t, scap, ns, ss);  // #{w >= scap}
+  int64_t lam[LPL], Q[LPL], acc[LPL];
+  for (int j = 0; j < LPL; ++j) {
+    lam[j] = min(max(lam_out[j], l0), l1);
+    Q[j] = half / lam[j];
+    acc[j] = 0;
+  }
+  const int64_t qmax = half / l0;
+  const int64_t qa = 1 + qmax * t.qc / t.qn, qb = qmax * (t.qc + 1) / t.qn;
+  // four q at a time, their loads in flight together
+  for (int64_t q0 = qa; q0 <= qb; q0 += 4) {
+    int64_t u[4][LPL];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int j = 0; j < LPL; ++j) {
+        const int64_t q = q0 + v;
+        const bool in = q <= qb && q <= Q[j];
+        int64_t a, b, s;
+        lut_ge(t, in ? q * lam[j] : scap, a, s);      // small sizes >= q lambda: #{w >= q lambda} - #{w >= scap}
+        lut_ge(t, in ? C - q * lam[j] + 1 : C, b, s);  // big sizes >= c - q lambda + 1, less the nf sizes c
+        u[v][j] = in ? (a - ns) - (nbig - (b - t.nf)) : 0;
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int j = 0; j < LPL; ++j) acc[j] += u[v][j];
+  }
+  for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j];
+}
+
 // f_RAD2 by segments: the four threshold counts of part_rad2 (small sizes
 // >= lambda and >= c - 2 lambda + 1, big sizes >= 2 lambda and
 // >= c - lambda + 1), one window each per tile.  Same part as part_rad2.
@@ -1738,6 +1841,11 @@ __device__ __forceinline__ bool entry_args(const LaunchDesc &d, const BP_CONST E
   t.divs = as_global(d.divs + p.div_off);
   t.dcnt = as_global(d.dcnt + p.dc_off);
   t.node = p.state_off >= 0 ? d.nodes + p.state_off + node_off(p.C, bound) : nullptr;
+  if (p.large == 2) {
+    t.vc = as_global(d.vcnt + p.vt_off);
+    t.vs = as_global(d.vsum + p.vt_off);
+    t.vo = as_global(d.vtot + p.vtt_off + 2 * (((int64_t)p.C + 2 + kVtChunk - 1) / kVtChunk));
+  }
   early = (p.flags & kPlanEarlyExit) != 0;
   return true;
 }
@@ -1804,7 +1912,10 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
     uint32_t l32[LPL];
     tile_lams<LPL>(tv, lam, l32);
     int64_t part[LPL];
-    if (e.mode == kModeSegments) {
+    if (e.mode == kModeLookup) {
+      if (bound == kCCM1) part_ccm1_lut<LPL>(t, lam, part);
+      else part_bj1_lut<LPL>(t, lam, part);
+    } else if (e.mode == kModeSegments) {
       if (bound == kMT) part_mt_seg<LPL>(t, lam, part);
       else if (bound == kCCM1) part_ccm1_seg<LPL>(t, lam, part);
       else if (bound == kRAD2) part_rad2_seg<LPL>(t, lam, part);
