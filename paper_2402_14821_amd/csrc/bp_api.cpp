@@ -435,8 +435,11 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
                   (long long)i, (long long)rcap, kLargeCap);
     p.r_cap = (int32_t)rcap;
     p.large = rcap > kSmallCap ? 1 : 0;
-    if (p.large && value_prep && q.C <= kVtMaxC && (int64_t)q.C <= kVtRatio * rcap) {
-      // prepared from value tables by kernels over the whole GPU
+    // Prepared from value tables by kernels over the whole GPU: a large
+    // instance whose c is not much above its item count.  (For a few hundred
+    // items the one-block prep and the windowed segment sums are faster than
+    // tables of c entries, measured at c = 10^3 .. 10^6.)
+    if (value_prep && p.large && q.C <= kVtMaxC && (int64_t)q.C <= kVtRatio * rcap) {
       p.large = 2;
       p.vt_off = vt;
       vt += (int64_t)q.C + 2;

@@ -33,12 +33,13 @@ constexpr int kSmallCap = 8192;         // items per small-instance prep block (
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
 static_assert(kLargeCap == BP_MAX_ITEMS, "the check's item limit is the large prep block's capacity");
-// Value-table prep of large instances (several kernels over the whole GPU
-// instead of one block): a count per size value, suffix-scanned into
-// #{w >= v} and sum{w : w >= v}, from which the sorted sizes, their prefix
-// sums, the class bounds and the threshold tables are read off.  Used when
-// the instance is large and c is at most kVtMaxC and kVtRatio times its
-// reduced count (the tables hold c + 2 entries).
+// Value-table prep (several kernels over the whole GPU instead of one
+// block): a count per size value, suffix-scanned into #{w >= v} and
+// sum{w : w >= v}, from which the sorted sizes, their prefix sums, the class
+// bounds and the threshold tables are read off, and which the lookup tiles
+// of BJ1 and CCM1 read.  Used for c at most kVtMaxC when the instance is
+// large and c is at most kVtRatio times its reduced count (the tables hold
+// c + 2 entries).
 constexpr int kVtChunk = 2048;           // values per block of the suffix scan (2^kVtChunkLog)
 constexpr int kVtThreads = 256;
 constexpr int32_t kVtMaxC = 1 << 21;
