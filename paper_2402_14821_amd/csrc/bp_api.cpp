@@ -506,6 +506,16 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         continue;
       }
       const double dense_tc = (double)tile * ((double)rcap * unit_cost(b) + 60.0);
+      const int64_t ncand = (b == kMT ? 2 : 4) * rcap + 1;
+      if (q.segments && (b == kMT || b == kRAD2) && q.state_off < 0 && ncand < q.hi[b] - q.lo[b] + 1) {
+        // fewer change points than parameters: tiles over the candidate
+        // indices, each a binary search per threshold (2 for MT, 4 for RAD2)
+        e.mode = kModeCand;
+        e.lam0 = 0;
+        e.ntiles = (ncand + tile - 1) / tile;
+        push(e, (double)tile * ((b == kMT ? 2.0 : 4.0) * (ilog2ceil(rcap + 1) + 1) * 4.0 + 20.0));
+        continue;
+      }
       if (q.segments && b == kRAD2) {
         // four windows per tile (128 or 256 thresholds wide)
         e.mode = kModeSegments;
@@ -674,7 +684,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
       e.nchunks = (int32_t)std::min<int64_t>(64, std::max<int64_t>(1, (kfirst + kSegQPerChunk - 1) / kSegQPerChunk));
       e.tpt = 1;
       task_cost[j] = tc / e.nchunks;
-    } else if (tc <= target || e.bound == kL2 || e.mode == kModeSegments) {
+    } else if (tc <= target || e.bound == kL2 || e.mode == kModeSegments || e.mode == kModeCand) {
       double tpt = std::floor(target / tc);
       tpt = std::min(std::max(tpt, 1.0), std::min((double)e.ntiles, 1e9));
       e.tpt = (int32_t)tpt;
@@ -696,11 +706,12 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   }
   std::vector<size_t> order(ent.size());
   for (size_t j = 0; j < order.size(); ++j) order[j] = j;
-  // Longest task first, except that L2 tasks go first of all: they are cheap
-  // in issue slots but wait on chains of dependent loads, and started early
-  // they overlap the sweeps of other waves instead of trailing the launch.
+  // Longest task first, except that L2 tasks and the candidate tiles of MT
+  // and RAD2 go first of all: they are cheap in issue slots but wait on
+  // chains of dependent loads, and started early they overlap the sweeps of
+  // other waves instead of trailing the launch.
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-    const bool la = ent[a].bound == kL2, lb = ent[b].bound == kL2;
+    const bool la = ent[a].bound == kL2 || ent[a].mode == kModeCand, lb = ent[b].bound == kL2 || ent[b].mode == kModeCand;
     if (la != lb) return la;
     const int32_t ra = order_rank[ent[a].bound], rb = order_rank[ent[b].bound];
     if (ra != rb) return ra < rb;

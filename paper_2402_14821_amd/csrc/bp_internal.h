@@ -90,7 +90,11 @@ constexpr uint32_t kPlanSegments = 4u;
 // kModeLookup (BJ1, CCM1 of value-table instances): each lane walks its own
 // thresholds q lambda and c - q lambda and reads #{w >= t} and sum{w >= t}
 // from the value tables.
-enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2, kModeL2State = 3, kModeLookup = 4 };
+// kModeCand (MT, RAD2): tiles over candidate indices, as L2's: the range's
+// first parameter and the points where a size crosses one of the function's
+// thresholds, each evaluated from counts and prefix sums of the sorted sizes.
+enum : int32_t { kModeDense = 0, kModeSegments = 1, kModeMirror = 2, kModeL2State = 3, kModeLookup = 4,
+                 kModeCand = 5 };
 constexpr int kVtChunkLog = 11;  // kVtChunk = 2^kVtChunkLog
 constexpr int kLutQPerChunk = 8;  // q values per chunk of a split lookup tile (each a chain of table loads)
 constexpr int kMaxDivs = 256;         // most divisors of c a mirrored instance may have

@@ -1681,6 +1681,104 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL
   }
 }
 
+// #{w > x[j]} over the decreasing sizes for NT thresholds per lane, by
+// binary lifting with a fixed number of steps, every search of the lane in
+// lockstep so that their loads are in flight together.
+template <int LPL, int NT>
+__device__ __forceinline__ void count_above(const TileArgs &t, const int64_t (&x)[NT][LPL], int32_t (&n)[NT][LPL]) {
+  const int32_t r = t.r;
+  for (int k = 0; k < NT; ++k)
+    for (int j = 0; j < LPL; ++j) n[k][j] = 0;
+  for (int32_t step = r > 0 ? (int32_t)(1u << (31 - __clz(r))) : 0; step > 0; step >>= 1) {
+    for (int k = 0; k < NT; ++k)
+      for (int j = 0; j < LPL; ++j) {
+        const int32_t q = n[k][j] + step;
+        const int64_t v = t.sorted[min(q, r) - 1];
+        if (q <= r && v > x[k][j]) n[k][j] = q;
+      }
+  }
+}
+
+// f_MT over its change points (Sec. 3.1; the candidate set of L2): lo and,
+// for every size w, w + 1 and c - w + 1.  Between them every size keeps its
+// case, so S(lambda) is constant there and the smallest parameter of each
+// piece is a candidate.  With n1 = #{w > c - lambda} (value c each) and
+// j3 = #{w >= lambda}, the sizes [n1, j3) of the sorted order count w:
+//   S = c n1 + pre[j3] - pre[n1],  L = ceil(S / c) = n1 + ceil((pre[j3] - pre[n1]) / c);
+// lbp leaves out the nf sizes c (k_finalize adds them back, as for every DFF).
+template <int LPL>
+__device__ void tile_mt_cand(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL], bool ok[LPL]) {
+  const int64_t C = t.C;
+  const int32_t r = t.r;
+  int64_t x[2][LPL];
+  int32_t n[2][LPL];
+  for (int j = 0; j < LPL; ++j) {
+    const int64_t cidx = t.lam0 + lane_id() + 64 * j;
+    int64_t lam = -1;
+    if (cidx == 0) lam = t.lo;
+    else if (cidx <= 2 * (int64_t)r) {
+      const int64_t w = t.sorted[(cidx - 1) >> 1];
+      lam = ((cidx - 1) & 1) ? C - w + 1 : w + 1;
+    }
+    ok[j] = lam >= t.lo && lam <= t.hi;
+    if (!ok[j]) lam = t.lo;
+    lam_out[j] = lam;
+    x[0][j] = C - lam;  // n1 = #{w > c - lambda}
+    x[1][j] = lam - 1;  // j3 = #{w > lambda - 1}
+  }
+  count_above<LPL, 2>(t, x, n);
+  for (int j = 0; j < LPL; ++j) {
+    const int32_t n1 = n[0][j], j3 = max(n[1][j], n1);
+    lbp[j] = (int64_t)(n1 - t.nf) + ceil_div_small(t.pre[j3] - t.pre[n1], C);
+  }
+}
+
+// f_RAD2 over its change points (Sec. 3.1): lo and, for every size w, w + 1,
+// c - w + 1, floor((c - w)/2) + 1 and floor(w/2) + 1, where w crosses lambda,
+// c - lambda, c - 2 lambda or 2 lambda.  For c/4 < lambda <= c/3 the cases
+// are, with a = #{w >= lambda}, b = #{w > c - 2 lambda}, g = #{w >= 2 lambda},
+// e = #{w > c - lambda} (a >= b >= g >= e):
+//   lambda <= w <= c - 2 lambda        (a - b sizes)  floor(c/3)
+//   c - 2 lambda < w < 2 lambda        (b - g)        floor(c/2)
+//   2 lambda <= w <= c - lambda        (g - e)        c - floor(c/3)
+//   w > c - lambda                     (e)            c
+// and f(c, lambda) = c; lbp leaves out the nf sizes c.
+template <int LPL>
+__device__ void tile_rad2_cand(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL], bool ok[LPL]) {
+  const int64_t C = t.C;
+  const int32_t r = t.r;
+  int64_t x[4][LPL];
+  int32_t n[4][LPL];
+  for (int j = 0; j < LPL; ++j) {
+    const int64_t cidx = t.lam0 + lane_id() + 64 * j;
+    int64_t lam = -1;
+    if (cidx == 0) lam = t.lo;
+    else if (cidx <= 4 * (int64_t)r) {
+      const int64_t w = t.sorted[(cidx - 1) >> 2];
+      switch ((cidx - 1) & 3) {
+        case 0: lam = w + 1; break;
+        case 1: lam = C - w + 1; break;
+        case 2: lam = (C - w) / 2 + 1; break;
+        default: lam = w / 2 + 1; break;
+      }
+    }
+    ok[j] = lam >= t.lo && lam <= t.hi;
+    if (!ok[j]) lam = t.lo;
+    lam_out[j] = lam;
+    x[0][j] = lam - 1;
+    x[1][j] = C - 2 * lam;
+    x[2][j] = 2 * lam - 1;
+    x[3][j] = C - lam;
+  }
+  count_above<LPL, 4>(t, x, n);
+  const int64_t f3 = C / 3, f2 = C / 2;
+  for (int j = 0; j < LPL; ++j) {
+    const int64_t a = n[0][j], b = n[1][j], g = n[2][j], e = n[3][j];
+    const int64_t S = f3 * (a - b) + f2 * (b - g) + (C - f3) * (g - e) + C * e;
+    lbp[j] = ceil_div_small(S, C) - t.nf;
+  }
+}
+
 // L2 aggregates of the node state at every lambda of the tile, lambda in
 // [0, c/2]: n1 = #{w > c - lambda} and T = sum W2 + sum W3, from the sorted
 // sizes (binary lifting, as tile_l2) and their prefix sums.
@@ -1877,7 +1975,7 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
   const int64_t tile1 = min(e.ntiles, tile0 + e.tpt);
   for (int64_t tl = tile0; tl < tile1; ++tl) {
     if (early && refuted_now(d, inst)) {
-      if (bound != kL2) {
+      if (bound != kL2 && e.mode != kModeCand) {
         // the work left out: this chunk's share of the r items (the shares
         // of a tile's chunks add up to r) for each remaining tile's parameters
         const uint32_t r32 = (uint32_t)t.r;
@@ -1900,6 +1998,13 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       // tiles of L2 run over candidate indices, not parameters
       tile_l2<LPL>(t, lam, lbp, ok);
       flush_tile<LPL>(d, inst, kL2, t, lam, lbp, ok, early);
+      continue;
+    }
+    if (e.mode == kModeCand) {
+      // so do the candidate tiles of MT and RAD2
+      if (bound == kMT) tile_mt_cand<LPL>(t, lam, lbp, ok);
+      else tile_rad2_cand<LPL>(t, lam, lbp, ok);
+      flush_tile<LPL>(d, inst, bound, t, lam, lbp, ok, early);
       continue;
     }
     if (t.lam0 > t.hi) return;
