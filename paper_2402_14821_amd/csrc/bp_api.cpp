@@ -264,6 +264,7 @@ bp_status Ctx::init(int dev) {
     memset(small_out, 0, sizeof(bp_bounds) + 64);
   }
   if ((st = small_keys.reserve(kSmallBufBytes))) return st;
+  HIP_TRY(hipMemset(small_keys.p, 0, kSmallBufBytes));  // the one-kernel keys and count start at zero
   // BP_SEGMENT_KCUT=K: segment tiles of BJ1 wherever floor(c / lambda) <= K
   // (0 .. 64) instead of where the cost model puts the cut; same results.
   const char *kc = getenv("BP_SEGMENT_KCUT");
@@ -1219,9 +1220,12 @@ bp_status run_small(Ctx *c, const PlanIn &q, const int32_t *sizes, const int32_t
   bp_bounds *h = (bp_bounds *)c->small_out;
   uint32_t *seq = (uint32_t *)((char *)c->small_out + sizeof(bp_bounds));
   const uint32_t want = ++c->small_seq;
-  const int grid = (int)std::min<int64_t>(
-      c->small_grid, std::max<int64_t>(1, (params * a.slices + kSmallFusedThreads - 1) / kSmallFusedThreads));
-  HIP_TRY(launch_small_check(a, grid, c->small_keys.p, h, seq, want, c->stream));
+  // a few workgroups of 256: one kernel; else workgroups of 1024 and the final kernel
+  const int64_t lanes = params * a.slices;
+  const bool one = (lanes + kSmallOneThreads - 1) / kSmallOneThreads <= kSmallOneMaxGrid;
+  const int grid = one ? (int)std::max<int64_t>(1, (lanes + kSmallOneThreads - 1) / kSmallOneThreads)
+                       : (int)std::min<int64_t>(c->small_grid, (lanes + kSmallFusedThreads - 1) / kSmallFusedThreads);
+  HIP_TRY(launch_small_check(a, one, grid, c->small_keys.p, h, seq, want, c->stream));
   // Wait for the kernel's sequence number in host memory; after two seconds
   // without it, let the stream report what went wrong.
   const auto t0 = std::chrono::steady_clock::now();

@@ -27,7 +27,7 @@ hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_pre
                                  bool with_combine, hipStream_t s, hipEvent_t ev[4]);
 hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
                              long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s);
-hipError_t launch_small_check(const SmallArgs &a, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
+hipError_t launch_small_check(const SmallArgs &a, bool one, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
                               uint32_t seq, hipStream_t s);
 hipError_t noalloc_scratch(int device, unsigned char **out);
 hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,

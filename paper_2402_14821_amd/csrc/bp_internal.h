@@ -262,8 +262,15 @@ struct SmallHead {
   int32_t r;
   int32_t bad;     // a size or residual outside [0, C]
 };
-// the buffer: kNB keys per workgroup, then the head
-constexpr size_t kSmallBufBytes = sizeof(unsigned long long) * kNB * kSmallFusedMaxGrid + sizeof(SmallHead);
+// Checks whose pairs fit in kSmallOneMaxGrid workgroups of kSmallOneThreads
+// fold their maxima by atomics in one kernel (k_small_check<true>); larger
+// ones run workgroups of kSmallFusedThreads and add k_small_final.
+constexpr int kSmallOneThreads = 256;
+constexpr int kSmallOneMaxGrid = 64;
+// the buffer: kNB keys per workgroup, the head, then the one-kernel keys and
+// count (kNB + 1 words, zero between calls)
+constexpr size_t kSmallBufBytes =
+    sizeof(unsigned long long) * kNB * kSmallFusedMaxGrid + sizeof(SmallHead) + sizeof(unsigned long long) * (kNB + 1);
 struct SmallArgs {
   int32_t C;
   int32_t m;       // residual form: bins given as residuals (after the n sizes)

@@ -2441,13 +2441,51 @@ __global__ __launch_bounds__(256) void k_node_finalize(const NodeTask *__restric
 // over the workgroups, writes the record to `out` (host memory) and then
 // publishes `seq`.
 
-__global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a, unsigned long long *part,
-                                                                   SmallHead *head) {
+// The record of a small check from the packed maxima of L2 .. BJ1 and the
+// instance totals, written to host memory, then its sequence number.
+__device__ void small_record(const unsigned long long *keys, uint64_t tot_w, int64_t evals, int32_t r, int32_t bad,
+                             uint32_t C, int64_t k, bp_bounds *out, uint32_t *seq_out, uint32_t seq) {
+  bp_bounds o;
+  o.k = k;
+  o.r = r;
+  o.status = bad ? BP_ERR_RANGE : BP_OK;
+  o.early_exit = 0;
+  o.evals = evals;
+  o.evals_done = evals;
+  o.value[kL1] = r > 0 ? (int64_t)((tot_w + C - 1) / C) : 0;
+  o.argmax_lambda[kL1] = -1;
+  for (int q = kL2; q < kNB; ++q) {
+    const unsigned long long gk = keys[q];
+    o.value[q] = gk ? (int64_t)(gk >> 32) : 0;
+    o.argmax_lambda[q] = gk ? (int64_t)(0xffffffffu - (uint32_t)gk) : -1;
+  }
+  int64_t lb = -1;
+  int32_t arg = 0;
+  for (int q = 0; q < kNB; ++q)
+    if (o.value[q] > lb) { lb = o.value[q]; arg = q; }
+  o.lb = lb;
+  o.lb_arg = arg;
+  o.verdict = lb <= k ? 1 : 0;
+  *out = o;
+  // the record is visible to the host before the sequence number that announces it
+  __threadfence_system();
+  __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// ONE (at most kSmallOneMaxGrid workgroups of kSmallOneThreads): the
+// workgroups fold their maxima into one set of keys by atomics and the last
+// one to finish writes the record (a few dozen device-scope atomics and
+// fences cost less than a second launch); otherwise (workgroups of
+// kSmallFusedThreads) each writes its own slots for k_small_final.
+template <bool ONE, int NT>
+__global__ __launch_bounds__(NT) void k_small_check(SmallArgs a, unsigned long long *part,
+                                                                   SmallHead *head, unsigned long long *onek,
+                                                                   bp_bounds *out, uint32_t *seq_out, uint32_t seq) {
   __shared__ uint32_t w[kSmallFusedMax];
-  __shared__ uint32_t wsum[kSmallFusedThreads / 64];
+  __shared__ uint32_t wsum[NT / 64];
   __shared__ unsigned long long key[kNB];
   __shared__ unsigned long long tot_w;
-  __shared__ int32_t nbig_s, maxw_s, bad_s;
+  __shared__ int32_t nbig_s, maxw_s, bad_s, last_s;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const uint32_t C = (uint32_t)a.C;
@@ -2459,7 +2497,7 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
     bad_s = 0;
   }
   // the sizes, validated
-  for (int i = tid; i < a.n; i += kSmallFusedThreads) {
+  for (int i = tid; i < a.n; i += NT) {
     int32_t x = a.v[i];
     if (x < 0 || x > a.C) { bad_s = 1; x = 0; }
     w[i] = (uint32_t)x;
@@ -2468,7 +2506,7 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
   if (a.form == kFormResidual) {
     // one virtual item of size c - residual per bin with residual < c, in bin order
     uint32_t base = 0;
-    for (int j0 = 0; j0 < a.m; j0 += kSmallFusedThreads) {
+    for (int j0 = 0; j0 < a.m; j0 += NT) {
       const int j = j0 + tid;
       const bool in = j < a.m;
       int32_t res = in ? a.v[a.n + j] : a.C;
@@ -2479,7 +2517,7 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
       if ((tid & 63) == 0) wsum[wave] = (uint32_t)__popcll(bal);
       __syncthreads();
       uint32_t off = 0, tot = 0;
-      for (int v = 0; v < kSmallFusedThreads / 64; ++v) {
+      for (int v = 0; v < NT / 64; ++v) {
         off += v < wave ? wsum[v] : 0u;
         tot += wsum[v];
       }
@@ -2491,7 +2529,7 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
   __syncthreads();
   if (bad_s) r = 0;
   // totals: sum, count of big sizes, largest size
-  for (int i = tid; i < r; i += kSmallFusedThreads) {
+  for (int i = tid; i < r; i += NT) {
     const uint32_t x = w[i];
     atomicAdd(&tot_w, (unsigned long long)x);
     if (2ull * x > C) atomicAdd(&nbig_s, 1);
@@ -2516,8 +2554,8 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
   const int sh = __builtin_ctz((unsigned)S);
   const int sl = tid & (S - 1);
   unsigned long long best[kNB] = {};
-  for (int64_t gt = (int64_t)blockIdx.x * kSmallFusedThreads + tid; gt < total * S;
-       gt += (int64_t)gridDim.x * kSmallFusedThreads) {
+  for (int64_t gt = (int64_t)blockIdx.x * NT + tid; gt < total * S;
+       gt += (int64_t)gridDim.x * NT) {
     int b = kL2;
     int64_t idx = gt >> sh;
     for (; b < kNB; ++b) {
@@ -2570,10 +2608,25 @@ __global__ __launch_bounds__(kSmallFusedThreads) void k_small_check(SmallArgs a,
     if (lane_id() == 0 && m) atomicMax(&key[q], (unsigned long long)m);
   }
   __syncthreads();
+  int64_t P = 0;
+  for (int b = kMT; b < kNB; ++b) P += a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
+  if (ONE) {
+    if (tid < kNB && key[tid]) atomicMax(&onek[tid], key[tid]);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last_s = atomicAdd(&onek[kNB], 1ull) == (unsigned long long)(gridDim.x - 1) ? 1 : 0;
+    __syncthreads();
+    if (!last_s) return;
+    __threadfence();
+    if (tid < kNB) key[tid] = __hip_atomic_load(&onek[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // clean for the next call (every other workgroup is done with the keys)
+    if (tid <= kNB) __hip_atomic_store(&onek[tid], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) small_record(key, tot_w, (int64_t)r * P, r, bad_s, C, a.k, out, seq_out, seq);
+    return;
+  }
   if (tid < kNB) part[(size_t)blockIdx.x * kNB + tid] = key[tid];
   if (blockIdx.x == 0 && tid == 0) {
-    int64_t P = 0;
-    for (int b = kMT; b < kNB; ++b) P += a.lo[b] <= hi[b] ? hi[b] - a.lo[b] + 1 : 0;
     SmallHead h;
     h.tot_w = tot_w;
     h.evals = (int64_t)r * P;
@@ -2599,40 +2652,24 @@ __global__ __launch_bounds__(256) void k_small_final(const unsigned long long *p
   }
   if (tid == 0) {
     const SmallHead h = *head;
-    bp_bounds o;
-    o.k = k;
-    o.r = h.r;
-    o.status = h.bad ? BP_ERR_RANGE : BP_OK;
-    o.early_exit = 0;
-    o.evals = h.evals;
-    o.evals_done = h.evals;
-    o.value[kL1] = h.r > 0 ? (int64_t)((h.tot_w + C - 1) / C) : 0;
-    o.argmax_lambda[kL1] = -1;
-    for (int q = kL2; q < kNB; ++q) {
-      const unsigned long long gk = red[q];
-      o.value[q] = gk ? (int64_t)(gk >> 32) : 0;
-      o.argmax_lambda[q] = gk ? (int64_t)(0xffffffffu - (uint32_t)gk) : -1;
-    }
-    int64_t lb = -1;
-    int32_t arg = 0;
-    for (int q = 0; q < kNB; ++q)
-      if (o.value[q] > lb) { lb = o.value[q]; arg = q; }
-    o.lb = lb;
-    o.lb_arg = arg;
-    o.verdict = lb <= k ? 1 : 0;
-    *out = o;
-    // the record is visible to the host before the sequence number that announces it
-    __threadfence_system();
-    __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    small_record(red, h.tot_w, h.evals, h.r, h.bad, C, k, out, seq_out, seq);
   }
 }
 
-hipError_t launch_small_check(const SmallArgs &a, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
+hipError_t launch_small_check(const SmallArgs &a, bool one, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
                               uint32_t seq, hipStream_t s) {
   if (grid < 1 || grid > kSmallFusedMaxGrid) return hipErrorInvalidValue;
   unsigned long long *part = (unsigned long long *)buf;
   SmallHead *head = (SmallHead *)(part + (size_t)kNB * kSmallFusedMaxGrid);
-  hipLaunchKernelGGL(k_small_check, dim3(grid), dim3(kSmallFusedThreads), 0, s, a, part, head);
+  unsigned long long *onek = (unsigned long long *)(head + 1);
+  if (one) {
+    if (grid > kSmallOneMaxGrid) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_small_check<true, kSmallOneThreads>), dim3(grid), dim3(kSmallOneThreads), 0, s, a, part,
+                       head, onek, out, seq_out, seq);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_small_check<false, kSmallFusedThreads>), dim3(grid), dim3(kSmallFusedThreads), 0, s, a, part,
+                     head, onek, out, seq_out, seq);
   hipLaunchKernelGGL(k_small_final, dim3(1), dim3(256), 0, s, (const unsigned long long *)part, grid,
                      (const SmallHead *)head, (uint32_t)a.C, a.k, out, seq_out, seq);
   return hipGetLastError();
