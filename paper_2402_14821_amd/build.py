@@ -33,12 +33,40 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# Kernels that must not use per-lane scratch memory: register spills there
+# cost issue slots in the hot loops and HBM traffic (the compiler reports
+# each kernel's scratch size; the build fails when one of these has any).
+# k_sweep<4> (four parameters per lane, an autotuner option) spills a few
+# registers and is left out.
+NO_SCRATCH = ("_ZN3bpi7k_sweepILi1E", "_ZN3bpi7k_sweepILi2E", "_ZN3bpi9k_combineILi", "_ZN3bpi13k_small_check",
+              "_ZN3bpi6k_prep", "_ZN3bpi9k_vt_", "_ZN3bpi10k_finalize")
+
+
+def _scratch_kernels(remarks: str):
+    """Kernels (mangled names) with a nonzero scratch size in the compiler's
+    kernel-resource-usage remarks."""
+    bad, name = [], None
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:")[1].split("[")[0].strip()
+        elif "ScratchSize [bytes/lane]:" in line and name:
+            size = int(line.split("ScratchSize [bytes/lane]:")[1].split("[")[0].strip())
+            if size > 0 and name.startswith(NO_SCRATCH):
+                bad.append((name, size))
+    return bad
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [_hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".hip"):
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile {src} failed:\n{res.stdout}\n{res.stderr}")
+    bad = _scratch_kernels(res.stderr)
+    if bad:
+        raise RuntimeError(f"compile {src}: kernels that must not spill use scratch memory: {bad}")
     return obj
 
 

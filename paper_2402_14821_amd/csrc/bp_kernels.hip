@@ -1442,33 +1442,32 @@ __device__ void part_bj1_lut(const TileArgs &t, const int64_t lam_out[LPL], int6
   const int64_t C = t.C;
   const int64_t l0 = uniform64(max(t.lo, t.lam0));
   const int64_t l1 = uniform64(min(t.hi, t.lam0 + 64 * LPL - 1));
-  int64_t lam[LPL], K[LPL], acc[LPL];
+  int64_t lam[LPL], acc[LPL];
+  int32_t K[LPL];
   for (int j = 0; j < LPL; ++j) {
     lam[j] = min(max(lam_out[j], l0), l1);
-    K[j] = C / lam[j];
+    K[j] = (int32_t)((uint32_t)C / (uint32_t)lam[j]);  // 32-bit: c < 2^31
     acc[j] = 0;
   }
-  const int64_t kmax = C / l0;
-  const int64_t qa = 1 + kmax * t.qc / t.qn, qb = kmax * (t.qc + 1) / t.qn;
-  // four q at a time, their loads in flight together (a q past a lane's K
-  // reads threshold 0 and is not added)
-  for (int64_t q0 = qa; q0 <= qb; q0 += 4) {
-    int64_t u[4][LPL];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      for (int j = 0; j < LPL; ++j) {
-        const int64_t q = q0 + v;
-        const bool in = q <= qb && q <= K[j];
-        u[v][j] = lut_u(t, in ? C - q * lam[j] : 0) - lut_u(t, in ? q * lam[j] : 0);
-        if (!in) u[v][j] = 0;
-      }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      for (int j = 0; j < LPL; ++j) acc[j] += u[v][j];
+  const int64_t kmax = (int64_t)((uint32_t)C / (uint32_t)l0);
+  const int64_t qa = 1 + (int64_t)((uint64_t)kmax * (uint32_t)t.qc / (uint32_t)t.qn),
+                qb = (int64_t)((uint64_t)kmax * (uint32_t)(t.qc + 1) / (uint32_t)t.qn);
+  // one parameter slot at a time (few registers: this runs inside the sweep
+  // kernel's 64-register budget), two q per step with their loads in flight
+  for (int j = 0; j < LPL; ++j) {
+    const int64_t qe = min(qb, K[j]);
+    int64_t a0 = 0, a1 = 0;
+    int64_t q = qa;
+    for (; q + 1 <= qe; q += 2) {
+      a0 += lut_u(t, C - q * lam[j]) - lut_u(t, q * lam[j]);
+      a1 += lut_u(t, C - (q + 1) * lam[j]) - lut_u(t, (q + 1) * lam[j]);
+    }
+    if (q <= qe) a0 += lut_u(t, C - q * lam[j]) - lut_u(t, q * lam[j]);
+    acc[j] = a0 + a1;
   }
   const int64_t n = t.nz - t.nf;
   for (int j = 0; j < LPL; ++j)
-    part[j] = 2 * acc[j] - (t.qc == 0 ? t.sumNZ - n * (C % lam[j]) : 0);
+    part[j] = 2 * acc[j] - (t.qc == 0 ? t.sumNZ - n * (int64_t)((uint32_t)C % (uint32_t)lam[j]) : 0);
 }
 
 // f_CCM1 by lookups: the counts of part_ccm1_seg, sum_{q >= 1} #{small w >=
@@ -1484,30 +1483,33 @@ __device__ void part_ccm1_lut(const TileArgs &t, const int64_t lam_out[LPL], int
   const int64_t nbig = t.nb - t.nf;
   int64_t ns, ss;
   lut_ge(t, scap, ns, ss);  // #{w >= scap}
-  int64_t lam[LPL], Q[LPL], acc[LPL];
+  int64_t lam[LPL], acc[LPL];
+  int32_t Q[LPL];
   for (int j = 0; j < LPL; ++j) {
     lam[j] = min(max(lam_out[j], l0), l1);
-    Q[j] = half / lam[j];
+    Q[j] = (int32_t)((uint32_t)half / (uint32_t)lam[j]);  // 32-bit: c < 2^31
     acc[j] = 0;
   }
-  const int64_t qmax = half / l0;
-  const int64_t qa = 1 + qmax * t.qc / t.qn, qb = qmax * (t.qc + 1) / t.qn;
-  // four q at a time, their loads in flight together
-  for (int64_t q0 = qa; q0 <= qb; q0 += 4) {
-    int64_t u[4][LPL];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      for (int j = 0; j < LPL; ++j) {
-        const int64_t q = q0 + v;
-        const bool in = q <= qb && q <= Q[j];
-        int64_t a, b, s;
-        lut_ge(t, in ? q * lam[j] : scap, a, s);      // small sizes >= q lambda: #{w >= q lambda} - #{w >= scap}
-        lut_ge(t, in ? C - q * lam[j] + 1 : C, b, s);  // big sizes >= c - q lambda + 1, less the nf sizes c
-        u[v][j] = in ? (a - ns) - (nbig - (b - t.nf)) : 0;
-      }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      for (int j = 0; j < LPL; ++j) acc[j] += u[v][j];
+  const int64_t qmax = (int64_t)((uint32_t)half / (uint32_t)l0);
+  const int64_t qa = 1 + (int64_t)((uint64_t)qmax * (uint32_t)t.qc / (uint32_t)t.qn),
+                qb = (int64_t)((uint64_t)qmax * (uint32_t)(t.qc + 1) / (uint32_t)t.qn);
+  // one parameter slot at a time, two q per step (as part_bj1_lut)
+  auto term = [&](int64_t q, int64_t l) {
+    int64_t a, b, s;
+    lut_ge(t, q * l, a, s);          // small sizes >= q lambda: #{w >= q lambda} - #{w >= scap}
+    lut_ge(t, C - q * l + 1, b, s);  // big sizes >= c - q lambda + 1, less the nf sizes c
+    return (a - ns) - (nbig - (b - t.nf));
+  };
+  for (int j = 0; j < LPL; ++j) {
+    const int64_t qe = min(qb, Q[j]);
+    int64_t a0 = 0, a1 = 0;
+    int64_t q = qa;
+    for (; q + 1 <= qe; q += 2) {
+      a0 += term(q, lam[j]);
+      a1 += term(q + 1, lam[j]);
+    }
+    if (q <= qe) a0 += term(q, lam[j]);
+    acc[j] = a0 + a1;
   }
   for (int j = 0; j < LPL; ++j) part[j] = 2 * acc[j];
 }
@@ -1681,21 +1683,19 @@ __device__ void tile_l2(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL
   }
 }
 
-// #{w > x[j]} over the decreasing sizes for NT thresholds per lane, by
-// binary lifting with a fixed number of steps, every search of the lane in
-// lockstep so that their loads are in flight together.
-template <int LPL, int NT>
-__device__ __forceinline__ void count_above(const TileArgs &t, const int64_t (&x)[NT][LPL], int32_t (&n)[NT][LPL]) {
+// #{w > x[k]} over the decreasing sizes for NT thresholds, by binary
+// lifting with a fixed number of steps, the NT searches in lockstep so that
+// their loads are in flight together.
+template <int NT>
+__device__ __forceinline__ void count_above(const TileArgs &t, const int64_t (&x)[NT], int32_t (&n)[NT]) {
   const int32_t r = t.r;
-  for (int k = 0; k < NT; ++k)
-    for (int j = 0; j < LPL; ++j) n[k][j] = 0;
+  for (int k = 0; k < NT; ++k) n[k] = 0;
   for (int32_t step = r > 0 ? (int32_t)(1u << (31 - __clz(r))) : 0; step > 0; step >>= 1) {
-    for (int k = 0; k < NT; ++k)
-      for (int j = 0; j < LPL; ++j) {
-        const int32_t q = n[k][j] + step;
-        const int64_t v = t.sorted[min(q, r) - 1];
-        if (q <= r && v > x[k][j]) n[k][j] = q;
-      }
+    for (int k = 0; k < NT; ++k) {
+      const int32_t q = n[k] + step;
+      const int64_t v = t.sorted[min(q, r) - 1];
+      if (q <= r && v > x[k]) n[k] = q;
+    }
   }
 }
 
@@ -1710,8 +1710,6 @@ template <int LPL>
 __device__ void tile_mt_cand(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL], bool ok[LPL]) {
   const int64_t C = t.C;
   const int32_t r = t.r;
-  int64_t x[2][LPL];
-  int32_t n[2][LPL];
   for (int j = 0; j < LPL; ++j) {
     const int64_t cidx = t.lam0 + lane_id() + 64 * j;
     int64_t lam = -1;
@@ -1723,12 +1721,10 @@ __device__ void tile_mt_cand(const TileArgs &t, int64_t lam_out[LPL], int64_t lb
     ok[j] = lam >= t.lo && lam <= t.hi;
     if (!ok[j]) lam = t.lo;
     lam_out[j] = lam;
-    x[0][j] = C - lam;  // n1 = #{w > c - lambda}
-    x[1][j] = lam - 1;  // j3 = #{w > lambda - 1}
-  }
-  count_above<LPL, 2>(t, x, n);
-  for (int j = 0; j < LPL; ++j) {
-    const int32_t n1 = n[0][j], j3 = max(n[1][j], n1);
+    const int64_t x[2] = {C - lam, lam - 1};  // n1 = #{w > c - lambda}, j3 = #{w > lambda - 1}
+    int32_t n[2];
+    count_above<2>(t, x, n);
+    const int32_t n1 = n[0], j3 = max(n[1], n1);
     lbp[j] = (int64_t)(n1 - t.nf) + ceil_div_small(t.pre[j3] - t.pre[n1], C);
   }
 }
@@ -1747,8 +1743,7 @@ template <int LPL>
 __device__ void tile_rad2_cand(const TileArgs &t, int64_t lam_out[LPL], int64_t lbp[LPL], bool ok[LPL]) {
   const int64_t C = t.C;
   const int32_t r = t.r;
-  int64_t x[4][LPL];
-  int32_t n[4][LPL];
+  const int64_t f3 = C / 3, f2 = C / 2;
   for (int j = 0; j < LPL; ++j) {
     const int64_t cidx = t.lam0 + lane_id() + 64 * j;
     int64_t lam = -1;
@@ -1765,15 +1760,10 @@ __device__ void tile_rad2_cand(const TileArgs &t, int64_t lam_out[LPL], int64_t 
     ok[j] = lam >= t.lo && lam <= t.hi;
     if (!ok[j]) lam = t.lo;
     lam_out[j] = lam;
-    x[0][j] = lam - 1;
-    x[1][j] = C - 2 * lam;
-    x[2][j] = 2 * lam - 1;
-    x[3][j] = C - lam;
-  }
-  count_above<LPL, 4>(t, x, n);
-  const int64_t f3 = C / 3, f2 = C / 2;
-  for (int j = 0; j < LPL; ++j) {
-    const int64_t a = n[0][j], b = n[1][j], g = n[2][j], e = n[3][j];
+    const int64_t x[4] = {lam - 1, C - 2 * lam, 2 * lam - 1, C - lam};
+    int32_t n[4];
+    count_above<4>(t, x, n);
+    const int64_t a = n[0], b = n[1], g = n[2], e = n[3];
     const int64_t S = f3 * (a - b) + f2 * (b - g) + (C - f3) * (g - e) + C * e;
     lbp[j] = ceil_div_small(S, C) - t.nf;
   }
