@@ -53,10 +53,12 @@ typedef int32_t bp_status;
 #define BP_ERR_LIMIT (-7)  /* input larger than the library's limits */
 
 /* Largest instance a check takes: n + m (residual form) or r (items form)
- * at most BP_MAX_ITEMS, because one workgroup sorts an instance in its LDS;
+ * at most 16 384 (one workgroup sorts such an instance in its LDS), or at
+ * most BP_MAX_ITEMS when c <= 2^21 and c <= 16 (n + m) (the instance is then
+ * prepared from tables of c + 2 entries by kernels over the whole GPU);
  * larger ones are BP_ERR_LIMIT.  The standalone reductions take up to
  * BP_MAX_REDUCE_ITEMS. */
-#define BP_MAX_ITEMS (1 << 14)
+#define BP_MAX_ITEMS (1 << 20)
 #define BP_MAX_REDUCE_ITEMS (1 << 30)
 #define BP_MAX_BATCH (1 << 20) /* most instances in one batched call */
 
@@ -453,7 +455,7 @@ typedef struct bp_solve_result {
  * bp_subset_sum_gap) to a fixpoint and then the feasibility check of Alg. 1.
  * The reductions and the symmetry constraint the paper's solvers add from
  * other work are not built.  bin_of[n] (optional) receives the packing, in
- * the caller's item order.  Sizes in [0, C], n <= BP_MAX_ITEMS.  Errors:
+ * the caller's item order.  Sizes in [0, C], n <= 16 384.  Errors:
  * BP_ERR_ARG (NULL, C < 1, unknown mode, the library's check without a
  * context), BP_ERR_RANGE (a size outside [0, C]), BP_ERR_LIMIT, or the
  * check's own error, which stops the search. */

@@ -28,7 +28,7 @@ BP_SWEEP_PAPER_VB2_CLAMP = 1
 BP_SWEEP_SEGMENTS = 2
 BP_NO_EARLY_EXIT = 1
 BP_SEGMENTS = 2
-BP_MAX_ITEMS = 1 << 14
+BP_MAX_ITEMS = 1 << 20
 BP_MAX_REDUCE_ITEMS = 1 << 30
 BP_NOALLOC_MAX_ITEMS = 1 << 14
 BP_NOALLOC_SCRATCH_BYTES = 32 << 20

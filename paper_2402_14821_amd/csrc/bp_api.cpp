@@ -431,16 +431,17 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
     p.C = q.C;
     p.form = q.form;
     const int64_t rcap = q.n_in + q.m_res;
-    if (rcap > kLargeCap)
-      return fail(BP_ERR_LIMIT, "instance %lld: %lld reduced items exceed the %d-item limit of this build",
-                  (long long)i, (long long)rcap, kLargeCap);
+    if (!instance_fits(q.C, rcap))
+      return fail(BP_ERR_LIMIT,
+                  "instance %lld: %lld reduced items; more than %d need c <= %d and c <= %lld x the items",
+                  (long long)i, (long long)rcap, kLargeCap, kVtMaxC, (long long)kVtRatio);
     p.r_cap = (int32_t)rcap;
-    p.large = rcap > kSmallCap ? 1 : 0;
+    p.large = rcap > kSmallCap ? 1 : 0;  // (above kLargeCap instance_fits leaves only the value tables)
     // Prepared from value tables by kernels over the whole GPU: a large
     // instance whose c is not much above its item count.  (For a few hundred
     // items the one-block prep and the windowed segment sums are faster than
     // tables of c entries, measured at c = 10^3 .. 10^6.)
-    if (value_prep && p.large && q.C <= kVtMaxC && (int64_t)q.C <= kVtRatio * rcap) {
+    if ((value_prep || rcap > kLargeCap) && p.large && q.C <= kVtMaxC && (int64_t)q.C <= kVtRatio * rcap) {
       p.large = 2;
       p.vt_off = vt;
       vt += (int64_t)q.C + 2;
@@ -669,7 +670,13 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   for (const Entry &e : ent)
     if (e.mode == kModeSegments && (e.bound == kBJ1 || e.bound == kCCM1)) seg_tiles += e.ntiles;
   const bool split_seg = seg_tiles < (int64_t)grid_sweep;
+  // Partial-sum slots of the split tiles stay under kMaxAccBytes: past it the
+  // chunk count of the item-split tiles is halved until they fit (a tile of a
+  // huge instance could otherwise ask for 64 chunks of every parameter).
+  int64_t max_chunks = 64;
   int64_t acc = 0, cnt = 0;
+  for (;;) {
+  int64_t slots = 0;
   for (size_t j = 0; j < ent.size(); ++j) {
     Entry &e = ent[j];
     const double tc = tile_cost_v[j];
@@ -700,10 +707,14 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
                                         : min_chunk;
       const int64_t maxch = std::max<int64_t>(1, rcap_v[j] / minc);
       const int64_t want = (int64_t)std::ceil(tc / target);
-      e.nchunks = (int32_t)std::min<int64_t>(std::min<int64_t>(want, maxch), 64);
+      e.nchunks = (int32_t)std::min<int64_t>(std::min<int64_t>(want, maxch), max_chunks);
       e.tpt = 1;
       task_cost[j] = tc / e.nchunks;
     }
+    if (e.nchunks > 1) slots += e.ntiles * e.nchunks * tile;
+  }
+  if (slots * (int64_t)sizeof(long long) <= kMaxAccBytes || max_chunks == 1) break;
+  max_chunks /= 2;
   }
   std::vector<size_t> order(ent.size());
   for (size_t j = 0; j < order.size(); ++j) order[j] = j;

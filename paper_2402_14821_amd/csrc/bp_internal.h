@@ -32,7 +32,7 @@ constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
-static_assert(kLargeCap == BP_MAX_ITEMS, "the check's item limit is the large prep block's capacity");
+static_assert(kLargeCap <= BP_MAX_ITEMS, "the block prep's capacity is within the check's item limit");
 // Value-table prep (several kernels over the whole GPU instead of one
 // block): a count per size value, suffix-scanned into #{w >= v} and
 // sum{w : w >= v}, from which the sorted sizes, their prefix sums, the class
@@ -45,6 +45,14 @@ constexpr int kVtThreads = 256;
 constexpr int32_t kVtMaxC = 1 << 21;
 constexpr int64_t kVtRatio = 16;
 constexpr int kVtMaxChunks = (kVtMaxC + 2 + kVtChunk - 1) / kVtChunk;
+// An instance of r reduced items fits a check when the block prep takes it
+// (r <= kLargeCap) or the value-table prep does (c <= kVtMaxC, c <= kVtRatio r),
+// up to BP_MAX_ITEMS.
+inline bool instance_fits(int32_t C, int64_t r) {
+  return r <= kLargeCap || (r <= BP_MAX_ITEMS && C <= kVtMaxC && (int64_t)C <= kVtRatio * r);
+}
+// most bytes of split-tile partial sums one launch may use
+constexpr int64_t kMaxAccBytes = int64_t(1) << 30;
 
 // Input form of an instance.
 enum : int32_t { kFormItems = 0, kFormResidual = 1 };

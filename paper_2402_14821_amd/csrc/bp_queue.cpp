@@ -140,11 +140,15 @@ int64_t param_count(int32_t C) {
 }
 
 // Bytes charged to an admitted request: for the full pipeline its inputs,
-// sorted sizes, stream records, prefix sums and one partial-sum slot per
-// parameter; for a child its changed items and task record.
+// sorted sizes, stream records, prefix sums, one partial-sum slot per
+// parameter and, for an instance the planner prepares from value tables
+// (large, c at most kVtRatio times its items), those tables; for a child its
+// changed items and task record.
 size_t full_bytes(int64_t n, int64_t m, int32_t C) {
   const int64_t r = n + m;
-  return (size_t)(4 * (n + m) + 16 * r + 8 * (r + 1) + 8 * param_count(C)) + sizeof(InstPlan) +
+  const bool vt = r > kSmallCap && C <= kVtMaxC && (int64_t)C <= kVtRatio * r;
+  const int64_t tables = vt ? 12 * ((int64_t)C + 2) + 32 * (((int64_t)C + 2 + kVtChunk - 1) / kVtChunk) + 4 : 0;
+  return (size_t)(4 * (n + m) + 16 * r + 8 * (r + 1) + 8 * param_count(C) + tables) + sizeof(InstPlan) +
          sizeof(InstState) + kNB * 8 + sizeof(bp_bounds) + 8 * sizeof(Entry) + 256;
 }
 size_t child_bytes(int32_t ncommit) {
@@ -710,7 +714,8 @@ bp_status bp_queue_submit(bp_queue *qh, const bp_request *req, int32_t blocking,
   if (child && (req->ncommit < 0 || req->ncommit > BP_MAX_COMMIT || (req->ncommit > 0 && !req->commits)))
     return fail(BP_ERR_ARG, "bad commit list");
   if (has_inst) {
-    if (req->n + req->m > kLargeCap) return fail(BP_ERR_LIMIT, "request of %lld items", (long long)(req->n + req->m));
+    if (!instance_fits(req->C, req->n + req->m))
+      return fail(BP_ERR_LIMIT, "request of %lld items at c = %d", (long long)(req->n + req->m), req->C);
     if ((st = host_validate_items(req->C, req->unpacked, req->n))) return st;
     if ((st = host_validate_items(req->C, req->residual, req->m))) return st;
   }

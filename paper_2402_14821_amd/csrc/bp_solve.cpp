@@ -509,7 +509,7 @@ bp_status bp_solve(bp_ctx *ctx, int32_t C, int64_t n, const int32_t *sizes, cons
                    int32_t *bin_of, bp_solve_result *out) {
   if (!opts || !out || (n > 0 && !sizes)) return fail(BP_ERR_ARG, "NULL argument");
   if (C < 1 || n < 0) return fail(BP_ERR_ARG, "bad capacity or count");
-  if (n > BP_MAX_ITEMS) return fail(BP_ERR_LIMIT, "%lld items > %d", (long long)n, BP_MAX_ITEMS);
+  if (n > kLargeCap) return fail(BP_ERR_LIMIT, "%lld items > %d", (long long)n, kLargeCap);
   if (!opts->check && opts->mode != BP_SOLVE_NO_CHECK && !ctx)
     return fail(BP_ERR_ARG, "the library's check needs a context");
   if (opts->mode != BP_SOLVE_DFFS && opts->mode != BP_SOLVE_L2 && opts->mode != BP_SOLVE_NO_CHECK)

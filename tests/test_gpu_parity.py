@@ -439,10 +439,34 @@ def test_block_capacity_boundaries(ctx, r):
     same(ctx.lower_bounds(C, r // 2, items), O.bounds(C, r // 2, items), ("cap", r))
 
 
+def test_more_items_than_one_block_sorts(ctx):
+    # past 16 384 reduced items the value tables prepare the instance: both
+    # forms against the oracle's record (ranges split over a thread pool)
+    g = np.random.default_rng(2024)
+    C, n, m = 12000, 30000, 8000
+    unp = g.integers(1, C // 2 + 1, size=n).astype(np.int32)
+    res = g.integers(C // 3, C + 1, size=m).astype(np.int32)
+    items = O.residual_reduce(C, res, unp)
+    want = oracle_par.dense_record(C, m, items)
+    say("more items", C, n, m, len(items))
+    for flags in (0, bp.BP_SEGMENTS):
+        got = ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT | flags)
+        same(got, want, ("more items", flags))
+        assert got["r"] == len(items) > 16384
+    items2 = g.integers(0, 700, size=70000).astype(np.int32)
+    want2 = oracle_par.dense_record(700, 30000, items2)
+    same(ctx.lower_bounds(700, 30000, items2), want2, "items form, 70 000 sizes")
+
+
 def test_limits_and_range_errors(ctx):
     say("errors")
+    # more than 16 384 items need c <= 2^21 and c <= 16 r (value tables)
+    for C in (1 << 22, 16 * 16385 + 1):
+        with pytest.raises(bp.BpError) as e:
+            ctx.lower_bounds(C, 1, np.ones(16385, np.int32))
+        assert e.value.status == bp.BP_ERR_LIMIT, C
     with pytest.raises(bp.BpError) as e:
-        ctx.lower_bounds(10, 1, np.ones(16385, np.int32))
+        ctx.lower_bounds(10, 1, np.ones(bp.BP_MAX_ITEMS + 1, np.int32))
     assert e.value.status == bp.BP_ERR_LIMIT
     with pytest.raises(bp.BpError) as e:
         ctx.lower_bounds(10, 1, [3, 11])
