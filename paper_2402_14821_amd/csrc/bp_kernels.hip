@@ -149,9 +149,16 @@ struct PrepSmem {
   int32_t flags[8];
 };
 
+// Rows of 64 keys per wave when n keys are spread evenly over the NW waves
+// (at most K = CAP / NT): wave w owns the keys [w 64 R, (w + 1) 64 R).
+template <int NW, int K>
+__device__ __forceinline__ int rows_per_wave(int n) {
+  return min(K, (((n + 63) >> 6) + NW - 1) / NW);
+}
+
 // Stable LSD radix sort (8-bit digits) of n keys in LDS, ascending.  Wave w
-// owns the keys [w 64 K, (w + 1) 64 K), K = CAP / NT, and holds them in
-// registers, key k of a lane at w 64 K + 64 k + lane.  Per digit pass each
+// owns the keys [w 64 R, (w + 1) 64 R), R = rows_per_wave(n), and holds them
+// in registers, key k of a lane at w 64 R + 64 k + lane.  Per digit pass each
 // wave ranks its keys in that order: a key's peers (lanes with the same
 // digit) come from ballots over the digit's bits, its rank is the wave's
 // running count of the digit plus the peers below it.  One block-wide scan
@@ -167,9 +174,10 @@ __device__ int lds_radix_sort(PrepSmem<NT, CAP> &sm, int n) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  const int wbase = wave * 64 * K;
+  const int R = rows_per_wave<NW, K>(n);
+  const int wbase = wave * 64 * R;
   // number of key rows of this wave that hold any key (wave-uniform)
-  const int rows = n > wbase ? min(K, (n - wbase + 63) >> 6) : 0;
+  const int rows = n > wbase ? min(R, (n - wbase + 63) >> 6) : 0;
   // key range: per-wave minimum and maximum, then every thread combines them
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   for (int k = 0; k < rows; ++k) {
@@ -274,8 +282,9 @@ __device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  const int wbase = wave * 64 * K;
-  const int rows = n > wbase ? min(K, (n - wbase + 63) >> 6) : 0;
+  const int R = rows_per_wave<NW, K>(n);
+  const int wbase = wave * 64 * R;
+  const int rows = n > wbase ? min(R, (n - wbase + 63) >> 6) : 0;
   uint64_t mine = 0;
   for (int k = 0; k < rows; ++k) {
     const int i = wbase + 64 * k + lane;
