@@ -68,6 +68,8 @@ def _load():
                                   _P64, _P64, _P64, _P64, _P64]
     lib.oracle_dff_bound_strided.argtypes = [ctypes.c_int, _I64, _P64, _I64, _I64, _I64, _I64, _P64, _P64]
     lib.oracle_dff_bound_strided.restype = _I64
+    lib.oracle_event_bound.argtypes = [ctypes.c_int, _I64, _P64, _I64, _I64, _I64, _P64]
+    lib.oracle_event_bound.restype = _I64
     _lib = lib
     return lib
 
@@ -156,6 +158,42 @@ def piecewise_bound(kind: int, C: int, items, lo: int | None = None, hi: int | N
     if v < 0:
         raise OracleError("allocation failure")
     return int(v), int(arg.value)
+
+
+def event_bound(dff: int, C: int, items, lo: int | None = None, hi: int | None = None):
+    """CCM1 or BJ1 by the event sweep (any capacity): (value, smallest argmax)."""
+    a = _arr(items)
+    dlo, dhi = default_range(dff, C)
+    lo = dlo if lo is None else lo
+    hi = dhi if hi is None else hi
+    arg = ctypes.c_int64(0)
+    v = _load().oracle_event_bound(dff, C, _ptr(a), len(a), lo, hi, ctypes.byref(arg))
+    if v < 0:
+        raise OracleError("bad argument or allocation failure")
+    return int(v), int(arg.value)
+
+
+def bounds_by_pieces(C: int, k: int, items, threads: int | None = None) -> dict:
+    """Every bound over the default ranges without visiting every parameter,
+    except VB2 (left out, value and argmax -1): L2, MT and RAD2 at their piece
+    starts, CCM1 and BJ1 by the event sweep, FS1 (100 parameters) directly.
+    For capacities where the dense loops are out of reach; lb and the verdict
+    are over the bounds computed."""
+    a = _arr(items)
+    jobs = {L2: lambda: piecewise_bound(L2, C, a), MT: lambda: piecewise_bound(MT, C, a),
+            RAD2: lambda: piecewise_bound(RAD2, C, a), FS1: lambda: dff_bound(FS1, C, a),
+            CCM1: lambda: event_bound(CCM1, C, a), BJ1: lambda: event_bound(BJ1, C, a)}
+    with ThreadPoolExecutor(max_workers=threads or len(jobs)) as ex:
+        futs = {b: ex.submit(fn) for b, fn in jobs.items()}
+        res = {b: f.result() for b, f in futs.items()}
+    val = np.full(NB, -1, dtype=np.int64)
+    arg = np.full(NB, -1, dtype=np.int64)
+    val[L1] = l1(C, a)
+    for b, (v, g) in res.items():
+        val[b], arg[b] = v, g
+    lb = int(val.max())
+    lb_arg = int(np.argmax(val))
+    return {"value": val, "argmax": arg, "lb": lb, "lb_arg": lb_arg, "verdict": int(lb <= k), "r": len(a)}
 
 
 def bounds(C: int, k: int, items, lo=None, hi=None, l2_dense: bool = False) -> dict:

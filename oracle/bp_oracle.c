@@ -364,3 +364,139 @@ i64 oracle_dff_bound_strided(int id, i64 C, const i64 *W, i64 r, i64 lo, i64 hi,
   if (evals) *evals = ev;
   return best;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Event sweep of f_CCM1 and f_BJ1 (Sec. 3.1) over [lo, hi], for capacities
+ * too large to visit every lambda.  Same result as oracle_dff_bound: the
+ * maximum of ceil(sum_w f(w, lambda) / f(c, lambda)) and its smallest
+ * maximiser.
+ *
+ * Both functions read lambda only through Q = floor(c / lambda) and, per size,
+ * floor-quotients by lambda.  On a run of lambda with Q fixed:
+ *   CCM1  each case of the definition is an integer combination of Q and of
+ *         t = floor(v / lambda) with v = w (small item) or v = c - w (big
+ *         item); t holds until lambda passes floor(v / t), so the item's value
+ *         is constant until floor(v / t) + 1 (for ever once t = 0);
+ *   BJ1   writing c mod lambda = c - Q lambda and w mod lambda = w - q lambda
+ *         with q = floor(w / lambda), the definition reads
+ *           f = q ((Q + 1) lambda - c) + max(0, (w - c) + (Q - q) lambda),
+ *         linear in lambda while q holds (until floor(w / q) + 1) and the
+ *         max keeps its case; with Q - q >= 0 the second term can only turn
+ *         positive as lambda grows, at floor((c - w) / (Q - q)) + 1.
+ * f(c, lambda) is the same expression at w = c (2Q for CCM1, Q((Q + 1)
+ * lambda - c) >= Q > 0 for BJ1).  Between two consecutive change points of
+ * any item the sum and f(c, .) are linear in lambda, the denominator is
+ * positive, so their ratio is monotone and so is its ceiling: the stretch's
+ * maximum is at one of its ends, and when the ceiling rises along the
+ * stretch its smallest maximiser is found by bisection.  Items are visited
+ * in the order of their next change point (a binary heap); every item is
+ * re-read when Q changes.  Sums are held as A + B lambda in 128-bit integers.
+ *
+ * Needs 1 <= lo and hi <= c (where both functions are defined).  Returns -1
+ * on a bad argument or allocation failure. */
+typedef __int128 i128;
+
+#define EV_NEVER INT64_MAX
+
+/* Item w's value on lambda's stretch (Q = floor(c / lambda) fixed):
+ * a + b * lambda up to next - 1. */
+static void ev_piece(int id, i64 C, i64 w, i64 lam, i64 Q, i128 *a, i128 *b, i64 *next) {
+  if (id == OR_CCM1) {
+    *b = 0;
+    if (2 * w > C) {
+      i64 u = C - w, t = u / lam;
+      *a = 2 * Q - 2 * t;
+      *next = t > 0 ? u / t + 1 : EV_NEVER;
+    } else if (2 * w == C) {
+      *a = Q;
+      *next = EV_NEVER;
+    } else {
+      i64 t = w / lam;
+      *a = 2 * t;
+      *next = t > 0 ? w / t + 1 : EV_NEVER;
+    }
+    return;
+  }
+  /* BJ1 */
+  i64 q = w / lam, d = Q - q;
+  int on = (w - C) + d * lam > 0;
+  *a = -(i128)q * C + (on ? (w - C) : 0);
+  *b = (i128)q * (Q + 1) + (on ? d : 0);
+  i64 nq = q > 0 ? w / q + 1 : EV_NEVER;
+  i64 nk = (!on && d > 0) ? (C - w) / d + 1 : EV_NEVER;
+  *next = nq < nk ? nq : nk;
+}
+
+static i64 ev_ceil(i128 s, i128 f) { return (i64)(s / f + (s % f != 0)); }
+
+static void ev_sift(i64 *heap, i64 n, const i64 *key, i64 at) {
+  for (;;) {
+    i64 l = 2 * at + 1, m = at;
+    if (l < n && key[heap[l]] < key[heap[m]]) m = l;
+    if (l + 1 < n && key[heap[l + 1]] < key[heap[m]]) m = l + 1;
+    if (m == at) return;
+    i64 t = heap[at]; heap[at] = heap[m]; heap[m] = t;
+    at = m;
+  }
+}
+
+i64 oracle_event_bound(int id, i64 C, const i64 *W, i64 r, i64 lo, i64 hi, i64 *argmax) {
+  if ((id != OR_CCM1 && id != OR_BJ1) || C < 1 || C > OR_MAX_C || r < 0 || (r > 0 && !W)) return -1;
+  if (lo > hi) { if (argmax) *argmax = -1; return 0; }
+  if (lo < 1 || hi > C) return -1;
+  size_t nr = (size_t)(r > 0 ? r : 1);
+  i128 *a = (i128 *)malloc(sizeof(i128) * nr), *b = (i128 *)malloc(sizeof(i128) * nr);
+  i64 *next = (i64 *)malloc(sizeof(i64) * nr), *heap = (i64 *)malloc(sizeof(i64) * nr);
+  if (!a || !b || !next || !heap) { free(a); free(b); free(next); free(heap); return -1; }
+  i64 best = 0, arg = -1;
+  for (i64 lam = lo; lam <= hi;) {
+    i64 Q = C / lam, qend = C / Q;
+    if (qend > hi) qend = hi;
+    i128 D, E, A = 0, B = 0;
+    i64 unused;
+    ev_piece(id, C, C, lam, Q, &D, &E, &unused);
+    for (i64 i = 0; i < r; i++) {
+      ev_piece(id, C, W[i], lam, Q, &a[i], &b[i], &next[i]);
+      A += a[i];
+      B += b[i];
+      heap[i] = i;
+    }
+    for (i64 i = r / 2 - 1; i >= 0; i--) ev_sift(heap, r, next, i);
+    for (i64 cur = lam;;) {
+      i64 stop = r > 0 ? next[heap[0]] : EV_NEVER;
+      if (stop > qend + 1) stop = qend + 1;
+      /* the stretch [cur, stop - 1] */
+      i64 x = cur, y = stop - 1;
+      i64 gx = ev_ceil(A + B * x, D + E * x), gy = ev_ceil(A + B * y, D + E * y), m, at;
+      if (gx >= gy) {
+        m = gx;
+        at = x;
+      } else {
+        m = gy;
+        i64 l2 = x + 1, h2 = y;
+        while (l2 < h2) {
+          i64 mid = l2 + (h2 - l2) / 2;
+          if (ev_ceil(A + B * mid, D + E * mid) >= m) h2 = mid;
+          else l2 = mid + 1;
+        }
+        at = l2;
+      }
+      if (arg < 0 || m > best) { best = m; arg = at; }
+      if (stop > qend) break;
+      while (next[heap[0]] == stop) {
+        i64 i = heap[0];
+        A -= a[i];
+        B -= b[i];
+        ev_piece(id, C, W[i], stop, Q, &a[i], &b[i], &next[i]);
+        A += a[i];
+        B += b[i];
+        ev_sift(heap, r, next, 0);
+      }
+      cur = stop;
+    }
+    lam = qend + 1;
+  }
+  free(a); free(b); free(next); free(heap);
+  if (argmax) *argmax = arg;
+  return best;
+}

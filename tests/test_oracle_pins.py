@@ -252,6 +252,72 @@ def test_piece_starts_match_every_lambda():
             assert O.piecewise_bound(kind, C, items) == dense, (O.NAMES[kind], C, items)
 
 
+def test_event_sweep_matches_every_lambda():
+    # the CCM1 / BJ1 event sweep against the per-lambda definition, on full
+    # ranges and random sub-ranges, with the boundary sizes over-represented
+    rng = random.Random(29)
+    for t in range(700):
+        C = rng.choice([rng.randint(1, 12), rng.randint(1, 200), rng.randint(1, 2500)])
+        pool = [0, 1, C - 1, C, C // 2, (C + 1) // 2, max(0, C // 2 - 1), min(C, C // 2 + 1)]
+        items = [rng.choice(pool) if rng.random() < 0.3 else rng.randint(0, C) for _ in range(rng.randint(0, 30))]
+        for dff in (O.CCM1, O.BJ1):
+            lo, hi = O.default_range(dff, C)
+            if t % 2 and hi >= lo:
+                lo = rng.randint(lo, hi)
+                hi = rng.randint(lo - 1, hi)
+            assert O.event_bound(dff, C, items, lo, hi) == O.dff_bound(dff, C, items, lo, hi), (
+                O.NAMES[dff], C, lo, hi, items)
+    # a medium capacity with many items: long runs of constant quotients
+    r2 = np.random.default_rng(31)
+    for C in (46_340, 65_536, 99_991):
+        items = np.concatenate([r2.integers(C // 10, C // 2, 120), r2.integers(C // 2, C + 1, 40)])
+        for dff in (O.CCM1, O.BJ1):
+            assert O.event_bound(dff, C, items) == O.dff_bound(dff, C, items), (O.NAMES[dff], C)
+
+
+def _definition_value(dff, C, items, lam):
+    return -(-sum(O.f(dff, C, int(w), lam) for w in items) // O.f(dff, C, C, lam))
+
+
+def test_event_sweep_at_huge_capacities():
+    # where every lambda is out of reach: the reported maximum is attained at
+    # the reported parameter, no sampled parameter beats it, none sampled
+    # below it reaches it, BJ1 is at least L1 (lambda = c), and an instance
+    # scaled by s has at least the bound of the original (f(s w, s lambda) at
+    # capacity s c is s f(w, lambda) for BJ1 and f(w, lambda) for CCM1)
+    r2 = np.random.default_rng(37)
+    for C in (2**31 - 1, 2**30, 1_000_000_007, 2 * 3 * 5 * 7 * 11 * 13 * 17 * 19 * 23):
+        items = np.concatenate([r2.integers(C // 3, C // 2 + 2, 25), r2.integers(C // 2, C + 1, 10),
+                                r2.integers(0, C // 5, 15), [C // 2, C, 0]])
+        for dff in (O.CCM1, O.BJ1):
+            v, arg = O.event_bound(dff, C, items)
+            lo, hi = O.default_range(dff, C)
+            assert lo <= arg <= hi
+            assert _definition_value(dff, C, items, arg) == v
+            for lam in list(r2.integers(lo, hi + 1, 150)) + list(range(lo, min(hi, lo + 50) + 1)):
+                g = _definition_value(dff, C, items, int(lam))
+                assert g <= v and (g < v or lam >= arg), (O.NAMES[dff], C, lam)
+            if dff == O.BJ1:
+                assert v >= O.l1(C, items)
+    base_C = 997
+    base = [int(x) for x in r2.integers(200, base_C + 1, 40)]
+    for s in (3, 1_000_003, 2_000_000):
+        for dff in (O.CCM1, O.BJ1):
+            v0 = O.dff_bound(dff, base_C, base)[0]
+            assert O.event_bound(dff, base_C * s, [w * s for w in base])[0] >= v0
+
+
+def test_event_sweep_rejects_what_it_cannot_do():
+    with pytest.raises(O.OracleError):
+        O.event_bound(O.VB2, 10, [3])
+    with pytest.raises(O.OracleError):
+        O.event_bound(O.BJ1, 10, [3], 0, 5)  # lambda = 0 is outside the definition
+    with pytest.raises(O.OracleError):
+        O.event_bound(O.BJ1, 10, [3], 1, 11)
+    assert O.event_bound(O.BJ1, 10, [3], 5, 4) == (0, -1)
+    assert O.event_bound(O.CCM1, 10, [], 1, 5) == (0, 1)
+
+
 def test_reduction_forms_agree_and_keep_total_size():
     rng = random.Random(17)
     for _ in range(200):
