@@ -3,9 +3,11 @@ triplet-tight batch with huge capacities.
 
 Every instance of each batch runs on the GPU in one launch.  Verdicts are
 pinned for all of them by construction; full records are compared with the
-oracle on seeded samples the oracle finishes in seconds.
+oracle on seeded samples the oracle finishes in seconds, and the full ranges
+of a few triplet instances with the oracle's piece-start and event sweeps.
 """
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -114,15 +116,22 @@ def test_triplet_batch_windowed(ctx):
 def test_triplet_full_ranges_by_construction(ctx):
     # full parameter ranges (up to 2^31 - 1) on the instances with the largest
     # and the smallest capacities; pinned by the construction alone
+    # and every bound but VB2 against the oracle's piece-start and event sweeps
     tb = W.triplet_batch(5, count=1024)
     order = np.argsort(tb.C)
-    for i in list(order[:3]) + list(order[-2:]):
-        C, k, items = tb.instance(int(i))
+    pick = [int(i) for i in list(order[:3]) + list(order[-2:])]
+    with ThreadPoolExecutor(max_workers=5) as ex:
+        wants = list(ex.map(lambda i: O.bounds_by_pieces(*tb.instance(i), threads=6), pick))
+    for i, want in zip(pick, wants):
+        C, k, items = tb.instance(i)
         m = len(items) // 3
-        say("triplet full range", int(i), C, len(items))
+        say("triplet full range", i, C, len(items))
         got = ctx.lower_bounds(C, k, items)
         assert got["status"] == 0
         assert got["value"][O.L1] == m and (got["value"] <= m).all() and got["lb"] == m
         assert got["verdict"] == (0 if tb.expect_fail[i] else 1)
         P = sum(max(0, hi - lo + 1) for lo, hi in (O.default_range(d, C) for d in O.DFFS))
         assert got["evals"] == len(items) * P
+        keep = [b for b in range(O.NB) if b != O.VB2]
+        assert np.array_equal(got["value"][keep], want["value"][keep]), (i, got["value"], want["value"])
+        assert np.array_equal(got["argmax"][keep], want["argmax"][keep]), (i, got["argmax"], want["argmax"])

@@ -6,7 +6,8 @@ The single large residual instance (r = 14 000, C = 100 000) is compared
 field by field with the oracle's dense record (every parameter of every
 range, L2 included, split over a thread pool), and per parameter: copies of
 it in one batch, each swept at single parameters or short windows.
-Capacities near 2^31 are compared on windows at both ends of every range.
+Capacities near 2^31 are compared on windows at both ends of every range,
+and over full ranges against the oracle's piece-start and event sweeps.
 """
 import os
 import random
@@ -405,6 +406,43 @@ def test_huge_capacity_windows(ctx):
                 say("huge C", C, t, side, n)
                 got = ctx.lower_bounds(C, n, items, bp.make_sweep(lo, hi))
                 same(got, O.bounds(C, n, items, lo, hi, l2_dense=False), ("huge", C, side, items))
+
+
+def _unpairable_instance(seed, C, r):
+    # items of 0.55-0.6 c and of 0.46-0.5 c never share a bin, so the DFF
+    # bounds beat L1 and their maximisers sit inside the ranges
+    g = np.random.default_rng(seed)
+    a = g.integers(int(C * 0.55), int(C * 0.6), int(r * 0.4))
+    b = g.integers(int(C * 0.46), C // 2, int(r * 0.4))
+    c = g.integers(1, C // 20, r - len(a) - len(b))
+    return np.concatenate([a, b, c]).astype(np.int32)
+
+
+def test_huge_capacity_full_ranges(ctx):
+    # every parameter of every range at capacities up to 2^31 - 1 (dense and
+    # segment form) against the oracle's piece-start and event sweeps; VB2 has
+    # no such oracle path: its value only enters lb
+    cases = [(1, 2**31 - 1, 700), (2, 1_000_000_007, 900), (3, 123_456_789, 1500)]
+    insts = [(C, _unpairable_instance(seed, C, r)) for seed, C, r in cases]
+    with oracle_par.ThreadPoolExecutor(max_workers=3) as ex:
+        wants = list(ex.map(lambda ci: O.bounds_by_pieces(ci[0], 0, ci[1], threads=6), insts))
+    for (C, items), want in zip(insts, wants):
+        k = int(want["value"].max())
+        for flags in (0, bp.BP_SWEEP_SEGMENTS):
+            say("huge C full ranges", C, len(items), flags)
+            got = ctx.lower_bounds(C, k, items, bp.default_sweep(C, 0, 0, flags))
+            assert got["status"] == 0
+            for b in range(O.NB):
+                if b == O.VB2:
+                    continue
+                assert got["value"][b] == want["value"][b], (C, flags, O.NAMES[b], got["value"], want["value"])
+                assert got["argmax"][b] == want["argmax"][b], (C, flags, O.NAMES[b], got["argmax"], want["argmax"])
+            vals = want["value"].copy()
+            vals[O.VB2] = got["value"][O.VB2]
+            assert got["lb"] == int(vals.max()) and got["lb_arg"] == int(np.argmax(vals))
+            assert got["verdict"] == int(got["lb"] <= k)
+            assert got["evals"] == len(items) * sum(
+                max(0, hi - lo + 1) for lo, hi in (O.default_range(d, C) for d in O.DFFS))
 
 
 def test_edge_cases(ctx):
