@@ -181,6 +181,21 @@ static const Ctx::DivInfo &divisors_of(Ctx *c, int32_t C) {
     info.lattice.push_back((int32_t)pr[j]);
     info.lattice.push_back(ex[j]);
   }
+  // the divisibility-test constants of p_j^e, e = 1..a_j, prime by prime (at
+  // most 30 prime powers below 2^31), as (low, high) 32-bit halves
+  std::vector<uint64_t> pm;
+  for (size_t j = 0; j < pr.size(); ++j) {
+    uint64_t q = 1;
+    for (int32_t e = 1; e <= ex[j]; ++e) {
+      q *= (uint64_t)pr[j];
+      pm.push_back(divides_const((uint32_t)q));
+    }
+  }
+  info.lattice.push_back((int32_t)pm.size());
+  for (uint64_t m : pm) {
+    info.lattice.push_back((int32_t)(uint32_t)m);
+    info.lattice.push_back((int32_t)(uint32_t)(m >> 32));
+  }
   return c->div_cache.emplace(C, std::move(info)).first->second;
 }
 
@@ -280,8 +295,8 @@ void Ctx::destroy() {
   if (last_run && any_run) (void)hipEventSynchronize(last_run);
   drop_graphs();
   for (DevBuf *b : {&stage_buf, &counter_buf, &state_buf, &sorted_buf, &pre_buf, &rec_buf, &keys_buf, &ref_buf,
-                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf, &small_keys, &vcnt_buf, &vsum_buf, &vtot_buf,
-                    &vlat_buf, &vflag_buf})
+                    &acc_buf, &out_buf, &red_buf, &bidx_buf, &dcnt_buf, &small_keys, &vraw_buf, &vcnt_buf, &vsum_buf,
+                    &vtot_buf, &vlat_buf, &vflag_buf})
     b->release();
   for (HostBuf *b : {&stage_host, &in_host, &out_host, &red_host}) b->release();
   if (small_out) (void)hipHostFree(small_out);
@@ -783,17 +798,19 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if ((st = reserve_dev(acc_buf, sizeof(long long) * (size_t)std::max<int64_t>(acc_len, 1)))) return st;
   if ((st = reserve_dev(bidx_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(bidx_items, 1)))) return st;
   if ((st = reserve_dev(dcnt_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(dcnt_items, 1)))) return st;
-  // value tables: the counts and lattice bins are zero at rest (a new
-  // allocation is cleared here, each launch clears what it used)
+  // value tables: the raw counts, chunk totals, lattice bins, flags and
+  // maxima are zero at rest (a new allocation is cleared here, each launch
+  // clears what it used)
   bool clear_vt = false;
   if (!vt_list.empty()) {
-    const void *old_c = vcnt_buf.p, *old_l = vlat_buf.p, *old_f = vflag_buf.p;
+    const void *old_r = vraw_buf.p, *old_t = vtot_buf.p, *old_l = vlat_buf.p, *old_f = vflag_buf.p;
+    if ((st = reserve_dev(vraw_buf, sizeof(int32_t) * (size_t)vt_items))) return st;
     if ((st = reserve_dev(vcnt_buf, sizeof(int32_t) * (size_t)vt_items))) return st;
     if ((st = reserve_dev(vsum_buf, sizeof(long long) * (size_t)vt_items))) return st;
     if ((st = reserve_dev(vtot_buf, sizeof(long long) * (size_t)std::max<int64_t>(vtt_items, 1)))) return st;
     if ((st = reserve_dev(vlat_buf, sizeof(int32_t) * (size_t)std::max<int64_t>(vl_items, 1)))) return st;
-    if ((st = reserve_dev(vflag_buf, sizeof(int32_t) * vt_list.size()))) return st;
-    clear_vt = vt_dirty || vcnt_buf.p != old_c || vlat_buf.p != old_l || vflag_buf.p != old_f;
+    if ((st = reserve_dev(vflag_buf, 2 * sizeof(int32_t) * vt_list.size()))) return st;
+    clear_vt = vt_dirty || vraw_buf.p != old_r || vtot_buf.p != old_t || vlat_buf.p != old_l || vflag_buf.p != old_f;
   }
   char *h = (char *)stage_host.p;
   char *dv = (char *)stage_buf.p;
@@ -815,6 +832,7 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   d->divs = (const int32_t *)(dv + off_div);
   d->dcnt = (int32_t *)dcnt_buf.p;
   d->nodes = nodes;
+  d->vraw = (int32_t *)vraw_buf.p;
   d->vcnt = (int32_t *)vcnt_buf.p;
   d->vsum = (long long *)vsum_buf.p;
   d->vtot = (long long *)vtot_buf.p;
@@ -842,7 +860,8 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   if (!vt_list.empty()) {
     if (clear_vt) {
       // outside any captured graph: a plain stream operation before the launch
-      HIP_TRY(hipMemsetAsync(vcnt_buf.p, 0, vcnt_buf.cap, s));
+      HIP_TRY(hipMemsetAsync(vraw_buf.p, 0, vraw_buf.cap, s));
+      HIP_TRY(hipMemsetAsync(vtot_buf.p, 0, vtot_buf.cap, s));
       HIP_TRY(hipMemsetAsync(vlat_buf.p, 0, vlat_buf.cap, s));
       HIP_TRY(hipMemsetAsync(vflag_buf.p, 0, vflag_buf.cap, s));
     }

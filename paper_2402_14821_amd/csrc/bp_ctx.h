@@ -121,7 +121,9 @@ struct Ctx {
   std::vector<int32_t> div_vec;  // divisor lists of this launch (staged with the plan)
   // divisors of c by c, and c's divisor lattice: per divisor its bin
   // sum_j e_j stride_j (e_j its exponent of the j-th prime of c, stride_j =
-  // prod_{i<j} (a_i + 1)), then the prime count and (prime, exponent) pairs
+  // prod_{i<j} (a_i + 1)), then the prime count and (prime, exponent) pairs,
+  // then the prime-power count and each prime power's divisibility-test
+  // constant as (low, high) halves
   struct DivInfo {
     std::vector<int32_t> divs, lattice;
   };
@@ -130,7 +132,7 @@ struct Ctx {
   std::vector<Entry> entry_vec;
 
   DevBuf stage_buf, counter_buf, state_buf, sorted_buf, pre_buf, rec_buf, keys_buf, ref_buf, acc_buf, out_buf,
-      red_buf, bidx_buf, dcnt_buf, vcnt_buf, vsum_buf, vtot_buf, vlat_buf, vflag_buf;
+      red_buf, bidx_buf, dcnt_buf, vraw_buf, vcnt_buf, vsum_buf, vtot_buf, vlat_buf, vflag_buf;
   HostBuf stage_host, in_host, out_host, red_host;
   // The one-launch small check writes its record, then its sequence number,
   // to this coherent host memory: [bp_bounds][uint32 sequence].

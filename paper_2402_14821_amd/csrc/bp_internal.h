@@ -38,7 +38,7 @@ constexpr int kSmallCap = 8192;         // items per small-instance prep block (
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
 static_assert(kLargeCap <= BP_MAX_ITEMS, "the block prep's capacity is within the check's item limit");
-// Value-table prep (several kernels over the whole GPU instead of one
+// Value-table prep (two kernels over the whole GPU instead of one
 // block): a count per size value, suffix-scanned into #{w >= v} and
 // sum{w : w >= v}, from which the sorted sizes, their prefix sums, the class
 // bounds and the threshold tables are read off, and which the lookup tiles
@@ -165,14 +165,15 @@ struct LaunchDesc {
   unsigned long long *counter; // kQueues task counters of the persistent sweep, kQueueStride apart
   long long *acc;           // partial sums of split tiles, one slot per (tile, chunk, parameter)
   int32_t *bidx;            // threshold tables: bidx[b] = #{sorted sizes >= b 2^bshift}
-  const int32_t *divs;      // per mirrored instance: divisors of c (ascending), their lattice bins, prime count, (prime, exponent) pairs
+  const int32_t *divs;      // per mirrored instance: divisors of c (ascending), their lattice bins, prime count, (prime, exponent) pairs, prime-power count, test constants
   int32_t *dcnt;            // per divisor d: #{small sizes divisible by d}, then the same for big sizes
   long long *nodes;         // node-state arena of served requests (InstPlan::state_off)
-  int32_t *vcnt;            // value tables (large == 2): counts per size, then #{w >= v} within the chunk; zero between launches
-  long long *vsum;          //   sum{w >= v} within the chunk
-  long long *vtot;          //   per chunk: (count, sum) totals, then (count, sum) of the chunks above it
+  int32_t *vraw;            // value tables (large == 2): count per size value; zero between launches
+  int32_t *vcnt;            //   #{w >= v} within the chunk of kVtChunk values (written whole by each launch)
+  long long *vsum;          //   sum{w >= v} within the chunk (likewise)
+  long long *vtot;          //   per chunk: (count, sum) totals, then (count, sum) of the chunks above it; zero between launches
   int32_t *vlat;            //   divisor-lattice bins of the mirrored VB2; zero between launches
-  int32_t *vflag;           //   per listed instance: an input outside [0, c] was seen; zero between launches
+  int32_t *vflag;           //   per listed instance: [an input outside [0, c] was seen, largest size]; zero between launches
   const int32_t *vlist;     //   the instances prepared this way
   int64_t nvt;
   bp_bounds *out;           // [count] results

@@ -466,22 +466,19 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
       // of bp_divide.h per prime, family 3); superset sums along each prime's
       // axis then turn the bins into the count of multiples of every divisor.
       // wcnt[0..1] hold the small and the big class; the sort's key buffer is
-      // free here and holds the test constants of p_j^e, e = 1..a_j.
+      // free here and holds the test constants of p_j^e, e = 1..a_j (laid
+      // out by the host after the (p_j, a_j) pairs).
       const int nd = p.ndiv;  // = number of lattice bins
       const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
       const BP_GLOBAL int32_t *dbin = dv + nd;
       const int np = dv[2 * nd];
       const BP_GLOBAL int32_t *pa = dv + 2 * nd + 1;  // (p_j, a_j) pairs
       uint64_t *pmul = reinterpret_cast<uint64_t *>(keys);
-      if (tid == 0) {
-        int o = 0;
-        for (int j = 0; j < np; ++j) {
-          uint32_t q = 1;
-          for (int e = 1; e <= pa[2 * j + 1]; ++e) {
-            q *= (uint32_t)pa[2 * j];  // p_j^e divides c < 2^31
-            pmul[o++] = divides_const(q);
-          }
-        }
+      {
+        const int npp = pa[2 * np];
+        const BP_GLOBAL int32_t *m = pa + 2 * np + 1;
+        for (int k = tid; k < npp; k += NT)
+          pmul[k] = (uint64_t)(uint32_t)m[2 * k] | ((uint64_t)(uint32_t)m[2 * k + 1] << 32);
       }
       for (int k = tid; k < 256; k += NT) {
         sm.wcnt[0][k] = 0;
@@ -578,20 +575,101 @@ __device__ void clear_sweep_state(const LaunchDesc &d) {
   if (blockIdx.x == 0 && threadIdx.x < kQueues) d.counter[threadIdx.x * kQueueStride] = 0ull;
 }
 
-// Every reduced size of the value-table instances adds 1 to its value's
-// count: a grid-stride loop of the small-instance prep kernel, which runs
-// first in every launch (the counts are zero then).  A size or residual
-// outside [0, c] sets the instance's flag.
-__device__ void vt_hist(const LaunchDesc &d) {
+// ---------------------------------------------------------------------------
+// Value-table prep of large instances (InstPlan::large == 2), over the whole
+// GPU instead of one block, in two steps:
+//   vt_hist    (in the small-instance prep kernel, which runs first) every
+//              reduced size adds 1 to the raw count of its value; per block
+//              in LDS, then one atomic per touched entry: each chunk's
+//              (count, sum) totals, and for a mirrored VB2 each size's
+//              divisor-lattice bin; the largest size and the input flag;
+//   k_vt_emit  the chunks' offsets (suffix sums of the totals, in LDS), then
+//              per chunk the suffix sums of the counts and of count x value
+//              within the chunk (the tables the lookup tiles read), and every
+//              value v present fills its run of sorted positions
+//              [#{w > v}, #{w >= v}) with v, av and the prefix sums; the
+//              class bounds, the threshold table and the instance state are
+//              written by the threads holding their values, the multiple
+//              counts of the mirrored VB2 from the lattice bins.
+// The raw counts, chunk totals, lattice bins and per-instance flag and
+// maximum are zero at the start of a launch: the allocation clears them and
+// k_finalize clears what a launch used.  The chunk-local tables are written
+// whole by every launch.
+
+// LDS of vt_hist, over the prep kernel's own (used before its instance loop).
+struct VtHistSmem {
+  unsigned long long csum[kVtMaxChunks];
+  unsigned long long pmul[32];
+  uint32_t ccnt[kVtMaxChunks];
+  uint32_t lat[2][kMaxDivs];
+  int32_t pa[64];
+  int32_t np;
+  int32_t maxw;
+  int32_t bad;
+};
+static_assert(sizeof(VtHistSmem) <= sizeof(PrepSmem<kSmallThreads, kSmallCap>), "vt_hist fits the prep LDS");
+
+// The divisor-lattice bin of a size w: its class (0 small, 0 < 2w < c; 1
+// big, c/2 < w < c; -1 neither) and sum_j e_j stride_j, e_j the exponent of
+// the j-th prime of c in gcd(w, c).
+__device__ __forceinline__ int vt_lattice_bin(uint32_t uw, uint32_t uC, const VtHistSmem &sm, int *bin) {
+  const int cls = (2ull * uw > uC && uw < uC) ? 1 : ((uw > 0 && 2ull * uw < uC) ? 0 : -1);
+  if (cls < 0) return cls;
+  int b = 0, stride = 1, o = 0;
+  for (int j = 0; j < sm.np; ++j) {
+    const int aj = sm.pa[2 * j + 1];
+    int e = 0;
+    while (e < aj && divides_u32(uw, sm.pmul[o + e])) ++e;
+    b += e * stride;
+    stride *= aj + 1;
+    o += aj;
+  }
+  *bin = b;
+  return cls;
+}
+
+__device__ void vt_hist(const LaunchDesc &d, VtHistSmem &sm) {
   const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
   for (int64_t jj = 0; jj < d.nvt; ++jj) {
     const int64_t inst = d.vlist[jj];
     const BP_CONST InstPlan &p = as_const(d.plan)[inst];
     const int32_t C = p.C;
     const int64_t tot = p.n_in + (p.form == kFormResidual ? p.m_res : 0);
-    int32_t *cnt = d.vcnt + p.vt_off;
+    const int64_t first = blockIdx.x * (int64_t)blockDim.x;
+    if (first >= tot) continue;  // no items in this block (block-uniform)
+    const int64_t nch = ((int64_t)C + 2 + kVtChunk - 1) >> kVtChunkLog;
+    const int nd = p.ndiv;
+    __syncthreads();  // the previous instance's LDS has been flushed
+    for (int64_t c = threadIdx.x; c < nch; c += blockDim.x) {
+      sm.ccnt[c] = 0u;
+      sm.csum[c] = 0ull;
+    }
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+      sm.lat[0][k] = 0u;
+      sm.lat[1][k] = 0u;
+    }
+    if (threadIdx.x == 0) {
+      sm.maxw = 0;
+      sm.bad = 0;
+    }
+    if (nd > 0) {
+      // the primes of c with their exponents, then the test constants of each
+      // prime power p_j^e, e = 1..a_j (laid out by the host)
+      const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off) + 2 * nd;
+      const int np = dv[0];
+      const int npp = dv[1 + 2 * np];
+      if ((int)threadIdx.x < 2 * np) sm.pa[threadIdx.x] = dv[1 + threadIdx.x];
+      if ((int)threadIdx.x < npp) {
+        const BP_GLOBAL int32_t *m = dv + 2 + 2 * np + 2 * threadIdx.x;
+        sm.pmul[threadIdx.x] = (unsigned long long)(uint32_t)m[0] | ((unsigned long long)(uint32_t)m[1] << 32);
+      }
+      if (threadIdx.x == 0) sm.np = np;
+    }
+    __syncthreads();
+    int32_t *raw = d.vraw + p.vt_off;
     bool bad = false;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += gsz) {
+    int32_t mx = 0;
+    for (int64_t i = first + threadIdx.x; i < tot; i += gsz) {
       int32_t w;
       if (i < p.n_in) {
         w = d.in[p.in_off + i];
@@ -608,10 +686,38 @@ __device__ void vt_hist(const LaunchDesc &d) {
         if (res == C) continue;  // an empty bin adds no virtual item (Fig. 3)
         w = C - res;
       }
-      atomicAdd(&cnt[w], 1);
+      atomicAdd(&raw[w], 1);
+      const int c = w >> kVtChunkLog;
+      atomicAdd(&sm.ccnt[c], 1u);
+      atomicAdd(&sm.csum[c], (unsigned long long)w);
+      mx = max(mx, w);
+      if (nd > 0) {
+        int bin;
+        const int cls = vt_lattice_bin((uint32_t)w, (uint32_t)C, sm, &bin);
+        if (cls >= 0) atomicAdd(&sm.lat[cls][bin], 1u);
+      }
     }
-    if (bad) atomicOr(&d.vflag[jj], 1);
+    const uint64_t wmx = wave_max_u64((uint64_t)(uint32_t)mx);
+    if ((threadIdx.x & 63) == 0) atomicMax(&sm.maxw, (int32_t)wmx);
+    if (bad) atomicOr(&sm.bad, 1);
+    __syncthreads();
+    unsigned long long *ctot = (unsigned long long *)(d.vtot + p.vtt_off);
+    for (int64_t c = threadIdx.x; c < nch; c += blockDim.x) {
+      const uint32_t n = sm.ccnt[c];
+      if (!n) continue;
+      atomicAdd(&ctot[2 * c], (unsigned long long)n);
+      atomicAdd(&ctot[2 * c + 1], sm.csum[c]);
+    }
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+      if (sm.lat[0][k]) atomicAdd(&d.vlat[p.vl_off + k], (int32_t)sm.lat[0][k]);
+      if (sm.lat[1][k]) atomicAdd(&d.vlat[p.vl_off + nd + k], (int32_t)sm.lat[1][k]);
+    }
+    if (threadIdx.x == 0) {
+      if (sm.bad) atomicOr(&d.vflag[2 * jj], 1);
+      if (sm.maxw > 0) atomicMax(&d.vflag[2 * jj + 1], sm.maxw);
+    }
   }
+  if (d.nvt > 0) __syncthreads();  // before the instance loop reuses the LDS
 }
 
 template <int NT, int CAP, int LARGE>
@@ -621,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
   const LaunchDesc d = *as_const(dp);
   if (!LARGE) {
     clear_sweep_state(d);
-    vt_hist(d);
+    vt_hist(d, *reinterpret_cast<VtHistSmem *>(smem_raw));
   }
   for (int64_t inst = blockIdx.x; inst < d.count; inst += gridDim.x) {
     if (as_const(d.plan)[inst].large != LARGE) continue;
@@ -631,24 +737,6 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
     __syncthreads();
   }
 }
-
-// ---------------------------------------------------------------------------
-// Value-table prep of large instances (InstPlan::large == 2), over the whole
-// GPU instead of one block:
-//   vt_hist    every reduced size adds 1 to the count of its value (in the
-//              small-instance prep kernel, which runs first);
-//   k_vt_scan  per chunk of kVtChunk values, suffix sums of the counts and
-//              of count x value within the chunk, and the chunk totals; for
-//              a mirrored VB2, each value present adds its count to its
-//              divisor-lattice bin (per block in LDS, then one atomic per bin);
-//   k_vt_emit  the chunks' offsets (suffix sums of the totals, in LDS), then
-//              per chunk every value v present fills its run of sorted
-//              positions [#{w > v}, #{w >= v}) with v, av and the prefix
-//              sums; the threshold table, the multiple counts of the mirrored
-//              VB2 and the instance state are read off the same tables.
-// The counts, lattice bins and input flags are zero at the start of a
-// launch: the allocation clears them, and k_finalize clears what a launch
-// used.
 
 // Block-wide inclusive scan of two 64-bit sums (kVtThreads threads); also
 // returns the block totals.  Uses red[2][kVtThreads / 64].
@@ -675,134 +763,33 @@ __device__ __forceinline__ void vt_block_scan(uint64_t a, uint64_t b, uint64_t (
   *tb = xb;
 }
 
-__global__ __launch_bounds__(kVtThreads) void k_vt_scan(const LaunchDesc *__restrict__ dp) {
-  __shared__ uint64_t red[2][kVtThreads / 64];
-  __shared__ uint64_t pmul[32];
-  __shared__ int32_t pa_s[64];
-  __shared__ int32_t np_s;
-  __shared__ uint32_t lat[2][kMaxDivs];
-  constexpr int PER = kVtChunk / kVtThreads;
-  const LaunchDesc d = *as_const(dp);
-  for (int64_t jj = 0; jj < d.nvt; ++jj) {
-    const BP_CONST InstPlan &p = as_const(d.plan)[d.vlist[jj]];
-    const int64_t C = p.C;
-    const uint32_t uC = (uint32_t)C;
-    const int64_t nv = C + 2;
-    const int64_t nch = (nv + kVtChunk - 1) / kVtChunk;
-    int32_t *cnt = d.vcnt + p.vt_off;
-    long long *sum = d.vsum + p.vt_off;
-    const int nd = p.ndiv;
-    if ((int64_t)blockIdx.x >= nch) continue;  // (block-uniform)
-    __syncthreads();
-    if (nd > 0) {
-      for (int k = threadIdx.x; k < nd; k += blockDim.x) {
-        lat[0][k] = 0u;
-        lat[1][k] = 0u;
-      }
-      if (threadIdx.x == 0) {
-        // the test constants of p_j^e, e = 1..a_j (c < 2^31: at most 30 prime powers, 9 primes)
-        const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
-        const int np = dv[2 * nd];
-        const BP_GLOBAL int32_t *pa = dv + 2 * nd + 1;
-        int o = 0;
-        for (int j = 0; j < np; ++j) {
-          pa_s[2 * j] = pa[2 * j];
-          pa_s[2 * j + 1] = pa[2 * j + 1];
-          uint32_t q = 1;
-          for (int e = 1; e <= pa[2 * j + 1]; ++e) {
-            q *= (uint32_t)pa[2 * j];
-            pmul[o++] = divides_const(q);
-          }
-        }
-        np_s = np;
-      }
-      __syncthreads();
-    }
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-      const int64_t v0 = c * kVtChunk + (int64_t)threadIdx.x * PER;
-      uint32_t cn[PER];
-      uint64_t mc = 0, ms = 0;
-#pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int64_t v = v0 + k;
-        cn[k] = v < nv ? (uint32_t)cnt[v] : 0u;
-        mc += cn[k];
-        ms += (uint64_t)cn[k] * (uint64_t)v;
-      }
-      if (nd > 0) {
-        // the divisor-lattice bin of each value present: big (c/2 < w < c)
-        // or small (0 < 2w < c) class
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-          const uint32_t uw = (uint32_t)(v0 + k);
-          if (!cn[k]) continue;
-          const int cls = (2ull * uw > uC && uw < uC) ? 1 : ((uw > 0 && 2ull * uw < uC) ? 0 : -1);
-          if (cls < 0) continue;
-          int bin = 0, stride = 1, o = 0;
-          for (int j = 0; j < np_s; ++j) {
-            const int aj = pa_s[2 * j + 1];
-            int e = 0;
-            while (e < aj && divides_u32(uw, pmul[o + e])) ++e;
-            bin += e * stride;
-            stride *= aj + 1;
-            o += aj;
-          }
-          atomicAdd(&lat[cls][bin], cn[k]);
-        }
-      }
-      uint64_t ic, is, tc, ts;
-      vt_block_scan(mc, ms, red, &ic, &is, &tc, &ts);
-      // suffix within the chunk: everything held by the threads after this
-      // one, then this thread's values downwards
-      uint64_t rc = tc - ic, rs = ts - is;
-#pragma unroll
-      for (int k = PER - 1; k >= 0; --k) {
-        const int64_t v = v0 + k;
-        rc += cn[k];
-        rs += (uint64_t)cn[k] * (uint64_t)v;
-        if (v < nv) {
-          cnt[v] = (int32_t)rc;
-          sum[v] = (long long)rs;
-        }
-      }
-      if (threadIdx.x == 0) {
-        d.vtot[p.vtt_off + 2 * c] = (long long)tc;
-        d.vtot[p.vtt_off + 2 * c + 1] = (long long)ts;
-      }
-    }
-    if (nd > 0) {
-      __syncthreads();
-      for (int k = threadIdx.x; k < nd; k += blockDim.x) {
-        if (lat[0][k]) atomicAdd(&d.vlat[p.vl_off + k], (int32_t)lat[0][k]);
-        if (lat[1][k]) atomicAdd(&d.vlat[p.vl_off + nd + k], (int32_t)lat[1][k]);
-      }
-    }
-  }
-}
-
 __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__restrict__ dp) {
   __shared__ long long offc[kVtMaxChunks + 1], offs[kVtMaxChunks + 1];
   __shared__ uint64_t red[2][kVtThreads / 64];
   __shared__ uint32_t lat[2][kMaxDivs];
   // runs longer than kVtShortRun, filled by the whole block: (value, first
-  // position, length), at most one per value of the chunk
+  // position, length, sum of the sizes above), at most one per value of the
+  // chunk
   constexpr int kVtShortRun = 16;
   constexpr int PER = kVtChunk / kVtThreads;
   __shared__ int32_t lrun_v[kVtChunk], lrun_s[kVtChunk], lrun_n[kVtChunk];
+  __shared__ long long lrun_a[kVtChunk];
   __shared__ int32_t nlong;
   const LaunchDesc d = *as_const(dp);
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
   for (int64_t jj = 0; jj < d.nvt; ++jj) {
     const int64_t inst = d.vlist[jj];
     const BP_CONST InstPlan &p = as_const(d.plan)[inst];
     const int64_t C = p.C;
     const int64_t nv = C + 2;
     const int64_t nch = (nv + kVtChunk - 1) / kVtChunk;
-    const int32_t *cnt = d.vcnt + p.vt_off;
-    const long long *sum = d.vsum + p.vt_off;
+    const int32_t *raw = d.vraw + p.vt_off;
+    int32_t *cnt = d.vcnt + p.vt_off;
+    long long *sum = d.vsum + p.vt_off;
     const long long *tot = d.vtot + p.vtt_off;
+    const bool ok = d.vflag[2 * jj] == 0;
     // offsets of the chunks: the totals of the chunks above each, a block scan
     // of up to E totals per thread
+    uint64_t all_c, all_s;
     {
       const int E = (int)((nch + kVtThreads - 1) / kVtThreads);
       const int64_t c0 = (int64_t)threadIdx.x * E;
@@ -812,9 +799,9 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
           mc += (uint64_t)tot[2 * (c0 + k)];
           ms += (uint64_t)tot[2 * (c0 + k) + 1];
         }
-      uint64_t ic, is, tc, ts;
-      vt_block_scan(mc, ms, red, &ic, &is, &tc, &ts);
-      uint64_t rc = tc - ic, rs = ts - is;
+      uint64_t ic, is;
+      vt_block_scan(mc, ms, red, &ic, &is, &all_c, &all_s);
+      uint64_t rc = all_c - ic, rs = all_s - is;
       for (int k = E - 1; k >= 0; --k) {
         const int64_t c = c0 + k;
         if (c < nch) {
@@ -829,60 +816,94 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
           rs += (uint64_t)tot[2 * c + 1];
         }
       }
-      __syncthreads();
     }
-    auto cnt_ge = [&](int64_t v) -> int64_t { return (int64_t)cnt[v] + offc[v / kVtChunk]; };  // v in [0, c + 1]
-    auto sum_ge = [&](int64_t v) -> int64_t { return (int64_t)sum[v] + offs[v / kVtChunk]; };
-    const bool ok = d.vflag[jj] == 0;
-    if (ok) {
-      int32_t *sorted = d.sorted + p.ws_off;
-      uint32_t *av = d.av + p.ws_off;
-      int64_t *pre = d.pre + p.pre_off;
-      // position i of value v's run: the size, av and the prefix sum through i
-      auto put = [&](int64_t v, int64_t i, int64_t above, int64_t sum_above) {
-        sorted[i] = (int32_t)v;
-        av[i] = (2 * v > C) ? (uint32_t)(C - v) : (uint32_t)v;
-        pre[i + 1] = sum_above + (i + 1 - above) * v;
-      };
-      if (blockIdx.x == 0 && threadIdx.x == 0) pre[0] = 0;
-      for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        if (threadIdx.x == 0) nlong = 0;
-        __syncthreads();
-        const int64_t v0 = c * kVtChunk + (int64_t)threadIdx.x * PER;
+    InstState *st = &d.state[inst];
+    int32_t *sorted = d.sorted + p.ws_off;
+    uint32_t *av = d.av + p.ws_off;
+    int64_t *pre = d.pre + p.pre_off;
+    const bool seg = (p.flags & kPlanSegments) != 0;
+    const int64_t bmask = ((int64_t)1 << p.bshift) - 1;
+    // position i of value v's run: the size, av and the prefix sum through i
+    auto put = [&](int64_t v, int64_t i, int64_t above, int64_t sum_above) {
+      sorted[i] = (int32_t)v;
+      av[i] = (2 * v > C) ? (uint32_t)(C - v) : (uint32_t)v;
+      pre[i + 1] = sum_above + (i + 1 - above) * v;
+    };
+    if (ok && blockIdx.x == 0 && threadIdx.x == 0) pre[0] = 0;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+      if (threadIdx.x == 0) nlong = 0;
+      const int64_t v0 = c * kVtChunk + (int64_t)threadIdx.x * PER;
+      uint32_t cn[PER];
+      uint64_t mc = 0, ms = 0;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int64_t v = v0 + k;
+        cn[k] = v < nv ? (uint32_t)raw[v] : 0u;
+        mc += cn[k];
+        ms += (uint64_t)cn[k] * (uint64_t)v;
+      }
+      uint64_t ic, is, tc, ts;
+      vt_block_scan(mc, ms, red, &ic, &is, &tc, &ts);  // (its barriers also order the nlong reset)
+      // #{w >= v} and sum{w >= v} within the chunk: everything held by the
+      // threads after this one, then this thread's values downwards
+      uint64_t rc = tc - ic, rs = ts - is;
+      long long ge[PER], sge[PER];
+#pragma unroll
+      for (int k = PER - 1; k >= 0; --k) {
+        const int64_t v = v0 + k;
+        rc += cn[k];
+        rs += (uint64_t)cn[k] * (uint64_t)v;
+        ge[k] = (long long)rc;
+        sge[k] = (long long)rs;
+        if (v < nv) {
+          cnt[v] = (int32_t)rc;
+          sum[v] = (long long)rs;
+        }
+      }
+      if (ok) {
+        const long long oc = offc[c], os = offs[c];
+#pragma unroll
         for (int k = 0; k < PER; ++k) {
           const int64_t v = v0 + k;
-          if (v > C) break;
-          const int64_t ge = cnt_ge(v), gt = cnt_ge(v + 1), n = ge - gt;
-          if (n <= 0) continue;
-          const int64_t sgt = sum_ge(v + 1);
-          if (gt == 0) d.state[inst].maxw = (int32_t)v;  // the run at position 0: the largest size
+          if (v >= nv) break;
+          const int64_t n = cn[k], cge = ge[k] + oc, sgev = sge[k] + os;
+          // the class bounds and sums of the state, by the thread holding the value
+          if (v == C) st->nf = (int32_t)cge;
+          if (v == C / 2 + 1) {
+            st->nb = (int32_t)cge;
+            st->sumBig = sgev - C * (int64_t)raw[C];  // sizes c/2 < w < c
+          }
+          if (v == (C + 1) / 2) st->nm = (int32_t)cge;
+          if (v == 1) {
+            st->nz = (int32_t)cge;
+            st->sumNZ = sgev - C * (int64_t)raw[C];  // sizes 0 < w < c
+          }
+          if (seg && (v & bmask) == 0) d.bidx[p.bidx_off + (v >> p.bshift)] = (int32_t)cge;
+          if (n == 0) continue;
+          const int64_t gt = cge - n, sgt = sgev - n * v;
           if (n <= kVtShortRun) {
-            for (int64_t i = gt; i < ge; ++i) put(v, i, gt, sgt);
+            for (int64_t i = gt; i < cge; ++i) put(v, i, gt, sgt);
           } else {
             const int slot = atomicAdd(&nlong, 1);
             lrun_v[slot] = (int32_t)v;
             lrun_s[slot] = (int32_t)gt;
             lrun_n[slot] = (int32_t)n;
+            lrun_a[slot] = sgt;
           }
         }
-        __syncthreads();
+      }
+      __syncthreads();
+      if (ok) {
         for (int q = 0; q < nlong; ++q) {
-          const int64_t v = lrun_v[q], gt = lrun_s[q];
-          const int64_t sgt = sum_ge(v + 1);
+          const int64_t v = lrun_v[q], gt = lrun_s[q], sgt = lrun_a[q];
           for (int64_t i = gt + threadIdx.x; i < gt + lrun_n[q]; i += blockDim.x) put(v, i, gt, sgt);
         }
-        __syncthreads();
       }
-      if (p.flags & kPlanSegments) {
-        int32_t *bidx = d.bidx + p.bidx_off;
-        for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < p.nbk; b += gsz) {
-          const int64_t v = b << p.bshift;
-          bidx[b] = v <= C + 1 ? (int32_t)cnt_ge(v) : 0;
-        }
-      }
+      __syncthreads();
     }
     if (blockIdx.x != jj % gridDim.x) continue;
-    // one block per instance: the multiple counts of the mirrored VB2 and the state
+    // one block per instance: the multiple counts of the mirrored VB2, the
+    // threshold-table entries past c + 1, and the rest of the state
     const int nd = p.ndiv;
     if (nd > 0 && ok) {
       const BP_GLOBAL int32_t *dv = as_global(d.divs + p.div_off);
@@ -916,20 +937,16 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
         dc[nd + k] = (int32_t)lat[1][bk];
       }
     }
+    if (seg && ok)
+      for (int64_t b = ((C + 1) >> p.bshift) + 1 + threadIdx.x; b < p.nbk; b += blockDim.x)
+        d.bidx[p.bidx_off + b] = 0;
     if (threadIdx.x == 0) {
-      InstState *st = &d.state[inst];
-      const int64_t r = cnt_ge(0);
+      const int64_t r = (int64_t)all_c;
       if (ok) {
         st->status = BP_OK;
         st->r = (int32_t)r;
-        st->nf = (int32_t)cnt_ge(C);
-        st->nb = (int32_t)cnt_ge(C / 2 + 1);
-        st->nm = (int32_t)cnt_ge((C + 1) / 2);
-        st->nz = (int32_t)cnt_ge(1);
-        if (r == 0) st->maxw = 0;  // else written with the run at position 0, by whichever block holds it
-        st->sumW = sum_ge(0);
-        st->sumBig = sum_ge(C / 2 + 1) - sum_ge(C);
-        st->sumNZ = sum_ge(1) - sum_ge(C);
+        st->maxw = d.vflag[2 * jj + 1];
+        st->sumW = (int64_t)all_s;
       } else {
         st->status = BP_ERR_RANGE;
         st->r = 0;
@@ -939,21 +956,14 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
       }
       for (int b = 0; b < kNB; ++b) st->hiEff[b] = p.hi[b];
       if ((p.flags & kPlanClampVB2) && ok && r > 0) {
-        // the VB2 cut needs the largest size here: the largest v with #{w >= v} > 0
-        int64_t lo = 0, hi = C;
-        while (lo < hi) {
-          const int64_t mid = (lo + hi + 1) >> 1;
-          if (cnt_ge(mid) > 0) lo = mid;
-          else hi = mid - 1;
-        }
-        const int64_t denom = r * lo;
+        const int64_t denom = r * (int64_t)st->maxw;
         const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)p.C;
         if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
       }
       for (int b = 0; b < kNB; ++b) d.keys[inst * kNB + b] = 0ull;
       st->evals_skipped = 0ull;
       int refuted = 0;
-      if ((p.flags & kPlanEarlyExit) && ok && r > 0) refuted = (st->sumW + p.C - 1) / p.C > p.k;
+      if ((p.flags & kPlanEarlyExit) && ok && r > 0) refuted = ((int64_t)all_s + p.C - 1) / p.C > p.k;
       d.refuted[inst] = refuted;
     }
     __syncthreads();
@@ -2208,13 +2218,17 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchDesc *__restrict__
     o.verdict = lb <= p.k ? 1 : 0;
     d.out[inst] = o;
   }
-  // the value tables' counts and lattice bins back to zero for the next launch
+  // the value tables' raw counts, chunk totals and offsets, lattice bins,
+  // flag and maximum back to zero for the next launch
   const int64_t gsz = (int64_t)gridDim.x * blockDim.x, gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t jj = 0; jj < d.nvt; ++jj) {
     const BP_CONST InstPlan &p = as_const(d.plan)[d.vlist[jj]];
-    for (int64_t v = gt; v < (int64_t)p.C + 2; v += gsz) d.vcnt[p.vt_off + v] = 0;
+    const int64_t nv = (int64_t)p.C + 2, nch = (nv + kVtChunk - 1) / kVtChunk;
+    for (int64_t v = gt; v < nv; v += gsz) d.vraw[p.vt_off + v] = 0;
+    // (the chunk offsets too: another launch may place its totals there)
+    for (int64_t k = gt; k < 4 * nch; k += gsz) d.vtot[p.vtt_off + k] = 0;
     for (int64_t k = gt; k < 2 * (int64_t)p.ndiv; k += gsz) d.vlat[p.vl_off + k] = 0;
-    if (gt == 0) d.vflag[jj] = 0;
+    if (gt < 2) d.vflag[2 * jj + gt] = 0;
   }
 }
 
@@ -2800,7 +2814,6 @@ static hipError_t launch_prep(const LaunchDesc *d_desc, int grid_prep_small, int
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (grid_vt > 0) {
-    hipLaunchKernelGGL(k_vt_scan, dim3(grid_vt), dim3(kVtThreads), 0, s, d_desc);
     hipLaunchKernelGGL(k_vt_emit, dim3(grid_vt), dim3(kVtThreads), 0, s, d_desc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

@@ -147,7 +147,7 @@ int64_t param_count(int32_t C) {
 size_t full_bytes(int64_t n, int64_t m, int32_t C) {
   const int64_t r = n + m;
   const bool vt = r > kSmallCap && C <= kVtMaxC && (int64_t)C <= kVtRatio * r;
-  const int64_t tables = vt ? 12 * ((int64_t)C + 2) + 32 * (((int64_t)C + 2 + kVtChunk - 1) / kVtChunk) + 4 : 0;
+  const int64_t tables = vt ? 16 * ((int64_t)C + 2) + 32 * (((int64_t)C + 2 + kVtChunk - 1) / kVtChunk) + 8 : 0;
   return (size_t)(4 * (n + m) + 16 * r + 8 * (r + 1) + 8 * param_count(C) + tables) + sizeof(InstPlan) +
          sizeof(InstState) + kNB * 8 + sizeof(bp_bounds) + 8 * sizeof(Entry) + 256;
 }

@@ -155,6 +155,29 @@ def test_value_table_prep_matches_block_prep_and_oracle(ctx, ctx_block):
     same(ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT), want, "after the range errors")
 
 
+def test_value_table_launch_sequences(ctx):
+    # value-table launches of different capacities and instance orders on one
+    # context, so that each launch finds its tables where earlier launches of
+    # other layouts left theirs (they must be back at zero in between)
+    g = np.random.default_rng(33)
+    insts = []
+    for C, n in ((60000, 9000), (20000, 9500), (45000, 8800)):
+        items = g.integers(0, C + 1, size=n).astype(np.int32)
+        insts.append((C, int(items.sum()) // C + 2, items))
+    want = [oracle_par.dense_record(C, k, items) for C, k, items in insts]
+    seq = [[0], [1], [0], [1, 0], [0, 1, 2], [2], [0], [2, 1], [1]]
+    for step, ids in enumerate(seq):
+        say("value-table sequence", step, ids)
+        if len(ids) == 1:
+            C, k, items = insts[ids[0]]
+            same(ctx.lower_bounds(C, k, items), want[ids[0]], ("sequence", step))
+        else:
+            out = ctx.lower_bounds_batch([insts[i][0] for i in ids], [insts[i][1] for i in ids],
+                                         [insts[i][2] for i in ids])
+            for j, i in enumerate(ids):
+                same(row_dict(out[j]), want[i], ("sequence batch", step, j))
+
+
 def test_small_checks_on_both_paths(ctx, ctx_pipe):
     # the one-launch path (instance in the kernel arguments) and the pipeline
     # on the same small checks: random instances with custom ranges and the
