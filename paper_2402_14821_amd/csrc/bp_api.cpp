@@ -354,10 +354,13 @@ static int pow2_at_least(int64_t x) {
 // sweep serves its task queues with any grid; a small launch so avoids
 // dispatching thousands of waves that would find no task.
 Ctx::LaunchShape Ctx::shape_of(int64_t count, int64_t ntasks) const {
-  bool with_large = false;
-  for (int64_t i = 0; i < count && !with_large; ++i) with_large = plan_vec[i].large == 1;
+  bool with_large = false, tiny = true;
+  for (int64_t i = 0; i < count; ++i) {
+    with_large |= plan_vec[i].large == 1;
+    tiny &= plan_vec[i].large != 0 || plan_vec[i].r_cap <= kTinyCap;
+  }
   LaunchShape sh;
-  sh.v = (with_large ? 1 : 0) | (nsplit > 0 ? 2 : 0);
+  sh.v = (with_large ? 1 : 0) | (nsplit > 0 ? 2 : 0) | (tiny ? 4 : 0);
   sh.lpl = tune.lanes_params;
   // (the small-instance prep kernel also counts the sizes of value-table instances)
   sh.prep_small = std::min(grid_prep_small, pow2_at_least(std::max<int64_t>(count, vt_list.empty() ? 1 : 64)));
@@ -393,9 +396,8 @@ bp_status Ctx::ensure_graph(const LaunchDesc *d_desc, const LaunchShape &sh, hip
     graph_used.erase(lru);
   }
   HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin,
-                                  (sh.v & 1) != 0,
-                                  (sh.v & 2) != 0, stream);
+  hipError_t le =
+      launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin, sh.v, stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(stream, &g);
   if (le != hipSuccess) {
@@ -869,21 +871,17 @@ bp_status Ctx::run(int64_t count, int64_t ntasks, const int32_t *host_in, int64_
   }
   const LaunchDesc *d_desc = (const LaunchDesc *)dv;
   const LaunchShape sh = shape_of(count, ntasks);
-  const bool with_large = (sh.v & 1) != 0, with_combine = (sh.v & 2) != 0;
   if (timing) {
     hipEvent_t *ev = nullptr;
     if ((st = timing_slot(&ev))) return st;
-    HIP_TRY(launch_pipeline_timed(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin,
-                                  with_large,
-                                  with_combine, s, ev));
+    HIP_TRY(launch_pipeline_timed(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin, sh.v,
+                                  s, ev));
   } else if (use_graph) {
     hipGraphExec_t ex = nullptr;
     if ((st = ensure_graph(d_desc, sh, &ex))) return st;
     HIP_TRY(hipGraphLaunch(ex, s));
   } else {
-    HIP_TRY(launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin,
-                            with_large,
-                            with_combine, s));
+    HIP_TRY(launch_pipeline(d_desc, sh.lpl, sh.prep_small, sh.prep_large, sh.vt, sh.sweep, sh.comb, sh.fin, sh.v, s));
   }
   HIP_TRY(hipEventRecord(last_run, s));
   any_run = true;
@@ -1425,8 +1423,8 @@ bp_status bp_feasible_dev_noalloc(int32_t C, int32_t m, const int32_t *d_residua
   t.p = planner.plan_vec[0];
   for (int64_t j = 0; j < planner.nentries; ++j) t.e[j] = planner.entry_vec[(size_t)j];
   const Ctx::LaunchShape sh = planner.shape_of(1, ntasks);
-  HIP_TRY(launch_noalloc(t, base, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, (sh.v & 1) != 0,
-                         (sh.v & 2) != 0, (hipStream_t)stream));
+  HIP_TRY(launch_noalloc(t, base, sh.lpl, sh.prep_small, sh.prep_large, sh.sweep, sh.comb, sh.fin, sh.v,
+                         (hipStream_t)stream));
   return BP_OK;
 }
 

@@ -20,19 +20,17 @@ void default_ranges(int32_t C, int64_t lo[kNB], int64_t hi[kNB]);
 // kernels (bp_kernels.hip)
 hipError_t set_kernel_attrs();
 hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_vt,
-                           int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
-                           hipStream_t s);
+                           int grid_sweep, int grid_comb, int grid_fin, int v, hipStream_t s);
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_vt, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
-                                 bool with_combine, hipStream_t s, hipEvent_t ev[4]);
+                                 int grid_vt, int grid_sweep, int grid_comb, int grid_fin, int v, hipStream_t s,
+                                 hipEvent_t ev[4]);
 hipError_t launch_node_delta(const NodeTask *tasks, int64_t ntasks, int64_t ntiles, const int32_t *delta,
                              long long *nodes, unsigned long long *keys, bp_bounds *out, int grid, hipStream_t s);
 hipError_t launch_small_check(const SmallArgs &a, bool one, int grid, void *buf, bp_bounds *out, uint32_t *seq_out,
                               uint32_t seq, hipStream_t s);
 hipError_t noalloc_scratch(int device, unsigned char **out);
 hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
-                          int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
-                          bool with_combine, hipStream_t s);
+                          int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, int v, hipStream_t s);
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,
                          int64_t n, unsigned long long *loads, int32_t *out, int64_t *out_r, int32_t *out_residual,
                          int32_t *bad, hipStream_t s);
@@ -86,7 +84,8 @@ struct Ctx {
   int64_t t_runs = 0, t_folded = 0;
   double t_sum[3] = {0, 0, 0};
   // Grids and kernels of one launch: variant bit 0 = large-instance prep
-  // block, bit 1 = combine; vt = grid of the value-table prep (0: none);
+  // block, bit 1 = combine, bit 2 = the short small-instance prep; vt = grid
+  // of the value-table prep (0: none);
   // each grid at most the machine-filling size of its kernel.
   struct LaunchShape {
     int v, lpl, prep_small, prep_large, vt, sweep, comb, fin;

@@ -35,6 +35,7 @@ constexpr int kSegQPerChunk = 8;  // q values per chunk of a split BJ1/CCM1 segm
 constexpr int64_t kSegWindowMinItems = 8192;
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
+constexpr int kTinyCap = 2048;          // the same block's short form, for launches whose small instances fit it
 constexpr int kLargeThreads = 1024;      // prep block for one large instance
 constexpr int kLargeCap = 16384;        // items per large-instance prep block (LDS resident)
 static_assert(kLargeCap <= BP_MAX_ITEMS, "the block prep's capacity is within the check's item limit");
@@ -46,7 +47,7 @@ static_assert(kLargeCap <= BP_MAX_ITEMS, "the block prep's capacity is within th
 // large and c is at most kVtRatio times its reduced count (the tables hold
 // c + 2 entries).
 constexpr int kVtChunk = 2048;           // values per block of the suffix scan (2^kVtChunkLog)
-constexpr int kVtThreads = 256;
+constexpr int kVtThreads = 512;
 constexpr int32_t kVtMaxC = 1 << 21;
 constexpr int64_t kVtRatio = 16;
 constexpr int kVtMaxChunks = (kVtMaxC + 2 + kVtChunk - 1) / kVtChunk;

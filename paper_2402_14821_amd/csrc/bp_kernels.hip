@@ -146,6 +146,7 @@ struct PrepSmem {
   uint32_t hist[256];
   uint32_t wcnt[NT / 64][256];  // per (wave, digit): counts, then offsets
   uint64_t wtot[NT / 64];
+  unsigned long long sums[3];  // sizes of all, of the big and of the non-zero non-full items
   int32_t flags[8];
 };
 
@@ -319,6 +320,18 @@ __device__ void block_prefix(PrepSmem<NT, CAP> &sm, const uint32_t *sizes, int n
   (void)NW;
 }
 
+// floor(UINT32_MAX / denom) for denom > 0 (the VB2 cut of Sec. 4), in
+// 32-bit arithmetic: 0 once denom exceeds UINT32_MAX.
+__device__ __forceinline__ int64_t vb2_cut_cap(int64_t denom) {
+  return denom > (int64_t)0xffffffffLL ? 0 : (int64_t)(0xffffffffu / (uint32_t)denom);
+}
+
+// L1 = ceil(sumW / c) > k for r items of sizes at most c, without a 64-bit
+// division: never when k >= r (then L1 <= r), else sumW > k c (k c < 2^52).
+__device__ __forceinline__ bool l1_exceeds(int64_t sumW, int64_t r, int64_t C, int64_t k) {
+  return k < r && sumW > k * C;
+}
+
 template <int NT, int CAP>
 __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CAP> &sm) {
   const BP_CONST InstPlan &p = as_const(d.plan)[inst];
@@ -328,6 +341,8 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
   const uint32_t uC = (uint32_t)C;
   int64_t r = 0;
   int32_t status = BP_OK;
+  int32_t maxw = 0;   // (thread 0)
+  int64_t sumW = 0;   // (thread 0)
   if (tid < 8) sm.flags[tid] = 0;
   __syncthreads();
   if (p.r_cap > CAP) {
@@ -425,26 +440,37 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
         bidx[b] = lo;
       }
     }
-    // class boundaries on the decreasing sizes
+    // class boundaries on the decreasing sizes, and the class sums
     if (tid < 8) sm.flags[tid] = 0;
+    if (tid < 3) sm.sums[tid] = 0ull;
     __syncthreads();
     uint32_t c_full = 0, c_big = 0, c_bm = 0, c_nz = 0;
+    uint64_t s_all = 0, s_big = 0, s_nz = 0;
     for (int i = tid; i < r; i += NT) {
       const uint32_t w = sz[i];
       c_full += w == uC;
       c_big += 2ull * w > uC;
       c_bm += 2ull * w >= uC;
       c_nz += w > 0;
+      s_all += w;
+      s_big += (2ull * w > uC && w < uC) ? w : 0u;
+      s_nz += (w > 0 && w < uC) ? w : 0u;
     }
     c_full = wave_incl_scan_u32(c_full);
     c_big = wave_incl_scan_u32(c_big);
     c_bm = wave_incl_scan_u32(c_bm);
     c_nz = wave_incl_scan_u32(c_nz);
+    s_all = wave_incl_scan_u64(s_all);
+    s_big = wave_incl_scan_u64(s_big);
+    s_nz = wave_incl_scan_u64(s_nz);
     if ((tid & 63) == 63) {
       atomicAdd(&sm.flags[1], (int)c_full);
       atomicAdd(&sm.flags[2], (int)c_big);
       atomicAdd(&sm.flags[3], (int)c_bm);
       atomicAdd(&sm.flags[4], (int)c_nz);
+      atomicAdd(&sm.sums[0], (unsigned long long)s_all);
+      atomicAdd(&sm.sums[1], (unsigned long long)s_big);
+      atomicAdd(&sm.sums[2], (unsigned long long)s_nz);
     }
     __syncthreads();
     const int nf = sm.flags[1], nb = sm.flags[2], nm = sm.flags[3], nz = sm.flags[4];
@@ -527,46 +553,40 @@ __device__ void prep_instance(const LaunchDesc &d, int64_t inst, PrepSmem<NT, CA
       __syncthreads();
     }
     if (tid == 0) {
+      maxw = r > 0 ? (int32_t)sz[0] : 0;
+      sumW = (int64_t)sm.sums[0];
       st->r = (int32_t)r;
       st->nf = nf;
       st->nb = nb;
       st->nm = nm;
       st->nz = nz;
-      st->maxw = r > 0 ? (int32_t)sz[0] : 0;
+      st->maxw = maxw;
+      st->sumW = sumW;
+      st->sumBig = (int64_t)sm.sums[1];
+      st->sumNZ = (int64_t)sm.sums[2];
     }
   }
-  __syncthreads();
+  // the rest of the state from what this block holds (no read-back of the
+  // global workspaces): status, effective ranges, cleared results
+  if (tid < kNB) d.keys[inst * kNB + tid] = 0ull;
   if (tid == 0) {
     st->status = status;
     if (status != BP_OK) {
+      r = 0;
       st->r = 0; st->nf = st->nb = st->nm = st->nz = 0; st->maxw = 0;
+      st->sumW = st->sumBig = st->sumNZ = 0;
     }
+    for (int b = 0; b < kNB; ++b) st->hiEff[b] = p.hi[b];
+    if ((p.flags & kPlanClampVB2) && status == BP_OK) {
+      const int64_t denom = r * (int64_t)maxw;
+      const int64_t cap = denom > 0 ? vb2_cut_cap(denom) : (int64_t)p.C;
+      if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
+    }
+    st->evals_skipped = 0ull;
+    int refuted = 0;
+    if ((p.flags & kPlanEarlyExit) && status == BP_OK && r > 0) refuted = l1_exceeds(sumW, r, p.C, p.k);
+    d.refuted[inst] = refuted;
   }
-}
-
-// Second half of prep (thread 0): sums, effective ranges, cleared results.
-__device__ void prep_finish(const LaunchDesc &d, int64_t inst) {
-  const BP_CONST InstPlan &p = as_const(d.plan)[inst];
-  InstState *st = &d.state[inst];
-  const int64_t *pre = d.pre + p.pre_off;
-  const int32_t r = st->r;
-  st->sumW = r > 0 ? pre[r] : 0;
-  st->sumBig = r > 0 ? pre[st->nb] - pre[st->nf] : 0;
-  st->sumNZ = r > 0 ? pre[st->nz] - pre[st->nf] : 0;
-  for (int b = 0; b < kNB; ++b) st->hiEff[b] = p.hi[b];
-  if ((p.flags & kPlanClampVB2) && st->status == BP_OK) {
-    const int64_t denom = (int64_t)r * (int64_t)st->maxw;
-    const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)p.C;
-    if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
-  }
-  for (int b = 0; b < kNB; ++b) d.keys[inst * kNB + b] = 0ull;
-  st->evals_skipped = 0ull;
-  int refuted = 0;
-  if ((p.flags & kPlanEarlyExit) && st->status == BP_OK && r > 0) {
-    const int64_t l1 = (st->sumW + p.C - 1) / p.C;
-    refuted = l1 > p.k;
-  }
-  d.refuted[inst] = refuted;
 }
 
 // Clears the task counters of the sweep that follows (run by the
@@ -607,7 +627,7 @@ struct VtHistSmem {
   int32_t maxw;
   int32_t bad;
 };
-static_assert(sizeof(VtHistSmem) <= sizeof(PrepSmem<kSmallThreads, kSmallCap>), "vt_hist fits the prep LDS");
+static_assert(sizeof(VtHistSmem) <= sizeof(PrepSmem<kSmallThreads, kTinyCap>), "vt_hist fits the prep LDS");
 
 // The divisor-lattice bin of a size w: its class (0 small, 0 < 2w < c; 1
 // big, c/2 < w < c; -1 neither) and sum_j e_j stride_j, e_j the exponent of
@@ -733,8 +753,6 @@ __global__ __launch_bounds__(NT) void k_prep(const LaunchDesc *__restrict__ dp) 
     if (as_const(d.plan)[inst].large != LARGE) continue;
     prep_instance<NT, CAP>(d, inst, sm);
     __syncthreads();
-    if (threadIdx.x == 0) prep_finish(d, inst);
-    __syncthreads();
   }
 }
 
@@ -774,6 +792,9 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
   constexpr int PER = kVtChunk / kVtThreads;
   __shared__ int32_t lrun_v[kVtChunk], lrun_s[kVtChunk], lrun_n[kVtChunk];
   __shared__ long long lrun_a[kVtChunk];
+  // the chunk's #{w >= v} and sum{w >= v} within the chunk, by value
+  __shared__ int32_t lge[kVtChunk + 1];
+  __shared__ long long lsge[kVtChunk];
   __shared__ int32_t nlong;
   const LaunchDesc d = *as_const(dp);
   for (int64_t jj = 0; jj < d.nvt; ++jj) {
@@ -787,6 +808,17 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
     long long *sum = d.vsum + p.vt_off;
     const long long *tot = d.vtot + p.vtt_off;
     const bool ok = d.vflag[2 * jj] == 0;
+    const int32_t maxw = d.vflag[2 * jj + 1];
+    const int64_t nfull = raw[C];  // items of size c
+    // this block's first chunk of raw counts, loaded with the totals (one
+    // memory round trip for both)
+    const int64_t v0_first = (int64_t)blockIdx.x * kVtChunk + (int64_t)threadIdx.x * PER;
+    uint32_t cn[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t v = v0_first + k;
+      cn[k] = ((int64_t)blockIdx.x < nch && v < nv) ? (uint32_t)raw[v] : 0u;
+    }
     // offsets of the chunks: the totals of the chunks above each, a block scan
     // of up to E totals per thread
     uint64_t all_c, all_s;
@@ -833,12 +865,11 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
       if (threadIdx.x == 0) nlong = 0;
       const int64_t v0 = c * kVtChunk + (int64_t)threadIdx.x * PER;
-      uint32_t cn[PER];
       uint64_t mc = 0, ms = 0;
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int64_t v = v0 + k;
-        cn[k] = v < nv ? (uint32_t)raw[v] : 0u;
+        if (c != (int64_t)blockIdx.x) cn[k] = v < nv ? (uint32_t)raw[v] : 0u;
         mc += cn[k];
         ms += (uint64_t)cn[k] * (uint64_t)v;
       }
@@ -847,36 +878,40 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
       // #{w >= v} and sum{w >= v} within the chunk: everything held by the
       // threads after this one, then this thread's values downwards
       uint64_t rc = tc - ic, rs = ts - is;
-      long long ge[PER], sge[PER];
 #pragma unroll
       for (int k = PER - 1; k >= 0; --k) {
         const int64_t v = v0 + k;
         rc += cn[k];
         rs += (uint64_t)cn[k] * (uint64_t)v;
-        ge[k] = (long long)rc;
-        sge[k] = (long long)rs;
+        lge[threadIdx.x * PER + k] = (int32_t)rc;
+        lsge[threadIdx.x * PER + k] = (long long)rs;
         if (v < nv) {
           cnt[v] = (int32_t)rc;
           sum[v] = (long long)rs;
         }
       }
+      if (threadIdx.x == 0) lge[kVtChunk] = 0;
+      __syncthreads();
       if (ok) {
         const long long oc = offc[c], os = offs[c];
-#pragma unroll
+        // (a rolled loop over this thread's values, read back from LDS: one
+        // copy of its body)
+#pragma unroll 1
         for (int k = 0; k < PER; ++k) {
           const int64_t v = v0 + k;
           if (v >= nv) break;
-          const int64_t n = cn[k], cge = ge[k] + oc, sgev = sge[k] + os;
+          const int li = threadIdx.x * PER + k;
+          const int64_t n = lge[li] - lge[li + 1], cge = lge[li] + oc, sgev = lsge[li] + os;
           // the class bounds and sums of the state, by the thread holding the value
           if (v == C) st->nf = (int32_t)cge;
           if (v == C / 2 + 1) {
             st->nb = (int32_t)cge;
-            st->sumBig = sgev - C * (int64_t)raw[C];  // sizes c/2 < w < c
+            st->sumBig = sgev - C * nfull;  // sizes c/2 < w < c
           }
           if (v == (C + 1) / 2) st->nm = (int32_t)cge;
           if (v == 1) {
             st->nz = (int32_t)cge;
-            st->sumNZ = sgev - C * (int64_t)raw[C];  // sizes 0 < w < c
+            st->sumNZ = sgev - C * nfull;  // sizes 0 < w < c
           }
           if (seg && (v & bmask) == 0) d.bidx[p.bidx_off + (v >> p.bshift)] = (int32_t)cge;
           if (n == 0) continue;
@@ -945,7 +980,7 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
       if (ok) {
         st->status = BP_OK;
         st->r = (int32_t)r;
-        st->maxw = d.vflag[2 * jj + 1];
+        st->maxw = maxw;
         st->sumW = (int64_t)all_s;
       } else {
         st->status = BP_ERR_RANGE;
@@ -957,13 +992,13 @@ __global__ __launch_bounds__(kVtThreads) void k_vt_emit(const LaunchDesc *__rest
       for (int b = 0; b < kNB; ++b) st->hiEff[b] = p.hi[b];
       if ((p.flags & kPlanClampVB2) && ok && r > 0) {
         const int64_t denom = r * (int64_t)st->maxw;
-        const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)p.C;
+        const int64_t cap = denom > 0 ? vb2_cut_cap(denom) : (int64_t)p.C;
         if (cap < st->hiEff[kVB2]) st->hiEff[kVB2] = cap;
       }
       for (int b = 0; b < kNB; ++b) d.keys[inst * kNB + b] = 0ull;
       st->evals_skipped = 0ull;
       int refuted = 0;
-      if ((p.flags & kPlanEarlyExit) && ok && r > 0) refuted = ((int64_t)all_s + p.C - 1) / p.C > p.k;
+      if ((p.flags & kPlanEarlyExit) && ok && r > 0) refuted = l1_exceeds((int64_t)all_s, r, p.C, p.k);
       d.refuted[inst] = refuted;
     }
     __syncthreads();
@@ -2554,7 +2589,7 @@ __global__ __launch_bounds__(NT) void k_small_check(SmallArgs a, unsigned long l
   for (int b = 0; b < kNB; ++b) hi[b] = a.hi[b];
   if (a.clamp) {
     const int64_t denom = (int64_t)r * maxw_s;
-    const int64_t cap = denom > 0 ? (int64_t)0xffffffffLL / denom : (int64_t)a.C;
+    const int64_t cap = denom > 0 ? vb2_cut_cap(denom) : (int64_t)a.C;
     if (cap < hi[kVB2]) hi[kVB2] = cap;
   }
   // this workgroup's (bound, parameter) pairs: a group of S consecutive
@@ -2774,11 +2809,15 @@ __global__ __launch_bounds__(1024) void k_reduce_one(int32_t C, int32_t m, const
 // Host-side launch helpers (C++ linkage inside the library).
 
 size_t prep_smem_small() { return sizeof(PrepSmem<kSmallThreads, kSmallCap>); }
+size_t prep_smem_tiny() { return sizeof(PrepSmem<kSmallThreads, kTinyCap>); }
 size_t prep_smem_large() { return sizeof(PrepSmem<kLargeThreads, kLargeCap>); }
 
 hipError_t set_kernel_attrs() {
   hipError_t e = hipFuncSetAttribute((const void *)k_prep<kSmallThreads, kSmallCap, 0>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)prep_smem_small());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_prep<kSmallThreads, kTinyCap, 0>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)prep_smem_tiny());
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)k_prep<kLargeThreads, kLargeCap, 1>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)prep_smem_large());
@@ -2802,13 +2841,20 @@ static hipError_t launch_combine(const LaunchDesc *d_desc, int lpl, int grid_com
   return hipGetLastError();
 }
 
+// The small-instance prep in its short form (kTinyCap items per block: a
+// quarter of the unrolled code) when every block-prepared instance is that
+// small (variant bit 4).
 static hipError_t launch_prep(const LaunchDesc *d_desc, int grid_prep_small, int grid_prep_large, int grid_vt,
-                              bool with_large, hipStream_t s) {
-  hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
-                     prep_smem_small(), s, d_desc);
+                              int v, hipStream_t s) {
+  if (v & 4)
+    hipLaunchKernelGGL((k_prep<kSmallThreads, kTinyCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
+                       prep_smem_tiny(), s, d_desc);
+  else
+    hipLaunchKernelGGL((k_prep<kSmallThreads, kSmallCap, 0>), dim3(grid_prep_small), dim3(kSmallThreads),
+                       prep_smem_small(), s, d_desc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (with_large) {
+  if (v & 1) {
     hipLaunchKernelGGL((k_prep<kLargeThreads, kLargeCap, 1>), dim3(grid_prep_large), dim3(kLargeThreads),
                        prep_smem_large(), s, d_desc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -2820,32 +2866,33 @@ static hipError_t launch_prep(const LaunchDesc *d_desc, int grid_prep_small, int
   return hipSuccess;
 }
 
-// The large-instance prep runs only when the launch holds a large instance
-// (the block form when with_large, the value-table kernels when grid_vt > 0)
-// and the combine only when it has split tiles (either would find no work);
-// the small-instance prep always runs, as it clears the sweep's task counters.
+// Variant bits v: 1 = the launch holds a large instance prepared by one
+// block, 2 = it has split tiles, 4 = its small instances fit the short prep.
+// The large-instance prep runs only with bit 1 (the block form) or grid_vt >
+// 0 (the value-table kernels), the combine only with bit 2 (either would find
+// no work); the small-instance prep always runs, as it clears the sweep's
+// task counters.
 hipError_t launch_pipeline(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large, int grid_vt,
-                           int grid_sweep, int grid_comb, int grid_fin, bool with_large, bool with_combine,
-                           hipStream_t s) {
-  hipError_t e = launch_prep(d_desc, grid_prep_small, grid_prep_large, grid_vt, with_large, s);
+                           int grid_sweep, int grid_comb, int grid_fin, int v, hipStream_t s) {
+  hipError_t e = launch_prep(d_desc, grid_prep_small, grid_prep_large, grid_vt, v, s);
   if (e != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
-  if (with_combine && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
+  if ((v & 2) && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   return hipGetLastError();
 }
 
 // The same launches with events around the stages (diagnostic timing).
 hipError_t launch_pipeline_timed(const LaunchDesc *d_desc, int lpl, int grid_prep_small, int grid_prep_large,
-                                 int grid_vt, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
-                                 bool with_combine, hipStream_t s, hipEvent_t ev[4]) {
+                                 int grid_vt, int grid_sweep, int grid_comb, int grid_fin, int v, hipStream_t s,
+                                 hipEvent_t ev[4]) {
   hipError_t e = hipEventRecord(ev[0], s);
   if (e != hipSuccess) return e;
-  if ((e = launch_prep(d_desc, grid_prep_small, grid_prep_large, grid_vt, with_large, s)) != hipSuccess) return e;
+  if ((e = launch_prep(d_desc, grid_prep_small, grid_prep_large, grid_vt, v, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if ((e = launch_sweep(d_desc, lpl, grid_sweep, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-  if (with_combine && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
+  if ((v & 2) && (e = launch_combine(d_desc, lpl, grid_comb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(grid_fin), dim3(256), 0, s, d_desc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipEventRecord(ev[3], s);
@@ -2887,13 +2934,12 @@ __global__ __launch_bounds__(64) void k_noalloc_tables(NoAllocTables t, NoAllocT
 // The tables' kernel, then the pipeline reading its descriptor from `base`
 // (the array's device address).
 hipError_t launch_noalloc(const NoAllocTables &t, unsigned char *base, int lpl, int grid_prep_small,
-                          int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, bool with_large,
-                          bool with_combine, hipStream_t s) {
+                          int grid_prep_large, int grid_sweep, int grid_comb, int grid_fin, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_noalloc_tables, dim3(1), dim3(64), 0, s, t, (NoAllocTables *)base);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_pipeline((const LaunchDesc *)base, lpl, grid_prep_small, grid_prep_large, 0, grid_sweep, grid_comb,
-                         grid_fin, with_large, with_combine, s);
+                         grid_fin, v, s);
 }
 
 hipError_t launch_reduce(int32_t C, int32_t m, const int32_t *residual, const int32_t *size, const int32_t *bin_of,

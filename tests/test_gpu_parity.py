@@ -491,7 +491,7 @@ def test_edge_cases(ctx):
     assert got["r"] == 0 and got["verdict"] == 1
 
 
-@pytest.mark.parametrize("r", [8191, 8192, 8193, 16384])
+@pytest.mark.parametrize("r", [2048, 2049, 8191, 8192, 8193, 16384])
 def test_block_capacity_boundaries(ctx, r):
     rng = np.random.default_rng(r)
     C = 600
