@@ -299,14 +299,17 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
     ops = sum(sweep_ops(bp, int(c), int(r)) for c, r in zip(Cs, out["r"]))
     fails = int((out["verdict"] == 0).sum())
     assert np.array_equal(out["verdict"] == 0, b.expect_fail), "batched verdicts differ from the construction"
-    # plain: one call per instance, each synchronous
+    # plain: one call per instance, each synchronous, with the default shape
+    # (the batch's tuned shape is chosen for a whole batch)
     n_plain = min(plain_max, len(b))
     per = np.zeros(n_plain)
+    ctx.set_tuning(*[default_tuning[k] for k in ("lanes_params", "waves_per_cu", "tasks_per_wave", "min_chunk")])
     for i in range(n_plain):
         C, k, it = b.instance(i)
         t0 = time.perf_counter()
         ctx.lower_bounds(C, k, it)
         per[i] = time.perf_counter() - t0
+    ctx.set_tuning(*[tuned[k] for k in ("lanes_params", "waves_per_cu", "tasks_per_wave", "min_chunk")])
     classes = {}
     for c in sorted(set(int(x) for x in Cs)):
         idx = np.flatnonzero(Cs[:n_plain] == c)
@@ -328,7 +331,7 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
     seg = None
     if segments:
         try:
-            seg = bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps)
+            seg = bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps, default_tuning)
         except bp.BpError as e:
             seg = {"error": str(e)}
 
@@ -345,7 +348,7 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
             "batched_s_default_shape": t_default}
 
 
-def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps):
+def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain, reps, default_tuning):
     """The uneven batch and its plain calls again with the segment sums (same records)."""
     import numpy as np
 
@@ -360,11 +363,14 @@ def bench_batched_segments(bp, b, ctx, Cs, ks, items_list, out, t_batch, n_plain
         ts.append(time.perf_counter() - t0)
     t_batch_seg = min(ts)
     per_s = np.zeros(n_plain)
+    tuned = ctx.get_tuning()
+    ctx.set_tuning(*[default_tuning[k] for k in ("lanes_params", "waves_per_cu", "tasks_per_wave", "min_chunk")])
     for i in range(n_plain):
         C, k, it = b.instance(i)
         t0 = time.perf_counter()
         ctx.lower_bounds(C, k, it, seg_sweeps[i])
         per_s[i] = time.perf_counter() - t0
+    ctx.set_tuning(*[tuned[k] for k in ("lanes_params", "waves_per_cu", "tasks_per_wave", "min_chunk")])
     plain = n_plain / per_s.sum()
     return {"batched_s": t_batch_seg, "batched_checks_per_s": len(b) / t_batch_seg, "plain_checks_per_s": plain,
             "batched_over_plain": (len(b) / t_batch_seg) / plain, "batched_speedup_vs_dense": t_batch / t_batch_seg,

@@ -583,7 +583,7 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
         }
         continue;
       }
-      if (q.segments && (b == kBJ1 || b == kCCM1) && (rcap >= kSegWindowMinItems || seg_kcut >= 0)) {
+      if (q.segments && (b == kBJ1 || b == kCCM1) && (rcap >= kSegWindowMinItems || pin.size() > 1 || seg_kcut >= 0)) {
         // A tile whose smallest parameter is lambda has K = floor(c / lambda)
         // (BJ1) or floor(floor(c/2) / lambda) (CCM1) and 2K windows of about
         // (tile j + bucket) sizes, at about per_size slots per size and

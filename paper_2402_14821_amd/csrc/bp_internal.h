@@ -28,10 +28,12 @@ constexpr int kSegTiles = 8;
 // Largest K = floor(c / lambda) a segment tile of BJ1 handles (2K windows).
 constexpr int kSegMaxK = 64;
 constexpr int kSegQPerChunk = 8;  // q values per chunk of a split BJ1/CCM1 segment tile
-// Windowed BJ1/CCM1 segment tiles only for instances of at least this many
-// items: below it their chains of dependent loads are slower than the dense
-// tiles (measured at c = 10^6 with r = 366 and 1 335: BJ1 142 vs 123 us,
-// 226 vs 213 us; CCM1 104 vs 73 us, 126 vs 98 us).
+// Windowed BJ1/CCM1 segment tiles in a single check only for instances of
+// at least this many items: below it their chains of dependent loads take
+// longer than the dense tiles' fuller machine (measured at c = 10^6 with
+// r = 366 and 1 335: BJ1 142 vs 123 us, 226 vs 213 us; CCM1 104 vs 73 us,
+// 126 vs 98 us).  A launch of several instances keeps them: there the total
+// work decides (the uneven batch of 4 096 checks: 0.085 s against 0.19 s).
 constexpr int64_t kSegWindowMinItems = 8192;
 constexpr int kSmallThreads = 256;      // prep block for small instances
 constexpr int kSmallCap = 8192;         // items per small-instance prep block (LDS resident)
