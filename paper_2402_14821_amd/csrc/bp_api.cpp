@@ -235,12 +235,12 @@ bp_status Ctx::init(int dev) {
   num_cu = prop.multiProcessorCount;
   HIP_TRY(set_kernel_attrs());
   HIP_TRY(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-  // Events that only order work on this device or time it skip the
-  // system-scope fence (an L2 writeback and invalidation at each record);
-  // `done`, which precedes host reads of results, keeps it.
-  HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming | hipEventDisableSystemFence));
+  // The stage-timing events only measure time: they skip the system-scope
+  // fence (an L2 writeback and invalidation at each record).  The ordering
+  // events keep it.
+  HIP_TRY(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&last_run, hipEventDisableTiming | hipEventDisableSystemFence));
+  HIP_TRY(hipEventCreateWithFlags(&last_run, hipEventDisableTiming));
   for (auto &set : tev)
     for (hipEvent_t &e : set) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   bp_status st = counter_buf.reserve(sizeof(unsigned long long) * kQueues * kQueueStride);
