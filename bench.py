@@ -720,7 +720,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="core-seconds of oracle work to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-checks", type=int, default=2000)
@@ -728,6 +728,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--per-bound", action="store_true",
                     help="only time each DFF sweep alone on the large instance, dense and segment form, and exit")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the checks of the large instance with several in flight on separate streams")
     ap.add_argument("--no-segments", action="store_true",
                     help="skip the segment-sum legs (profiling runs of the dense kernel alone)")
     ap.add_argument("--served-seconds", type=float, default=2.0)
@@ -866,6 +868,41 @@ def main():
             ctx.set_timing(False)
             segments = {"error": str(e)}
 
+    def bench_pipelined(nstreams: int):
+        """Independent checks of the same instance, each the plain path, on
+        `nstreams` contexts and streams in turn: a stream of checks with
+        several in flight (one sweep's tail and the next check's prep and
+        finalize overlap).  Reported beside the one-stream headline."""
+        ctxs = [bp.Context(0) for _ in range(nstreams)]
+        strs = [torch.cuda.Stream(dev) for _ in range(nstreams)]
+        outs = [torch.zeros(bp.BOUNDS_DTYPE.itemsize, dtype=torch.uint8, device=dev) for _ in range(nstreams)]
+        try:
+            def one(i):
+                j = i % nstreams
+                ctxs[j].feasible_dev(C, m, d_res.data_ptr(), len(unpacked), d_unp.data_ptr(), outs[j].data_ptr(),
+                                     strs[j].cuda_stream, flags=bp.BP_NO_EARLY_EXIT)
+            for i in range(max(args.warmup, nstreams)):
+                one(i)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            for i in range(args.steps):
+                one(i)
+            torch.cuda.synchronize()
+            dtp = time.perf_counter() - t3
+            for j in range(nstreams):
+                got = bp.bounds_to_dict(np.frombuffer(outs[j].cpu().numpy().tobytes(), dtype=bp.BOUNDS_DTYPE)[0])
+                if not all(np.array_equal(got[f], rec[f]) for f in ("value", "argmax")):
+                    return {"error": "a pipelined record differs from the single-stream record"}
+            return {"streams": nstreams, "ms_per_check": dtp * 1e3 / args.steps, "checks_per_s": args.steps / dtp,
+                    "evals_per_s": evals_per_step * args.steps / dtp}
+        finally:
+            for c in ctxs:
+                c.close()
+
+    pipelined = None
+    if not args.no_pipelined:
+        pipelined = [bench_pipelined(k) for k in (2, 3)]
+
     ops = sweep_ops(bp, C, r)
     achieved = ops / (sweep_avg * 1e-3)
     traffic = load_traffic("k_sweep")
@@ -903,6 +940,7 @@ def main():
                                  "workload": "n=50 sizes U[20,100], m=20, C=150, 30% pre-packed; host in/out"},
         "verdict": rec["verdict"], "lb": rec["lb"],
         "segments": segments,
+        "pipelined": pipelined,
     }
     log(f"large instance done: {ms_per_step:.3f} ms/step")
     if not args.no_batched:
