@@ -754,9 +754,22 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
   for (size_t j : order) seq.push_back(ent[j]);
   for (Entry &e : seq) {
     e.split_base = cnt;
+    e.slot32 = 0;
     if (e.nchunks > 1) {
+      // Item chunks of MT, RAD2, CCM1, VB2 and BJ1 tiles have partial sums of
+      // magnitude at most 2 c per item (MT, RAD2, VB2: c; CCM1: 2c / lambda;
+      // BJ1: the sizes' sum plus lambda per item), so a chunk of at most
+      // ceil(r / chunks) items fits an int32 slot when that times 2c does:
+      // half the slot traffic.  FS1 (up to 100 c per item) and the q-range
+      // chunks of segment and lookup tiles keep int64.
+      const int64_t rcap = plan_vec[(size_t)e.inst].r_cap;
+      const int64_t per = (rcap + e.nchunks - 1) / e.nchunks;
+      const bool item_split = e.mode == kModeDense || e.mode == kModeMirror;
+      const bool bounded = e.bound == kMT || e.bound == kRAD2 || e.bound == kCCM1 || e.bound == kVB2 || e.bound == kBJ1;
+      e.slot32 = item_split && bounded && per * 2 * (int64_t)plan_vec[(size_t)e.inst].C < (int64_t(1) << 31) ? 1 : 0;
+      const int64_t n = e.ntiles * e.nchunks * tile;
       e.acc_base = acc;
-      acc += e.ntiles * e.nchunks * tile;
+      acc += e.slot32 ? (n + 1) / 2 : n;
       cnt += (e.ntiles + kSegTiles - 1) / kSegTiles;
     }
   }

@@ -148,8 +148,10 @@ struct Entry {
   int32_t bound;        // kL2 .. kBJ1
   int32_t tpt;          // tiles per task
   int32_t nchunks;      // item chunks per tile
-  int32_t mode;         // kModeDense, kModeSegments or kModeMirror (the last two never split into chunks)
+  int32_t mode;         // kModeDense, kModeSegments, kModeMirror, ...
   int32_t aux;          // kModeMirror: last parameter of the dense half
+  int32_t slot32;       // nchunks > 1: the slots hold int32 (every chunk's partial sum fits), else int64
+  int32_t pad;
 };
 
 struct LaunchDesc {

@@ -2081,8 +2081,14 @@ __device__ void run_task(const LaunchDesc &d, uint64_t task) {
       // A chunk of a split tile: store its partial sums in its own slot (no
       // other wave touches it) and move on; the combine kernel adds the
       // chunks of the tile once the sweep is over.
-      long long *slot = d.acc + e.acc_base + (tl * nch + chunk) * (64 * LPL);
-      for (int j = 0; j < LPL; ++j) slot[lane_id() + 64 * j] = (long long)part[j];
+      const int64_t at = (tl * nch + chunk) * (64 * LPL);
+      if (e.slot32) {
+        int32_t *slot = (int32_t *)(d.acc + e.acc_base) + at;
+        for (int j = 0; j < LPL; ++j) slot[lane_id() + 64 * j] = (int32_t)part[j];
+      } else {
+        long long *slot = d.acc + e.acc_base + at;
+        for (int j = 0; j < LPL; ++j) slot[lane_id() + 64 * j] = (long long)part[j];
+      }
       continue;
     }
     if (e.mode == kModeMirror) {
@@ -2131,7 +2137,6 @@ __global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__
     uint64_t key = 0;
     if (tl < e.ntiles && t.lam0 <= t.hi && !(early && refuted_now(d, e.inst))) {
       const int32_t nch = e.nchunks;
-      const long long *slots = d.acc + e.acc_base + tl * nch * (64 * LPL);
       int64_t lam[LPL], lbp[LPL], part[LPL];
       bool ok[LPL];
       uint32_t l32[LPL];
@@ -2143,18 +2148,24 @@ __global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__
       tile_lams<LPL>(tv, lam, l32);
       for (int j = 0; j < LPL; ++j) part[j] = 0;
       // four chunks' loads in flight at a time
-      int32_t c = 0;
-      for (; c + 4 <= nch; c += 4) {
-        long long v[4][LPL];
+      auto add_slots = [&](const auto *slots) {
+        int32_t c = 0;
+        for (; c + 4 <= nch; c += 4) {
+          int64_t v[4][LPL];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          for (int j = 0; j < LPL; ++j) v[u][j] = slots[(c + u) * (64 * LPL) + lane_id() + 64 * j];
+          for (int u = 0; u < 4; ++u)
+            for (int j = 0; j < LPL; ++j) v[u][j] = slots[(c + u) * (64 * LPL) + lane_id() + 64 * j];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          for (int j = 0; j < LPL; ++j) part[j] += v[u][j];
-      }
-      for (; c < nch; ++c)
-        for (int j = 0; j < LPL; ++j) part[j] += slots[c * (64 * LPL) + lane_id() + 64 * j];
+          for (int u = 0; u < 4; ++u)
+            for (int j = 0; j < LPL; ++j) part[j] += v[u][j];
+        }
+        for (; c < nch; ++c)
+          for (int j = 0; j < LPL; ++j) part[j] += slots[c * (64 * LPL) + lane_id() + 64 * j];
+      };
+      if (e.slot32)
+        add_slots((const int32_t *)(d.acc + e.acc_base) + tl * nch * (64 * LPL));
+      else
+        add_slots(d.acc + e.acc_base + tl * nch * (64 * LPL));
       if (e.mode == kModeMirror) {
         key = vb2_mirror_key<LPL>(t, e.aux, lam, part);
       } else {
