@@ -493,6 +493,23 @@ def test_huge_capacity_full_ranges(ctx):
                 max(0, hi - lo + 1) for lo, hi in (O.default_range(d, C) for d in O.DFFS))
 
 
+@pytest.mark.parametrize("C", [1 << 20, 1 << 21])
+def test_split_tile_slot_widths(ctx, C):
+    # 16 000 big sizes, each range cut to 384 parameters (three tiles) at its
+    # top end, so every tile is split into 16 item chunks of 1 000 sizes: at
+    # c = 2^20 the chunk sums go through 32-bit slots (1 000 x 2c < 2^31), at
+    # 2^21 through 64-bit ones; both against the oracle
+    g = np.random.default_rng(C)
+    items = g.integers(C // 2, C + 1, size=16000).astype(np.int32)
+    lo, hi = [0] * O.NB, [-1] * O.NB
+    for b in range(1, O.NB):
+        dlo, dhi = O.default_range(b, C)
+        lo[b], hi[b] = (max(dlo, dhi - 383), dhi) if dlo <= dhi else (1, 0)
+    want = O.bounds(C, 0, items, lo, hi)
+    say("split-tile slot widths", C)
+    same(ctx.lower_bounds(C, 0, items, bp.make_sweep(lo, hi)), want, ("slots", C))
+
+
 def test_edge_cases(ctx):
     cases = [
         (1, []), (1, [0]), (1, [1, 1, 0]), (2, [1, 1, 2]), (3, [1, 2, 3, 0]), (7, [7] * 5),
