@@ -1,20 +1,33 @@
 // bp_kernels.hip -- gfx950 kernels of the bin_packing feasibility check.
 //
 // Pipeline of one launch (a batch; a single check is a batch of one):
-//   k_prep_small / k_prep_large  one block per instance (persistent over the
-//       batch): reduce the partial packing to one capacity (Sec. 3, Fig. 3),
-//       validate, LSD radix sort by decreasing size in LDS, int64 prefix sums
-//       (DPP wave scans), class boundaries and the class-sorted item stream.
-//   k_sweep  persistent: waves pull tasks (instance, bound, run of parameter
-//       tiles) from one atomic counter, in longest-first order.  A tile gives
-//       each lane LPL parameters; the wave reads the item stream with scalar
-//       loads (every lane uses the same item) and accumulates
-//       sum_w f(w, lambda) per lane (Alg. 2's inner loop, Alg. 4's per-thread
-//       loop), then ceil(sum / f(c, lambda)) and a DPP wave max of packed
-//       (bound, parameter) keys, one 64-bit atomic max per tile.  L2 tiles
-//       evaluate L2(I, lambda) at the parameters where it can change, from
-//       the sorted sizes and prefix sums by binary search (Sec. 3.1).
-//   k_finalize  per instance: L1, the maximum over the collection, verdict.
+//   k_prep  one block per instance (persistent over the batch): reduce the
+//       partial packing to one capacity (Sec. 3, Fig. 3), validate, LSD radix
+//       sort by decreasing size in LDS, int64 prefix sums (DPP wave scans),
+//       class boundaries and sums, the class-sorted item stream.  Three
+//       forms: 256 threads for up to 2 048 or 8 192 items, 1 024 threads for
+//       up to 16 384.  The 256-thread form also builds the histogram of the
+//       value-table instances (vt_hist).
+//   k_vt_emit  value-table prep of large instances over the whole GPU: the
+//       sorted sizes, prefix sums and class bounds read off per-value counts.
+//   k_sweep  persistent: each wave runs task (its index) first, then claims
+//       tasks (instance, bound, run of parameter tiles, or one item chunk of
+//       a tile) from eight queues, its own XCD's first, in longest-first
+//       order.  A tile gives each lane LPL parameters; the wave reads the
+//       item stream with scalar loads (every lane uses the same item) and
+//       accumulates sum_w f(w, lambda) per lane (Alg. 2's inner loop, Alg.
+//       4's per-thread loop), then ceil(sum / f(c, lambda)) and a DPP wave
+//       max of packed (bound, parameter) keys, one 64-bit atomic max per
+//       tile.  An item chunk stores its partial sums in a slot of its own.
+//       L2 tiles evaluate L2(I, lambda) at the parameters where it can
+//       change (Sec. 3.1); the segment forms read threshold sums.
+//   k_combine  adds the chunk slots of each split tile and finalises it.
+//   k_finalize  per instance: L1, the maximum over the collection, verdict;
+//       clears the value tables the launch used.
+// Beside the pipeline: k_small_check (a whole small check in one launch),
+// k_node_* (served children from their base's sums), k_reduce_one /
+// k_bin_loads (the reductions alone), and the allocation-free variant's
+// tables kernel.
 //
 // Class split used by the sweeps (sizes sorted decreasing):
 //   [0, nf) w = c ; [nf, nb) c/2 < w < c ; [nb, nm) 2w = c ;
