@@ -89,7 +89,7 @@ struct InstPlan {
   int32_t ndiv;      // divisors of c listed for the mirrored VB2 tiles (0: none)
   int32_t pad2;
   int64_t state_off; // >= 0: the instance's node state (see node_layout) at LaunchDesc::nodes + state_off
-  int64_t vt_off;    // large == 2: offset of the c + 2 value-table entries (LaunchDesc::vcnt, vsum)
+  int64_t vt_off;    // large == 2: offset of the c + 2 value-table entries (LaunchDesc::vraw, vcnt, vsum)
   int64_t vtt_off;   // large == 2: offset of the chunk totals, then the chunk offsets (2 x 2 x chunks, LaunchDesc::vtot)
   int64_t vl_off;    // large == 2, ndiv > 0: offset of the 2 x ndiv lattice bins (LaunchDesc::vlat)
 };
