@@ -701,8 +701,10 @@ bp_status Ctx::plan(const std::vector<PlanIn> &pin, int64_t *ntasks_out) {
     Entry &e = ent[j];
     const double tc = tile_cost_v[j];
     if (e.mode == kModeLookup) {
-      e.nchunks = e.aux;  // chunks of the q range, set by the band
-      e.aux = 0;
+      if (e.aux) {  // chunks of the q range, set by the band (moved once: this loop may run again)
+        e.nchunks = e.aux;
+        e.aux = 0;
+      }
       e.tpt = 1;
       task_cost[j] = tc / e.nchunks;
     } else if (split_seg && e.mode == kModeSegments && (e.bound == kBJ1 || e.bound == kCCM1)) {
