@@ -239,8 +239,8 @@ def test_vb2_below_scaled_size():
 
 def test_piece_starts_match_every_lambda():
     rng = random.Random(13)
-    for _ in range(300):
-        C, items = _rand_instance(rng, cmax=200, nmax=12)
+    for t in range(500):
+        C, items = _rand_instance(rng, cmax=200 if t < 300 else 3000, nmax=12 if t < 300 else 80)
         for kind in (O.L2, O.MT, O.RAD2):
             lo, hi = O.default_range(kind, C)
             if kind == O.L2:
