@@ -617,103 +617,122 @@ def per_bound_table(bp, W, ctx, reps: int = 5):
 
 
 def bench_served(bp, W, ctx, rate: float, duration: float, seed: int, budget: int = 8 << 30, flags: int = 0,
-                 max_slots: int = 8192):
+                 max_slots: int = 8192, warmup: float = 0.25):
     """Open-loop Poisson arrivals of the simulated search's requests into a
     bp_queue.  Roots go in as partial packings (checked exhaustively: the
     search expands them), children as (parent ticket, commits) without their
     instances; a request whose parent was rejected is dropped with its
-    subtree.  Latency from the library's clock; evaluations as performed."""
+    subtree.  A shorter stream of another seed first warms the queue (its
+    contexts' launch shapes and buffers) and is not counted.  Latency from
+    the library's clock; evaluations as performed."""
     import ctypes
     import threading
 
     import numpy as np
 
+    lib = bp.load()
+    q = bp.Queue(ctx, budget, max_slots)
+
+    def run_stream(reqs):
+        m_of = {}
+        structs, keep = [], []
+        for i, r in enumerate(reqs):
+            if r.parent < 0:
+                res = np.ascontiguousarray(r.residual, dtype=np.int32)
+                unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
+                keep.append((res, unp))
+                m_of[i] = len(res)
+                structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
+                                             unp.ctypes.data_as(bp._P32), i, flags | bp.BP_NO_EARLY_EXIT, 0, 0,
+                                             None, 0, 0))
+            else:
+                m_of[i] = m_of[r.parent]
+                cm = (bp.bp_commit * max(1, len(r.commits)))(*[bp.bp_commit(w, b) for w, b in r.commits])
+                keep.append(cm)
+                structs.append(bp.bp_request(r.C, m_of[i], 0, None, None, i, flags, 0, 0, cm, len(r.commits), 0))
+        results = []
+        done = threading.Event()
+        submitted = [0]
+
+        def poller():
+            arr = (bp.bp_result * 4096)()
+            got = ctypes.c_int32(0)
+            while True:
+                lib.bp_queue_poll(q.handle, ctypes.cast(arr, ctypes.c_void_p), 4096, ctypes.byref(got), 2000)
+                for j in range(got.value):
+                    a = arr[j]
+                    results.append((a.tag, a.submit_us, a.done_us, a.status, a.bounds.evals, a.bounds.evals_done,
+                                    a.from_parent, a.verdict))
+                if done.is_set() and len(results) >= submitted[0]:
+                    return
+
+        th = threading.Thread(target=poller, daemon=True)
+        th.start()
+        # the open-loop submitter runs natively (bp_queue_replay): a Python
+        # loop cannot keep 5 us between arrivals
+        n = len(reqs)
+        arr = (bp.bp_request * n)(*structs)
+        arrival = np.ascontiguousarray([r.t for r in reqs], dtype=np.float64)
+        parent = np.ascontiguousarray([r.parent for r in reqs], dtype=np.int64)
+        tickets = np.zeros(n, dtype=np.uint64)
+        status = np.zeros(n, dtype=np.int32)
+        late_c = ctypes.c_double(0)
+        submitted[0] = n  # an upper bound until the replay returns
+        t0 = time.perf_counter()
+        st = lib.bp_queue_replay(q.handle, ctypes.cast(arr, ctypes.c_void_p),
+                                 arrival.ctypes.data_as(ctypes.c_void_p), parent.ctypes.data_as(ctypes.c_void_p), n,
+                                 tickets.ctypes.data_as(ctypes.c_void_p), status.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(late_c))
+        if st != 0:
+            raise bp.BpError(st, lib.bp_last_error().decode())
+        t_submit = time.perf_counter() - t0
+        other = status[(status != 0) & (status != bp.BP_ERR_AGAIN) & (status != bp.BP_ERR_STATE)]
+        if len(other):
+            raise bp.BpError(int(other[0]), "replay submit failed")
+        submitted[0] = int((status == 0).sum())
+        done.set()
+        th.join(timeout=120)
+        t_end = time.perf_counter() - t0
+        return results, status, late_c.value, t_submit, t_end, arrival
+
     t_gen = time.perf_counter()
     reqs = W.dfs_requests(seed, rate=rate, duration=duration, instances="roots")
     t_gen = time.perf_counter() - t_gen
-    lib = bp.load()
-    m_of = {}
-    structs, keep = [], []
-    for i, r in enumerate(reqs):
-        if r.parent < 0:
-            res = np.ascontiguousarray(r.residual, dtype=np.int32)
-            unp = np.ascontiguousarray(r.unpacked, dtype=np.int32)
-            keep.append((res, unp))
-            m_of[i] = len(res)
-            structs.append(bp.bp_request(r.C, len(res), len(unp), res.ctypes.data_as(bp._P32),
-                                         unp.ctypes.data_as(bp._P32), i, flags | bp.BP_NO_EARLY_EXIT, 0, 0, None,
-                                         0, 0))
-        else:
-            m_of[i] = m_of[r.parent]
-            cm = (bp.bp_commit * max(1, len(r.commits)))(*[bp.bp_commit(w, b) for w, b in r.commits])
-            keep.append(cm)
-            structs.append(bp.bp_request(r.C, m_of[i], 0, None, None, i, flags, 0, 0, cm, len(r.commits), 0))
-    q = bp.Queue(ctx, budget, max_slots)
-    results = []
-    done = threading.Event()
-    submitted = [0]
-
-    def poller():
-        arr = (bp.bp_result * 4096)()
-        got = ctypes.c_int32(0)
-        while True:
-            lib.bp_queue_poll(q.handle, ctypes.cast(arr, ctypes.c_void_p), 4096, ctypes.byref(got), 2000)
-            for j in range(got.value):
-                a = arr[j]
-                results.append((a.tag, a.submit_us, a.done_us, a.status, a.bounds.evals, a.bounds.evals_done,
-                                a.from_parent, a.verdict))
-            if done.is_set() and len(results) >= submitted[0]:
-                return
-
-    th = threading.Thread(target=poller, daemon=True)
-    th.start()
-    # the open-loop submitter runs natively (bp_queue_replay): a Python loop
-    # cannot keep 5 us between arrivals
-    n = len(reqs)
-    arr = (bp.bp_request * n)(*structs)
-    arrival = np.ascontiguousarray([r.t for r in reqs], dtype=np.float64)
-    parent = np.ascontiguousarray([r.parent for r in reqs], dtype=np.int64)
-    tickets = np.zeros(n, dtype=np.uint64)
-    status = np.zeros(n, dtype=np.int32)
-    late_c = ctypes.c_double(0)
-    submitted[0] = n  # an upper bound until the replay returns
-    t0 = time.perf_counter()
-    st = lib.bp_queue_replay(q.handle, ctypes.cast(arr, ctypes.c_void_p), arrival.ctypes.data_as(ctypes.c_void_p),
-                             parent.ctypes.data_as(ctypes.c_void_p), n, tickets.ctypes.data_as(ctypes.c_void_p),
-                             status.ctypes.data_as(ctypes.c_void_p), ctypes.byref(late_c))
-    if st != 0:
-        raise bp.BpError(st, lib.bp_last_error().decode())
-    t_submit = time.perf_counter() - t0
-    late = late_c.value
-    rejected = int((status == bp.BP_ERR_AGAIN).sum())
-    dropped = int((status == bp.BP_ERR_STATE).sum())
-    other = status[(status != 0) & (status != bp.BP_ERR_AGAIN) & (status != bp.BP_ERR_STATE)]
-    if len(other):
-        raise bp.BpError(int(other[0]), "replay submit failed")
-    submitted[0] = int((status == 0).sum())
-    done.set()
-    th.join(timeout=120)
-    t_end = time.perf_counter() - t0
+    if warmup > 0:
+        run_stream(W.dfs_requests(seed + 7919, rate=rate, duration=warmup, instances="roots"))
+    s0 = q.stats()
+    results, status, late, t_submit, t_end, arrival = run_stream(reqs)
     stats = q.stats()
     q.close()
+    rejected = int((status == bp.BP_ERR_AGAIN).sum())
+    dropped = int((status == bp.BP_ERR_STATE).sum())
     ok = [x for x in results if x[3] == 0]
     lat = np.array([d - s for _, s, d, *_ in ok])
+    # the second half of the stream's arrivals: steady state
+    late_half = np.array([d - s for tag, s, d, *_ in ok if arrival[tag] >= duration / 2])
+    # the stream's span on the library's clock: first submit to last result
+    span = (max(x[2] for x in ok) - min(x[1] for x in ok)) * 1e-6 if ok else t_end
     evals_nominal = sum(x[4] for x in ok)
     evals_done = sum(x[5] for x in ok)
-    return {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "submitted": submitted[0],
+    return {"rate_per_s": rate, "duration_s": duration, "warmup_s": warmup, "requests": len(reqs),
+            "submitted": int((status == 0).sum()),
             "completed": int(len(ok)), "rejected": rejected, "dropped_with_rejected_parent": dropped,
-            "checks_per_s": len(ok) / t_end, "evals_per_s": evals_done / t_end,
-            "nominal_evals_per_s": evals_nominal / t_end,
+            "checks_per_s": len(ok) / span, "evals_per_s": evals_done / span,
+            "nominal_evals_per_s": evals_nominal / span, "span_s": span, "wall_s": t_end,
             "p50_us": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_us": float(np.percentile(lat, 99)) if len(lat) else None,
-            "from_parent": int(stats["from_parent"]), "full_sweeps": int(stats["full_sweeps"]),
-            "node_evictions": int(stats["node_evictions"]), "batches": stats["batches"],
+            "p99_us_second_half": float(np.percentile(late_half, 99)) if len(late_half) else None,
+            "from_parent": int(stats["from_parent"] - s0["from_parent"]),
+            "full_sweeps": int(stats["full_sweeps"] - s0["full_sweeps"]),
+            "node_evictions": int(stats["node_evictions"] - s0["node_evictions"]),
+            "batches": stats["batches"] - s0["batches"],
             "peak_bytes": stats["bytes_peak"], "max_slots": max_slots, "max_submit_lateness_s": late,
             "submit_s": t_submit, "generate_s": t_gen, "segments": bool(flags & bp.BP_SEGMENTS),
             "fails": int(sum(1 for x in ok if x[7] == 0)),
             "workload": "simulated search: roots n~U[200,5000], sizes U[C/20,C/2], C=10000, m = best-fit-decreasing "
                         "bins; children commit 1-3 items by decreasing best fit, 30% backtracking, a new root every "
-                        "64 nodes; roots exhaustive, children from their parents' sums; HBM budget 8 GB"}
+                        "64 nodes; roots exhaustive, children from their parents' sums; HBM budget 8 GB; a 0.25 s "
+                        "stream of another seed warms the queue first"}
 
 
 def main():
