@@ -155,10 +155,6 @@ def test_value_table_prep_matches_block_prep_and_oracle(ctx, ctx_block):
     same(ctx.feasible(C, res, unp, flags=bp.BP_NO_EARLY_EXIT), want, "after the range errors")
 
 
-@pytest.mark.skip(reason="a GPU memory fault followed when test_value_table_launch_sequences ran right after "
-                         "this test in one process (with the staging and ordering events recorded without the "
-                         "system-scope fence, a change since taken out); the cause is not shown, so this case "
-                         "stays off the GPU")
 @pytest.mark.parametrize("C", [2046, 2047, 2048, 4094, 4095])
 def test_value_table_chunk_edges(ctx, C):
     # the tables hold c + 2 values in chunks of 2 048: c + 2 at, just past and
