@@ -42,7 +42,14 @@ sys.path.insert(0, ROOT)
 #   BJ1  v_mul_hi_u32, v_lshrrev_b32 (1/2), v_mad_u64_u32, v_sad_u32,
 #        1/2 v_add3_u32                                                      = 4.0
 # (v_add3_u32 adds two items' increments at once, hence 1/2 per evaluation.)
+# Where the quotient's product is at most 2^32 one high multiply gives it
+# (CCM1: a lambda, BJ1: w lambda over the tile's largest lambda; VB2: a c),
+# and the evaluation drops the shift or the v_mad_u64_u32:
+#   CCM1 v_mul_hi_u32, 1/2 v_add3_u32                                       = 1.5
+#   VB2  v_mul_hi_u32, 1/2 v_add3_u32                                       = 1.5
+#   BJ1  v_mul_hi_u32, v_mad_u64_u32, v_sad_u32, 1/2 v_add3_u32             = 3.5
 OPS_PER_EVAL = {"MT": 2.0, "RAD2": 3.0, "FS1": 10.25, "CCM1": 2.0, "VB2": 2.5, "BJ1": 4.0}
+OPS_PER_EVAL_SHORT = {"CCM1": 1.5, "VB2": 1.5, "BJ1": 3.5}
 PEAK_VALU = 256 * 64 * 2.4e9  # full-rate lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 DFF_NAMES = ("MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1")
 
@@ -209,14 +216,42 @@ def valu_rates(blocks_per_cu: int = 8, iters: int = 4000, reps: int = 3):
             "insts_per_lane": iters * 128, "reps": reps, "rates": rows}
 
 
-def sweep_ops(bp, C, r):
+def sweep_ops(bp, C, items, lanes_params: int = 2):
     """Algorithmic VALU slots of the six sweeps of one instance (exact ranges,
-    as the library's own bp_default_sweep states them)."""
-    sw = bp.default_sweep(int(C))
+    as the library's own bp_default_sweep states them), each evaluation at
+    the weight of the form the kernel takes for it: tiles of 64 x
+    lanes_params parameters from the range's start, and per tile the sizes
+    whose quotient fits one high multiply on the short form."""
+    import numpy as np
+
+    C = int(C)
+    w = np.asarray(items, dtype=np.int64)
+    w = w[(w > 0) & (w < C)]
+    a = np.sort(np.where(2 * w > C, C - w, w)[2 * w != C])  # CCM1 and VB2 stream these (big and small)
+    ws = np.sort(w)                                           # BJ1 streams the sizes 0 < w < c
+    r = len(items)
+    sw = bp.default_sweep(C)
+    width = 64 * lanes_params
     ops = 0.0
     for j, name in enumerate(DFF_NAMES):
         b = bp.BP_MT + j
-        ops += OPS_PER_EVAL[name] * r * max(0, sw.hi[b] - sw.lo[b] + 1)
+        lo, hi = int(sw.lo[b]), int(sw.hi[b])
+        if hi < lo:
+            continue
+        if name not in OPS_PER_EVAL_SHORT:
+            ops += OPS_PER_EVAL[name] * r * (hi - lo + 1)
+            continue
+        full, short = OPS_PER_EVAL[name], OPS_PER_EVAL_SHORT[name]
+        vals = ws if name == "BJ1" else a
+        if name == "VB2":
+            n_short = np.searchsorted(vals, 0xFFFFFFFF // C, side="right")
+            ops += (hi - lo + 1) * (short * n_short + full * (len(vals) - n_short))
+            continue
+        t0 = np.arange(lo, hi + 1, width, dtype=np.int64)
+        t1 = np.minimum(t0 + width - 1, hi)
+        lim = np.where(t0 >= 2, 0xFFFFFFFF // t1, -1)
+        n_short = np.searchsorted(vals, lim, side="right")
+        ops += float(((t1 - t0 + 1) * (short * n_short + full * (len(vals) - n_short))).sum())
     return ops
 
 
@@ -296,7 +331,8 @@ def bench_batched(bp, W, ctx, seed: int = 2, count: int = 4096, reps: int = 3, p
         ctx.lower_bounds_batch(Cs, ks, items_list)
     (prep_ms, sweep_ms, fin_ms), runs = ctx.stage_times(with_runs=True)
     ctx.set_timing(False)
-    ops = sum(sweep_ops(bp, int(c), int(r)) for c, r in zip(Cs, out["r"]))
+    lpl = int(ctx.get_tuning()["lanes_params"])
+    ops = sum(sweep_ops(bp, int(c), it, lpl) for c, it in zip(Cs, items_list))
     fails = int((out["verdict"] == 0).sum())
     assert np.array_equal(out["verdict"] == 0, b.expect_fail), "batched verdicts differ from the construction"
     # plain: one call per instance, each synchronous, with the default shape
@@ -922,7 +958,10 @@ def main():
     if not args.no_pipelined:
         pipelined = [bench_pipelined(k) for k in (2, 3)]
 
-    ops = sweep_ops(bp, C, r)
+    # the reduced items (Fig. 3): the unpacked sizes and one virtual item per bin that is not empty
+    items_red = np.concatenate([unpacked, C - residual[residual < C]])
+    assert len(items_red) == r
+    ops = sweep_ops(bp, C, items_red, int(ctx.get_tuning()["lanes_params"]))
     achieved = ops / (sweep_avg * 1e-3)
     traffic = load_traffic("k_sweep")
     valu_insts = load_valu_insts("k_sweep")
@@ -950,7 +989,8 @@ def main():
         "stages_ms": {"prep": prep_avg, "sweep": sweep_avg, "finalize": fin_avg, "runs": runs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic, "kernel": "k_sweep",
-                     "ops_per_eval": OPS_PER_EVAL, "weights": "profiles/valu_rates_gfx950.txt",
+                     "ops_per_eval": OPS_PER_EVAL, "ops_per_eval_short": OPS_PER_EVAL_SHORT,
+                     "weights": "profiles/valu_rates_gfx950.txt",
                      "slots_per_launch": ops,
                      # every VALU instruction the kernel issued (SQ_INSTS_VALU x 64 lanes) as one full slot
                      "frac_issue": (valu_insts * 64 / (sweep_avg * 1e-3) / PEAK_VALU) if valu_insts else None,

@@ -480,7 +480,9 @@ int32_t bp_subset_sum_gap(const int32_t *x, int32_t n, int64_t alpha, int64_t be
  * n < 2^31; mode 1: ceil(a lam / c) - 1 (f_VB2's quotient), d taken as c;
  * mode 2: the divisibility test d | n; mode 3: floor(n / d) through an fp64
  * reciprocal and one correction step; mode 4: floor((a lam - 1) / c) the
- * same way, d taken as c.  d_lo >= 1, d_hi < 2^31, n_hi < 2^31, else
+ * same way, d taken as c; mode 5: floor(n / d) by one high multiply where
+ * n d <= 2^32 (d >= 2); mode 6: ceil(a lam / c) - 1 by one high multiply
+ * where a c <= 2^32, d taken as c.  d_lo >= 1, d_hi < 2^31, n_hi < 2^31, else
  * BP_ERR_ARG (also for any other mode).  Returns the number of mismatches
  * found (0 = all exact) or a negative status. */
 int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32_t mode);

@@ -1798,6 +1798,65 @@ int64_t bp_selftest_division(uint32_t d_lo, uint32_t d_hi, uint32_t n_hi, uint32
         }
       }
     }
+  } else if (mode == 5) {
+    // floor(n / d) by family (5a) where n d <= 2^32: every d in [max(d_lo, 2), d_hi], n in [0, n_hi] under
+    // that limit, the multiples of d around it and the limit itself
+    for (uint64_t d = std::max<uint64_t>(d_lo, 2); d <= d_hi; ++d) {
+      const uint32_t m = magic_short((uint32_t)d);
+      const uint64_t lim = (1ull << 32) / d;  // the largest n with n d <= 2^32
+      auto one = [&](uint64_t n) {
+        if (n > lim) return;
+        if (div_short((uint32_t)n, m) != (uint32_t)(n / d)) ++bad;
+      };
+      for (uint64_t n = 0; n <= n_hi; ++n) one(n);
+      for (uint64_t k = 1; k <= 64; ++k) {
+        one(d * k - 1);
+        one(d * k);
+        one(d * k + 1);
+      }
+      const uint64_t q = lim / d;
+      for (uint64_t t = 0; t <= 4; ++t) {
+        if (q * d + t >= 2) one(q * d + t - 2);
+        if (q >= t && (q - t) * d > 0) {
+          one((q - t) * d - 1);
+          one((q - t) * d);
+        }
+        if (lim >= t) one(lim - t);
+      }
+    }
+  } else if (mode == 6) {
+    // ceil(a lam / c) - 1 by family (5b) where a c <= 2^32: c in [d_lo, d_hi], lam as in mode 1, a up to
+    // that limit (capped at n_hi, plus the top of the range and a where a lam / c is an integer or one off)
+    for (uint64_t c = d_lo; c <= d_hi; ++c) {
+      const uint64_t alim = std::min<uint64_t>(c, (1ull << 32) / c);
+      const uint64_t lam_step = c > 4096 ? c / 4096 : 1;
+      for (uint64_t lam = 1; lam <= c; lam += (lam < 64 || c - lam < 64) ? 1 : lam_step) {
+        const uint64_t R = vb2_recip((uint32_t)lam, (uint32_t)c);
+        auto one = [&](uint64_t a) {
+          if (a < 1 || a > alim) return;
+          const unsigned __int128 p = (unsigned __int128)a * lam;
+          const uint64_t want = (uint64_t)((p + c - 1) / c) - 1;
+          if (vb2_part_short((uint32_t)a, (uint32_t)(R >> 32)) != want) ++bad;
+        };
+        for (uint64_t a = 1; a <= std::min<uint64_t>(alim, n_hi); ++a) one(a);
+        for (uint64_t a = alim > 64 ? alim - 64 : 1; a <= alim; ++a) one(a);
+        for (uint64_t k = 1; k <= 64; ++k) {
+          const unsigned __int128 t = (unsigned __int128)k * c;
+          const uint64_t a = (uint64_t)(t / lam);
+          one(a);
+          one(a + 1);
+          if (a > 1) one(a - 1);
+          // the same near the limit
+          const uint64_t kk = (uint64_t)(((unsigned __int128)alim * lam) / c);
+          if (kk >= k) {
+            const uint64_t b = (uint64_t)(((unsigned __int128)(kk - k + 1) * c) / lam);
+            one(b);
+            one(b + 1);
+            if (b > 1) one(b - 1);
+          }
+        }
+      }
+    }
   } else {
     return BP_ERR_ARG;
   }

@@ -1,7 +1,7 @@
 // bp_divide.h -- exact integer division by multiplication, for the sweep kernels.
 //
-// Two families, both exact for every input the kernels feed them (proofs
-// inline; the host self-test bp_selftest_division checks them against '/').
+// Each form is exact for every input the kernels feed it (proofs inline; the
+// host self-test bp_selftest_division checks them against '/').
 //
 // (1) Division by a per-lane parameter d (1 <= d < 2^31) of a numerator
 //     n < 2^31.  Granlund & Montgomery, "Division by invariant integers using
@@ -32,6 +32,22 @@
 //     d | n iff n M mod 2^64 <= M - 1.  For d = 1, M wraps to 0 and the test
 //     reads n 0 <= 2^64 - 1, true.  Cost: a 64-bit product by a 32-bit value
 //     and a 64-bit compare.
+//
+// (5) Short forms of (1) and (2) for small products, one v_mul_hi_u32 each.
+//     (a) floor(n / d) for 2 <= d < 2^31 and n d <= 2^32: with
+//         m = ceil(2^32 / d) = (2^32 + e) / d, 0 <= e < d (m <= 2^31), and
+//         n = q d + t (0 <= t < d), n m / 2^32 = q + (t + n e / 2^32) / d;
+//         n e < n d <= 2^32 keeps t + n e / 2^32 below t + 1 <= d, so
+//         floor(n m / 2^32) = q.  m = floor((2^32 - 1) / d) + 1 (equal to
+//         ceil(2^32 / d) whether or not d divides 2^32).
+//     (b) ceil(a lam / c) - 1 for 1 <= a, 1 <= lam <= c and a c <= 2^32,
+//         from R_hi, the high word of (2)'s R: R_hi = floor((lam 2^32 - 1) / c)
+//         (no multiple of c lies strictly between lam 2^32 - 1 and
+//         lam 2^32 - 2^-32), so lam 2^32 / c - 1 <= R_hi < lam 2^32 / c and
+//         v = a R_hi / 2^32 lies in [a lam / c - a / 2^32, a lam / c).  If
+//         a lam / c is an integer q, floor(v) = q - 1 (a / 2^32 <= 1);
+//         otherwise its fraction is at least 1/c >= a / 2^32 and floor(v) =
+//         floor(a lam / c).  Both equal ceil(a lam / c) - 1.
 #pragma once
 
 #include <stdint.h>
@@ -116,6 +132,23 @@ __host__ __device__ inline int64_t fdiv_u62(int64_t N, int64_t c, double rc) {
   while (r >= c) { ++q; r -= c; }
   return q;
 }
+
+// Constant of family (5a) for 2 <= d < 2^31: ceil(2^32 / d); 0 for d = 1
+// (which (5a) does not cover).
+__host__ __device__ inline uint32_t magic_short(uint32_t d) { return d >= 2 ? 0xffffffffu / d + 1u : 0u; }
+
+// floor(n / d) from m = magic_short(d), for n d <= 2^32 (family (5a)).
+__host__ __device__ inline uint32_t div_short(uint32_t n, uint32_t m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umulhi(n, m);
+#else
+  return (uint32_t)(((uint64_t)n * m) >> 32);
+#endif
+}
+
+// ceil(a lam / c) - 1 from the high word of vb2_recip(lam, c), for a >= 1
+// and a c <= 2^32 (family (5b)).
+__host__ __device__ inline uint32_t vb2_part_short(uint32_t a, uint32_t r_hi) { return div_short(a, r_hi); }
 
 // Constant of family (3) for divisor d in [1, 2^31): ceil(2^64 / d) mod 2^64.
 __host__ __device__ inline uint64_t divides_const(uint32_t d) { return ~0ull / d + 1ull; }

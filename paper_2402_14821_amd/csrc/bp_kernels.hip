@@ -1104,6 +1104,35 @@ __device__ __forceinline__ void stream_u32(const BP_CONST uint32_t *p, int i0, i
   for (; i < i1; ++i) f(p[i]);
 }
 
+// The sub-range of [i0, i1) whose values are at most lim, for a monotone
+// range (the sorted sizes of one class, or their complements): it is a
+// prefix or a suffix, [*s0, *s1), and the rest of the range is the other
+// end.  Two scalar loads decide the common cases (all or none); a range
+// that straddles lim takes a binary search.
+__device__ __forceinline__ void small_part(const BP_CONST uint32_t *p, int i0, int i1, uint32_t lim, int *s0,
+                                           int *s1) {
+  *s0 = *s1 = i0;
+  if (i0 >= i1) return;
+  const bool a = p[i0] <= lim, b = p[i1 - 1] <= lim;
+  if (a == b) {
+    if (a) *s1 = i1;
+    return;
+  }
+  // the first index whose test differs from the first item's, in (i0, i1 - 1]
+  int lo = i0 + 1, hi = i1 - 1;
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if ((p[mid] <= lim) == a) lo = mid + 1;
+    else hi = mid;
+  }
+  if (a) {
+    *s1 = lo;  // [i0, lo) passes
+  } else {
+    *s0 = lo;  // [lo, i1) passes
+    *s1 = i1;
+  }
+}
+
 // Sums over [i0, i1) in segments of at most L items so that 32-bit partial
 // sums cannot wrap; flushes each segment into the 64-bit totals.
 template <int LPL, typename F>
@@ -1116,6 +1145,20 @@ __device__ __forceinline__ void stream_chunked(const BP_CONST uint32_t *p, int i
     for (int j = 0; j < LPL; ++j) tot[j] += s[j];
     a = e;
   }
+}
+
+// stream_chunked over a monotone range with two bodies: fs for the items
+// at most lim (small_part), ff for the others.  Integer sums: the order of
+// the two parts does not change them.
+template <int LPL, typename FS, typename FF>
+__device__ __forceinline__ void stream_chunked_two(const BP_CONST uint32_t *p, int i0, int i1, int L, uint32_t lim,
+                                                   uint64_t tot[LPL], FS &&fs, FF &&ff) {
+  int s0, s1;
+  small_part(p, i0, i1, lim, &s0, &s1);
+  stream_chunked<LPL>(p, s0, s1, L, tot, fs);
+  // the other items: one end of the range
+  if (s0 > i0) stream_chunked<LPL>(p, i0, s0, L, tot, ff);
+  else stream_chunked<LPL>(p, s1, i1, L, tot, ff);
 }
 
 template <int LPL>
@@ -1234,21 +1277,28 @@ template <int LPL>
 __device__ void part_ccm1(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
   int b0, b1, s0, s1;
   split_ranges(t, b0, b1, s0, s1);
-  uint32_t mg[LPL], sh[LPL];
+  uint32_t mg[LPL], sh[LPL], ms[LPL];
   for (int j = 0; j < LPL; ++j) {
     const MagicU31 g = magic_u31(lam[j]);
     mg[j] = g.m;
     sh[j] = g.s;
+    ms[j] = magic_short(lam[j]);
   }
   const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
+  const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + (64 * LPL) - 1));
+  // a lambda <= 2^32 for every lane (and lambda >= 2): one high multiply
+  const uint32_t lim = lmin >= 2 ? 0xffffffffu / lmax : 0u;
   uint64_t hb[LPL] = {}, hs[LPL] = {};
   const int L = chunk_len(((uint64_t)t.C / 2) / lmin + 1);
   auto body = [&](uint32_t a, uint32_t *s) {
     const uint32_t a2 = 2u * a;
     for (int j = 0; j < LPL; ++j) s[j] += div_u31(a2, mg[j], sh[j]);
   };
-  stream_chunked<LPL>(t.av, b0, b1, L, hb, body);
-  stream_chunked<LPL>(t.av, s0, s1, L, hs, body);
+  auto body_short = [&](uint32_t a, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] += div_short(a, ms[j]);
+  };
+  stream_chunked_two<LPL>(t.av, b0, b1, L, lim, hb, body_short, body);
+  stream_chunked_two<LPL>(t.av, s0, s1, L, lim, hs, body_short, body);
   for (int j = 0; j < LPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
 }
 
@@ -1275,11 +1325,16 @@ __device__ void part_vb2(const TileArgs &t, const uint32_t lam[LPL], int64_t par
   uint64_t hb[LPL] = {}, hs[LPL] = {};
   // h(a) <= a lambda / c <= lambda / 2 for a <= c/2
   const int L = chunk_len((uint64_t)lmax / 2 + 1);
+  // a c <= 2^32: one high multiply by R's high word
+  const uint32_t lim = 0xffffffffu / (uint32_t)t.C;
   auto body = [&](uint32_t a, uint32_t *s) {
     for (int j = 0; j < LPL; ++j) s[j] += vb2_part(a, rlo[j], rhi[j]);
   };
-  stream_chunked<LPL>(t.av, b0, b1, L, hb, body);
-  stream_chunked<LPL>(t.av, s0, s1, L, hs, body);
+  auto body_short = [&](uint32_t a, uint32_t *s) {
+    for (int j = 0; j < LPL; ++j) s[j] += vb2_part_short(a, rhi[j]);
+  };
+  stream_chunked_two<LPL>(t.av, b0, b1, L, lim, hb, body_short, body);
+  stream_chunked_two<LPL>(t.av, s0, s1, L, lim, hs, body_short, body);
   for (int j = 0; j < LPL; ++j) part[j] = 2 * ((int64_t)hs[j] - (int64_t)hb[j]);
 }
 
@@ -1296,36 +1351,52 @@ __device__ __forceinline__ int64_t sum_vb2(const TileArgs &t, int64_t lam, int64
 // so part = (lambda - 2p) Q + A and S = (part + W - n p) / 2.
 template <int LPL>
 __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t part[LPL]) {
-  uint32_t mg[LPL], sh[LPL], pm[LPL];
+  uint32_t ms[LPL], pm[LPL];
   for (int j = 0; j < LPL; ++j) {
-    const MagicU31 g = magic_u31(lam[j]);
-    mg[j] = g.m;
-    sh[j] = g.s;
+    ms[j] = magic_short(lam[j]);
     pm[j] = (uint32_t)t.C % lam[j];
   }
   const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
   const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + (64 * LPL) - 1));
+  // w lambda <= 2^32 for every lane (and lambda >= 2): one high multiply
+  const uint32_t lim = lmin >= 2 ? 0xffffffffu / lmax : 0u;
   uint64_t Q[LPL] = {}, A[LPL] = {};
   const uint64_t inc = max((uint64_t)((uint32_t)t.C / lmin), (uint64_t)lmax) + 1;
   const int L = chunk_len(inc);
-  const int a0 = max(t.i0, t.nf), a1 = min(t.i1, t.nz);
-  for (int i0 = a0; i0 < a1;) {
-    const int e = i0 + min(a1 - i0, L);  // i0 + L could overflow int
-    uint32_t sq[LPL] = {}, sa[LPL] = {};
-    stream_u32(t.wv, i0, e, [&](uint32_t w) {
-      const uint32_t w2 = 2u * w;
+  // sums over [x0, x1) in segments of at most L items, q from quot(w, j)
+  auto run = [&](int x0, int x1, auto &&quot) {
+    for (int i0 = x0; i0 < x1;) {
+      const int e = i0 + min(x1 - i0, L);  // i0 + L could overflow int
+      uint32_t sq[LPL] = {}, sa[LPL] = {};
+      stream_u32(t.wv, i0, e, [&](uint32_t w) {
+        for (int j = 0; j < LPL; ++j) {
+          const uint32_t q = quot(w, j);
+          const uint32_t v = q * lam[j] + pm[j];
+          sq[j] += q;
+          sa[j] = sad_u32(w, v, sa[j]);
+        }
+      });
       for (int j = 0; j < LPL; ++j) {
-        const uint32_t q = div_u31(w2, mg[j], sh[j]);
-        const uint32_t v = q * lam[j] + pm[j];
-        sq[j] += q;
-        sa[j] = sad_u32(w, v, sa[j]);
+        Q[j] += sq[j];
+        A[j] += sa[j];
       }
-    });
-    for (int j = 0; j < LPL; ++j) {
-      Q[j] += sq[j];
-      A[j] += sa[j];
+      i0 = e;
     }
-    i0 = e;
+  };
+  const int a0 = max(t.i0, t.nf), a1 = min(t.i1, t.nz);
+  int s0, s1;
+  small_part(t.wv, a0, a1, lim, &s0, &s1);
+  run(s0, s1, [&](uint32_t w, int j) { return div_short(w, ms[j]); });
+  // the other items (one end of the range), by the two-step quotient
+  const int f0 = s0 > a0 ? a0 : s1, f1 = s0 > a0 ? s0 : a1;
+  if (f0 < f1) {
+    uint32_t mg[LPL], sh[LPL];
+    for (int j = 0; j < LPL; ++j) {
+      const MagicU31 g = magic_u31(lam[j]);
+      mg[j] = g.m;
+      sh[j] = g.s;
+    }
+    run(f0, f1, [&](uint32_t w, int j) { return div_u31(2u * w, mg[j], sh[j]); });
   }
   for (int j = 0; j < LPL; ++j)
     part[j] = ((int64_t)lam[j] - 2 * (int64_t)pm[j]) * (int64_t)Q[j] + (int64_t)A[j];
@@ -1884,9 +1955,7 @@ __device__ __forceinline__ uint64_t tile_max(const int64_t lam[LPL], const int64
   return wave_max_u64(key);
 }
 
-// Folds a key into the instance's maximum for the bound and raises the
-// early-exit flag when the bound refutes the instance.  Keys only grow: a key
-// that does not beat the current one leaves it alone.
+// Greatest common divisor (Euclid).
 __device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b) {
   while (b) {
     const uint32_t r = a % b;
@@ -1910,8 +1979,7 @@ __device__ uint64_t vb2_mirror_key(const TileArgs &t, int64_t mm, const int64_t 
   const int64_t nsm = t.nz - t.nm, nbg = t.nb - t.nf;
   const int64_t sum_small = t.sumNZ - t.sumBig - (int64_t)(t.nm - t.nb) * (C / 2);
   const int64_t base = (sum_small - nsm) - (nbg * C - t.sumBig - nbg);  // (A - n) small minus (A - n) big
-  int64_t l1[LPL], v1[LPL], l2[LPL], v2[LPL];
-  bool o1[LPL], o2[LPL];
+  uint64_t key = 0;  // this lane's largest key, folded as each one is made
   for (int j = 0; j < LPL; ++j) {
     const bool in = lam[j] >= 1 && lam[j] <= mm;
     const uint32_t lj = in ? (uint32_t)lam[j] : 1u;
@@ -1923,20 +1991,22 @@ __device__ uint64_t vb2_mirror_key(const TileArgs &t, int64_t mm, const int64_t 
     }
     const int64_t dsm = t.dcnt[lo], dbg = t.dcnt[t.ndiv + lo];
     const int64_t part2 = 2 * (base - dsm + dbg) - part[j];
-    l1[j] = lam[j];
-    l2[j] = C - lam[j];
-    o1[j] = in && l1[j] >= t.lo && l1[j] <= t.hi;
-    o2[j] = in && l2[j] >= t.lo && l2[j] <= t.hi;
-    v1[j] = o1[j] ? fin_bound(kVB2, t, l1[j], part[j]) : 0;
-    v2[j] = o2[j] ? fin_bound(kVB2, t, l2[j], part2) : 0;
-    if (t.node) {
-      if (o1[j]) store_state(kVB2, t, l1[j], part[j]);
-      if (o2[j]) store_state(kVB2, t, l2[j], part2);
+    const int64_t l1 = lam[j], l2 = C - lam[j];
+    if (in && l1 >= t.lo && l1 <= t.hi) {
+      key = umax64(key, pack_key(fin_bound(kVB2, t, l1, part[j]), l1));
+      if (t.node) store_state(kVB2, t, l1, part[j]);
+    }
+    if (in && l2 >= t.lo && l2 <= t.hi) {
+      key = umax64(key, pack_key(fin_bound(kVB2, t, l2, part2), l2));
+      if (t.node) store_state(kVB2, t, l2, part2);
     }
   }
-  return umax64(tile_max<LPL>(l1, v1, o1), tile_max<LPL>(l2, v2, o2));
+  return wave_max_u64(key);
 }
 
+// Folds a key into the instance's maximum for the bound and raises the
+// early-exit flag when the bound refutes the instance.  Keys only grow: a key
+// that does not beat the current one leaves it alone.
 __device__ __forceinline__ void publish_key(const LaunchDesc &d, int64_t inst, int bound, const TileArgs &t,
                                             uint64_t key, bool early) {
   if (!key) return;

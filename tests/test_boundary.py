@@ -131,6 +131,29 @@ def test_fp64_floor_vb2_quotient():
         assert bp.selftest_division(c, c, 4096, 4) == 0, c
 
 
+def test_short_quotient_small_divisors_exhaustive():
+    # floor(n / d) = mulhi(n, ceil(2^32 / d)) wherever n d <= 2^32: every 2 <= d < 2^11, n < 2^13, multiples of d
+    # and the limit floor(2^32 / d) itself
+    assert bp.selftest_division(1, 2048, 8192, 5) == 0
+
+
+def test_short_quotient_edge_divisors():
+    for lo, hi in [(2**15 - 3, 2**15 + 3), (2**16 - 2, 2**16 + 2), (42_949, 42_951), (50_000, 50_001),
+                   (85_898, 85_900), (99_999, 100_001), (2**20 - 1, 2**20 + 1), (2**31 - 4, 2**31 - 1)]:
+        assert bp.selftest_division(lo, hi, 4096, 5) == 0, (lo, hi)
+
+
+def test_vb2_short_form_small_capacities_exhaustive():
+    # ceil(a lambda / c) - 1 = mulhi(a, R_hi) for every c <= 160, lambda <= c, a <= c (a c <= 2^32 throughout)
+    assert bp.selftest_division(1, 160, 1 << 20, 6) == 0
+
+
+def test_vb2_short_form_large_capacities():
+    # capacities where a c <= 2^32 cuts a below c / 2 (the limit and the a just under it included)
+    for c in (65_536, 65_537, 92_681, 92_682, 100_000, 1_000_000, 2**25, 2**31 - 1):
+        assert bp.selftest_division(c, c, 2048, 6) == 0, c
+
+
 def test_selftest_rejects_bad_ranges():
     assert bp.selftest_division(0, 10, 10, 0) == bp.BP_ERR_ARG
     assert bp.selftest_division(10, 5, 10, 0) == bp.BP_ERR_ARG

@@ -176,6 +176,30 @@ def test_value_table_chunk_edges(ctx, C):
         same(ctx.lower_bounds(C, m, unp, sw), want_items, ("chunk edge items", C, flags))
 
 
+def test_one_multiply_quotient_cuts(ctx):
+    # sizes around the limits of the one-multiply quotients: VB2's a <= 2^32 / c (a the size or its complement),
+    # CCM1's a <= 2^32 / lambda and BJ1's w <= 2^32 / lambda over the top tiles of their ranges, so that tiles
+    # and item chunks straddle every cut; at capacities where the VB2 cut lies below c / 2, dense and segment
+    # form, against the oracle's dense record
+    insts = []
+    for C in (92_682, 100_000, 140_001):
+        g = np.random.default_rng(C)
+        lv = (1 << 32) // C
+        near = g.integers(max(1, lv - 400), min(C // 2, lv + 400), size=150)
+        spread = g.integers(1, C, size=250)
+        exact = [lv - 1, lv, lv + 1, C - lv - 1, C - lv, C - lv + 1, C // 2, (C + 1) // 2, C - 1, 1, C]
+        items = np.concatenate([near, C - near, spread, exact]).astype(np.int32)
+        k = int(items.astype(np.int64).sum()) // C + 2
+        insts.append((C, k, items))
+    wants = O.bounds_many([(C, k, list(map(int, items))) for C, k, items in insts], l2_dense=True)
+    for (C, k, items), want in zip(insts, wants):
+        for flags in (0, bp.BP_SWEEP_SEGMENTS):
+            say("one-multiply cuts", C, flags)
+            sw = bp.default_sweep(C)
+            sw.flags = flags
+            same(ctx.lower_bounds(C, k, items, sw), want, ("quotient cuts", C, flags))
+
+
 def test_value_table_launch_sequences(ctx):
     # value-table launches of different capacities and instance orders on one
     # context, so that each launch finds its tables where earlier launches of
