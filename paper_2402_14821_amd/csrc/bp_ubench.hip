@@ -20,13 +20,14 @@ namespace {
 enum Op : int {
   kAddU32 = 0, kSubU32, kAndB32, kXorB32, kLshrB32, kAshrI32, kAdd3U32, kSadU32, kMulLoU32, kMulHiU32,
   kMadU64U32, kCndmask, kMaxU32, kAddCoU32, kCmpLtU32, kFmaF64, kAddF64, kMulF64, kCvtF64U32, kBfeI32,
-  kNumOps
+  kMadU32U24, kMulU32U24, kMulHiU32U24, kLshlAddU32, kNumOps
 };
 
 const char *const kNames[kNumOps] = {
   "v_add_u32", "v_sub_u32", "v_and_b32", "v_xor_b32", "v_lshrrev_b32", "v_ashrrev_i32", "v_add3_u32",
   "v_sad_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_cndmask_b32", "v_max_u32",
-  "v_add_co_u32", "v_cmp_lt_u32", "v_fma_f64", "v_add_f64", "v_mul_f64", "v_cvt_f64_u32", "v_bfe_i32"};
+  "v_add_co_u32", "v_cmp_lt_u32", "v_fma_f64", "v_add_f64", "v_mul_f64", "v_cvt_f64_u32", "v_bfe_i32",
+  "v_mad_u32_u24", "v_mul_u32_u24", "v_mul_hi_u32_u24", "v_lshl_add_u32"};
 
 constexpr int kChains = 8;
 constexpr int kUnroll = 16;  // steps of each chain per loop iteration (one asm block of kChains * kUnroll instructions)
@@ -54,6 +55,10 @@ constexpr int kUnroll = 16;  // steps of each chain per loop iteration (one asm 
 #define BPU_MULHI(i) "v_mul_hi_u32 %" #i ", %" #i ", %8\n\t"
 #define BPU_MAX(i) "v_max_u32 %" #i ", %" #i ", %8\n\t"
 #define BPU_BFE(i) "v_bfe_i32 %" #i ", %" #i ", %8, 1\n\t"
+#define BPU_MAD24(i) "v_mad_u32_u24 %" #i ", %" #i ", %8, %8\n\t"
+#define BPU_MUL24(i) "v_mul_u32_u24 %" #i ", %" #i ", %8\n\t"
+#define BPU_MULHI24(i) "v_mul_hi_u32_u24 %" #i ", %" #i ", %8\n\t"
+#define BPU_LSHLADD(i) "v_lshl_add_u32 %" #i ", %" #i ", 1, %8\n\t"
 #define BPU_CND(i) "v_cndmask_b32_e64 %" #i ", %" #i ", %8, %9\n\t"
 #define BPU_ADDCO(i) "v_add_co_u32_e64 %" #i ", %8, %" #i ", %9\n\t"
 #define BPU_CMP(i) "v_cmp_lt_u32_e64 %8, %" #i ", %9\n\t"
@@ -82,6 +87,10 @@ __device__ __forceinline__ void row32(uint32_t (&x)[kChains], uint32_t b, uint64
   else if constexpr (OP == kMulHiU32) asm volatile(BPU_L8(BPU_MULHI) : BPU_X8 : "v"(b));
   else if constexpr (OP == kMaxU32) asm volatile(BPU_L8(BPU_MAX) : BPU_X8 : "v"(b));
   else if constexpr (OP == kBfeI32) asm volatile(BPU_L8(BPU_BFE) : BPU_X8 : "v"(b));
+  else if constexpr (OP == kMadU32U24) asm volatile(BPU_L8(BPU_MAD24) : BPU_X8 : "v"(b));
+  else if constexpr (OP == kMulU32U24) asm volatile(BPU_L8(BPU_MUL24) : BPU_X8 : "v"(b));
+  else if constexpr (OP == kMulHiU32U24) asm volatile(BPU_L8(BPU_MULHI24) : BPU_X8 : "v"(b));
+  else if constexpr (OP == kLshlAddU32) asm volatile(BPU_L8(BPU_LSHLADD) : BPU_X8 : "v"(b));
   else if constexpr (OP == kCndmask) asm volatile(BPU_L8(BPU_CND) : BPU_X8 : "v"(b), "s"(m));
   else if constexpr (OP == kAddCoU32) asm volatile(BPU_L8(BPU_ADDCO) : BPU_X8, "=s"(c) : "v"(b));
   else if constexpr (OP == kCmpLtU32) asm volatile(BPU_L8(BPU_CMP) : BPU_X8, "=s"(c) : "v"(b));
