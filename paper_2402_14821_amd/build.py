@@ -36,9 +36,8 @@ def _hipcc() -> str:
 # Kernels that must not use per-lane scratch memory: register spills there
 # cost issue slots in the hot loops and HBM traffic (the compiler reports
 # each kernel's scratch size; the build fails when one of these has any).
-# k_sweep<4> (four parameters per lane, an autotuner option) spills a few
-# registers and is left out.
-NO_SCRATCH = ("_ZN3bpi7k_sweepILi1E", "_ZN3bpi7k_sweepILi2E", "_ZN3bpi9k_combineILi", "_ZN3bpi13k_small_check",
+NO_SCRATCH = ("_ZN3bpi7k_sweepILi1E", "_ZN3bpi7k_sweepILi2E", "_ZN3bpi7k_sweepILi4E", "_ZN3bpi9k_combineILi",
+              "_ZN3bpi13k_small_check",
               "_ZN3bpi6k_prep", "_ZN3bpi9k_vt_", "_ZN3bpi10k_finalize")
 
 

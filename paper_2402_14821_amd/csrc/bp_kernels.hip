@@ -2277,8 +2277,11 @@ __global__ __launch_bounds__(64 * kSegTiles) void k_combine(const LaunchDesc *__
 // its own XCD first (blocks are dispatched to the XCDs round-robin) and from
 // the others once that one is exhausted, so no single counter serialises
 // every claim of the launch.  Every wave leaves when all queues are empty.
+// One and two parameters per lane fit 64 VGPRs (eight waves per SIMD); four
+// hold twice the per-lane sums and constants and get four waves per SIMD
+// rather than spill.
 template <int LPL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep(const LaunchDesc *__restrict__ dp) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LPL == 4 ? 4 : 8))) void k_sweep(const LaunchDesc *__restrict__ dp) {
   const LaunchDesc d = *as_const(dp);
   const uint64_t ntasks = (uint64_t)d.ntasks;
   const uint64_t grid = gridDim.x;
