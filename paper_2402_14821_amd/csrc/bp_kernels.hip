@@ -36,7 +36,10 @@
 // to every bound and are counted, not streamed.  Zero sizes add 0 to every
 // function.  Mid items (2w = c) take one fixed value per parameter.  For the
 // big and small classes each function reduces to per-lane arithmetic on a
-// scalar operand, written out per function below.
+// scalar operand, written out per function below.  The quotients of CCM1,
+// VB2 and BJ1 take one high multiply where the product is at most 2^32 and a
+// multiply-shift or a 64-bit reciprocal otherwise; within each sorted class
+// range the short form covers a prefix or a suffix (bp_divide.h).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
