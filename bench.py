@@ -48,8 +48,11 @@ sys.path.insert(0, ROOT)
 #   CCM1 v_mul_hi_u32, 1/2 v_add3_u32                                       = 1.5
 #   VB2  v_mul_hi_u32, 1/2 v_add3_u32                                       = 1.5
 #   BJ1  v_mul_hi_u32, v_mad_u64_u32, v_sad_u32, 1/2 v_add3_u32             = 3.5
+# and BJ1 over tiles whose parameters all exceed c/2 (floor(c / lambda) = 1:
+# f is a clamp, two absolute differences): 2 v_sad_u32                      = 2.0
 OPS_PER_EVAL = {"MT": 2.0, "RAD2": 3.0, "FS1": 10.25, "CCM1": 2.0, "VB2": 2.5, "BJ1": 4.0}
 OPS_PER_EVAL_SHORT = {"CCM1": 1.5, "VB2": 1.5, "BJ1": 3.5}
+OPS_PER_EVAL_BJ1_UPPER = 2.0
 PEAK_VALU = 256 * 64 * 2.4e9  # full-rate lane-instructions/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 DFF_NAMES = ("MT", "RAD2", "FS1", "CCM1", "VB2", "BJ1")
 
@@ -251,7 +254,10 @@ def sweep_ops(bp, C, items, lanes_params: int = 2):
         t1 = np.minimum(t0 + width - 1, hi)
         lim = np.where(t0 >= 2, 0xFFFFFFFF // t1, -1)
         n_short = np.searchsorted(vals, lim, side="right")
-        ops += float(((t1 - t0 + 1) * (short * n_short + full * (len(vals) - n_short))).sum())
+        per = short * n_short + full * (len(vals) - n_short)
+        if name == "BJ1":
+            per = np.where(2 * t0 > C, OPS_PER_EVAL_BJ1_UPPER * len(vals), per)
+        ops += float(((t1 - t0 + 1) * per).sum())
     return ops
 
 
@@ -990,6 +996,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic, "kernel": "k_sweep",
                      "ops_per_eval": OPS_PER_EVAL, "ops_per_eval_short": OPS_PER_EVAL_SHORT,
+                     "ops_per_eval_bj1_upper": OPS_PER_EVAL_BJ1_UPPER,
                      "weights": "profiles/valu_rates_gfx950.txt",
                      "slots_per_launch": ops,
                      # every VALU instruction the kernel issued (SQ_INSTS_VALU x 64 lanes) as one full slot

@@ -1361,6 +1361,35 @@ __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
   }
   const uint32_t lmin = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)max(t.lo, t.lam0));
   const uint32_t lmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)min(t.hi, t.lam0 + (64 * LPL) - 1));
+  const int a0 = max(t.i0, t.nf), a1 = min(t.i1, t.nz);
+  if (2ull * lmin > (uint64_t)(uint32_t)t.C) {
+    // Every lane's lambda exceeds c/2: floor(c / lambda) = 1 and p = c - lambda,
+    // so for 0 < w < c f = clamp(w - p, 0, 2 lambda - c)
+    // = (|w - p| - |w - lambda| + 2 lambda - c) / 2, two v_sad_u32 per item.
+    // part = 2S - W + n p = A1 - A2 + n lambda - W over the streamed items,
+    // A1 = sum |w - p|, A2 = sum |w - lambda| (each term below c).
+    uint64_t A1[LPL] = {}, A2[LPL] = {};
+    const int L = chunk_len((uint64_t)(uint32_t)t.C);
+    for (int i0 = a0; i0 < a1;) {
+      const int e = i0 + min(a1 - i0, L);  // i0 + L could overflow int
+      uint32_t s1[LPL] = {}, s2[LPL] = {};
+      stream_u32(t.wv, i0, e, [&](uint32_t w) {
+        for (int j = 0; j < LPL; ++j) {
+          s1[j] = sad_u32(w, pm[j], s1[j]);
+          s2[j] = sad_u32(w, lam[j], s2[j]);
+        }
+      });
+      for (int j = 0; j < LPL; ++j) {
+        A1[j] += s1[j];
+        A2[j] += s2[j];
+      }
+      i0 = e;
+    }
+    const int64_t n = a1 > a0 ? a1 - a0 : 0;
+    const int64_t W = a1 > a0 ? t.prec[a1] - t.prec[a0] : 0;
+    for (int j = 0; j < LPL; ++j) part[j] = (int64_t)A1[j] - (int64_t)A2[j] + n * (int64_t)lam[j] - W;
+    return;
+  }
   // w lambda <= 2^32 for every lane (and lambda >= 2): one high multiply
   const uint32_t lim = lmin >= 2 ? 0xffffffffu / lmax : 0u;
   uint64_t Q[LPL] = {}, A[LPL] = {};
@@ -1386,7 +1415,6 @@ __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
       i0 = e;
     }
   };
-  const int a0 = max(t.i0, t.nf), a1 = min(t.i1, t.nz);
   int s0, s1;
   small_part(t.wv, a0, a1, lim, &s0, &s1);
   run(s0, s1, [&](uint32_t w, int j) { return div_short(w, ms[j]); });
