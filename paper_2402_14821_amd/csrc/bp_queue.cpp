@@ -698,6 +698,21 @@ bp_status bp_queue_create(bp_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slot
     }
     s.ctx.magic = kCtxMagic;
     s.ctx.nodes = q->arena;
+    // a full batch's records and child tasks (with a few changed items each)
+    // from the start: a burst that fills a batch then grows no buffer (a
+    // growth waits for the context's launches and frees memory mid-stream)
+    const size_t nodes = (sizeof(NodeTask) * kMaxBatch + 255) & ~size_t(255);
+    const size_t deltas = (sizeof(int32_t) * 16 * kMaxBatch + 255) & ~size_t(255);
+    const size_t keys = sizeof(unsigned long long) * kNB * kMaxBatch;
+    if (!st) st = s.ctx.reserve_dev(s.out_dev, sizeof(bp_bounds) * kMaxBatch);
+    if (!st) st = s.out_host.reserve(sizeof(bp_bounds) * kMaxBatch);
+    if (!st) st = s.node_host.reserve(nodes + deltas);
+    if (!st) st = s.ctx.reserve_dev(s.node_dev, nodes + deltas + keys);
+    if (st) {
+      destroy_slots(q);
+      delete q;
+      return st;
+    }
   }
   q->magic = kQueueMagic;
   try {
