@@ -1079,13 +1079,18 @@ __device__ __forceinline__ int64_t ceil_div_small(int64_t a, int64_t b) {
   return q + (r != 0);
 }
 
+// Items per scalar block of the dense sweeps: 16 (one s_load_dwordx16, the
+// next 16 in flight) with two or four parameters per lane; 8 with one, whose
+// wave would otherwise spill.
+template <int LPL>
+constexpr int kStreamBlock = LPL >= 2 ? 16 : 8;
+
 // Calls f(p[i]) for i in [i0, i1) in order.  Every lane uses the same item,
-// so items are read with scalar loads, 8 at a time, and the next block's
+// so items are read with scalar loads, U at a time, and the next block's
 // loads are issued before the current block is processed: the stream is
 // larger than the scalar cache, and this hides the latency of its misses.
-template <typename F>
+template <int U = 8, typename F>
 __device__ __forceinline__ void stream_u32(const BP_CONST uint32_t *p, int i0, int i1, F &&f) {
-  constexpr int U = 8;
   int i = i0;
   if (i1 - i >= U) {
     uint32_t cur[U];
@@ -1144,7 +1149,7 @@ __device__ __forceinline__ void stream_chunked(const BP_CONST uint32_t *p, int i
   for (int a = i0; a < i1;) {
     const int e = a + min(i1 - a, L);  // a + L could overflow int
     uint32_t s[LPL] = {};
-    stream_u32(p, a, e, [&](uint32_t x) { f(x, s); });
+    stream_u32<kStreamBlock<LPL>>(p, a, e, [&](uint32_t x) { f(x, s); });
     for (int j = 0; j < LPL; ++j) tot[j] += s[j];
     a = e;
   }
@@ -1224,13 +1229,13 @@ __device__ void part_rad2(const TileArgs &t, const uint32_t lam[LPL], int64_t pa
     u4[j] = (uint32_t)t.C - lam[j];             // w >= c - lambda + 1
   }
   uint32_t n1[LPL] = {}, n2[LPL] = {}, n3[LPL] = {}, n4[LPL] = {};
-  stream_u32(t.wv, s0, s1, [&](uint32_t w) {
+  stream_u32<kStreamBlock<LPL>>(t.wv, s0, s1, [&](uint32_t w) {
     for (int j = 0; j < LPL; ++j) {
       n1[j] += (u1[j] - w) >> 31;
       n2[j] += (u2[j] - w) >> 31;
     }
   });
-  stream_u32(t.wv, b0, b1, [&](uint32_t w) {
+  stream_u32<kStreamBlock<LPL>>(t.wv, b0, b1, [&](uint32_t w) {
     for (int j = 0; j < LPL; ++j) {
       n3[j] += (u3[j] - w) >> 31;
       n4[j] += (u4[j] - w) >> 31;
@@ -1373,7 +1378,7 @@ __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
     for (int i0 = a0; i0 < a1;) {
       const int e = i0 + min(a1 - i0, L);  // i0 + L could overflow int
       uint32_t s1[LPL] = {}, s2[LPL] = {};
-      stream_u32(t.wv, i0, e, [&](uint32_t w) {
+      stream_u32<kStreamBlock<LPL>>(t.wv, i0, e, [&](uint32_t w) {
         for (int j = 0; j < LPL; ++j) {
           s1[j] = sad_u32(w, pm[j], s1[j]);
           s2[j] = sad_u32(w, lam[j], s2[j]);
@@ -1400,7 +1405,7 @@ __device__ void part_bj1(const TileArgs &t, const uint32_t lam[LPL], int64_t par
     for (int i0 = x0; i0 < x1;) {
       const int e = i0 + min(x1 - i0, L);  // i0 + L could overflow int
       uint32_t sq[LPL] = {}, sa[LPL] = {};
-      stream_u32(t.wv, i0, e, [&](uint32_t w) {
+      stream_u32<kStreamBlock<LPL>>(t.wv, i0, e, [&](uint32_t w) {
         for (int j = 0; j < LPL; ++j) {
           const uint32_t q = quot(w, j);
           const uint32_t v = q * lam[j] + pm[j];
