@@ -221,10 +221,13 @@ def valu_rates(blocks_per_cu: int = 8, iters: int = 4000, reps: int = 3):
 
 def sweep_ops(bp, C, items, lanes_params: int = 2):
     """Algorithmic VALU slots of the six sweeps of one instance (exact ranges,
-    as the library's own bp_default_sweep states them), each evaluation at
-    the weight of the form the kernel takes for it: tiles of 64 x
-    lanes_params parameters from the range's start, and per tile the sizes
-    whose quotient fits one high multiply on the short form."""
+    as the library's own bp_default_sweep states them): every parameter
+    times the sizes its sweep streams (MT, RAD2, CCM1 and VB2 the big and
+    small classes, FS1 and BJ1 every size strictly between 0 and c; sizes 0,
+    c/2 and c are counted, not streamed), each evaluation at the weight of
+    the form the kernel takes for it: tiles of 64 x lanes_params parameters
+    from the range's start, and per tile the sizes whose quotient fits one
+    high multiply on the short form."""
     import numpy as np
 
     C = int(C)
@@ -232,7 +235,6 @@ def sweep_ops(bp, C, items, lanes_params: int = 2):
     w = w[(w > 0) & (w < C)]
     a = np.sort(np.where(2 * w > C, C - w, w)[2 * w != C])  # CCM1 and VB2 stream these (big and small)
     ws = np.sort(w)                                           # BJ1 streams the sizes 0 < w < c
-    r = len(items)
     sw = bp.default_sweep(C)
     width = 64 * lanes_params
     ops = 0.0
@@ -242,7 +244,7 @@ def sweep_ops(bp, C, items, lanes_params: int = 2):
         if hi < lo:
             continue
         if name not in OPS_PER_EVAL_SHORT:
-            ops += OPS_PER_EVAL[name] * r * (hi - lo + 1)
+            ops += OPS_PER_EVAL[name] * (len(ws) if name == "FS1" else len(a)) * (hi - lo + 1)
             continue
         full, short = OPS_PER_EVAL[name], OPS_PER_EVAL_SHORT[name]
         vals = ws if name == "BJ1" else a
