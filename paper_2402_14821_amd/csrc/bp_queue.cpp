@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
@@ -168,6 +169,7 @@ struct Queue {
   std::mutex mu;
   std::condition_variable cv_work, cv_space, cv_results;
   std::deque<Req> pending;
+  std::atomic<uint64_t> npending{0};  // pending.size(), readable without mu
   std::deque<bp_result> results;
   size_t bytes_in_use = 0, bytes_peak = 0;
   int64_t admitted = 0;  // submitted and not yet completed
@@ -590,7 +592,9 @@ struct Queue {
           break;
         }
       bool stop = false, took = false;
-      {
+      // (with a batch running and nothing to take, the lock is left to the
+      // submitters)
+      if (!busy_any() || (idle >= 0 && npending.load(std::memory_order_acquire) > 0)) {
         std::unique_lock<std::mutex> lk(mu);
         if (idle >= 0 && !pending.empty() && !shutdown) {
           std::vector<Work> &batch = slots[idle].work;
@@ -599,6 +603,7 @@ struct Queue {
           while (!pending.empty() && (int)batch.size() < kMaxBatch) {
             plan_work(pending.front(), idle, batch, in_batch);
             pending.pop_front();
+            npending.fetch_sub(1, std::memory_order_relaxed);
           }
           took = !batch.empty();
         }
@@ -624,11 +629,10 @@ struct Queue {
         }
         continue;
       }
-      // a batch is running: poll its completion at a short interval
-      if (busy_any()) {
-        std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait_for(lk, std::chrono::microseconds(20));
-      }
+      // a batch is running: poll its end event again (a timed wait of a few
+      // microseconds would sleep for the scheduler's timer slack, tens of
+      // microseconds, and every served request would wait it out)
+      if (busy_any()) std::this_thread::yield();
     }
     // shut down: what never started completes with BP_ERR_STATE
     std::vector<Work> rest;
@@ -639,6 +643,7 @@ struct Queue {
         w.req = pending.front();
         rest.push_back(std::move(w));
         pending.pop_front();
+        npending.fetch_sub(1, std::memory_order_relaxed);
       }
     }
     if (!rest.empty()) publish(rest, nullptr, BP_ERR_STATE, now_us(), -2);
@@ -862,6 +867,7 @@ bp_status bp_queue_submit(bp_queue *qh, const bp_request *req, int32_t blocking,
   q->history.push_back(r.ticket);
   q->forget_old_nodes();
   q->pending.push_back(r);
+  q->npending.fetch_add(1, std::memory_order_release);
   q->cv_work.notify_one();
   return BP_OK;
 }
